@@ -1,0 +1,125 @@
+"""FP64 CPU oracle for the direct-form filter and its closed-form backward.
+
+TEST INFRASTRUCTURE ONLY: the tests, the package smoke check and the
+benchmark's CPU-baseline leg call this; the product path never does.  It
+shares no code with the HIP library (``oracle.c`` is plain C compiled with
+gcc).  See ``oracle.c`` for the equations (paper Sec. 2 Eq. 1, Sec. 3.1
+Eqs. 6-9, Appendix A) and the reading of each.
+
+Array conventions (numpy, any real dtype; converted to float64 here):
+
+* layout ``"TB"``: signals ``[T, B]``; layout ``"BT"``: signals ``[B, T]``.
+* ``a``: ``[B, N]`` (time-invariant) or ``[T, B, N]`` / ``[B, T, N]``
+  (per-sample, following the signal layout), holding ``a_1..a_N``.
+* ``b``: same with ``M + 1`` taps ``b_0..b_M``; ``None`` means ``b = [1]``.
+* ``xi``: ``[B, M]`` with ``xi[:, j-1] = x[-j]``; ``yi``: ``[B, N]``.
+
+Parity status: every function here is pinned by tests under
+``tests/test_oracle_pins.py`` (closed forms, SciPy, dense solves, finite
+differences, adjoint identity); none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc into liboracle.so (in place)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC,
+                               "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64, I = ctypes.c_int64, ctypes.c_int
+        lib.oracle_forward.argtypes = [I64, I64, I, I, I, I, P, P, P, P, P, P, I]
+        lib.oracle_forward.restype = I
+        lib.oracle_backward.argtypes = [I64, I64, I, I, I, I] + [P] * 12 + [I]
+        lib.oracle_backward.restype = I
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(x, a, b, layout):
+    if layout not in ("TB", "BT"):
+        raise ValueError("layout must be 'TB' or 'BT'")
+    if x.ndim != 2:
+        raise ValueError("x must be 2-D")
+    T, B = x.shape if layout == "TB" else x.shape[::-1]
+    N = 0 if a is None else a.shape[-1]
+    M = 0 if b is None else b.shape[-1] - 1
+    tv = int((a is not None and a.ndim == 3) or (b is not None and b.ndim == 3))
+    for c, K in ((a, N), (b, M + 1)):
+        if c is None:
+            continue
+        want = (B, K) if not tv else ((T, B, K) if layout == "TB" else (B, T, K))
+        if c.shape != want:
+            raise ValueError(f"coefficient shape {c.shape} != {want}")
+    return int(B), int(T), int(M), int(N), tv
+
+
+def forward(x, a, b=None, xi=None, yi=None, layout="BT", nthreads=1):
+    """y = direct-form filter of x (FP64)."""
+    x, a, b, xi, yi = map(_f64, (x, a, b, xi, yi))
+    B, T, M, N, tv = _dims(x, a, b, layout)
+    if a is None:
+        a = np.zeros((B, 0) if not tv else x.shape + (0,))
+    y = np.zeros_like(x)
+    rc = _load().oracle_forward(B, T, M, N, tv, 0 if layout == "TB" else 1, _ptr(x), _ptr(b),
+                                _ptr(a), _ptr(xi), _ptr(yi), _ptr(y), int(nthreads))
+    if rc:
+        raise ValueError("oracle_forward rejected its arguments")
+    return y
+
+
+def backward(gy, x, y, a, b=None, xi=None, yi=None, layout="BT", nthreads=1,
+             want=("x", "a", "b", "xi", "yi")):
+    """Closed-form gradients.  Returns a dict with the requested keys among
+    x, a, b, xi, yi (b only if b was given)."""
+    gy, x, y, a, b, xi, yi = map(_f64, (gy, x, y, a, b, xi, yi))
+    B, T, M, N, tv = _dims(x, a, b, layout)
+    if a is None:
+        a = np.zeros((B, 0) if not tv else x.shape + (0,))
+    out = {}
+    gx = np.zeros_like(x) if "x" in want else None
+    ga = np.zeros_like(a) if "a" in want else None
+    gb = np.zeros_like(b) if ("b" in want and b is not None) else None
+    gxi = np.zeros((B, M)) if "xi" in want else None
+    gyi = np.zeros((B, N)) if "yi" in want else None
+    rc = _load().oracle_backward(B, T, M, N, tv, 0 if layout == "TB" else 1, _ptr(gy), _ptr(x),
+                                 _ptr(y), _ptr(b), _ptr(a), _ptr(xi), _ptr(yi), _ptr(gx),
+                                 _ptr(gb), _ptr(ga), _ptr(gxi), _ptr(gyi), int(nthreads))
+    if rc:
+        raise ValueError("oracle_backward rejected its arguments")
+    for k, v in (("x", gx), ("a", ga), ("b", gb), ("xi", gxi), ("yi", gyi)):
+        if v is not None:
+            out[k] = v
+    return out

@@ -1,0 +1,371 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test ties one part of the oracle to something the paper or mathematics
+fixes independently: closed-form impulse / zero-input responses, SciPy's
+lfilter (a library routine), np.convolve, dense linear solves, central finite
+differences, the adjoint identity of a linear map, a naive FP64 autograd
+loop (the paper's "Naive" baseline, Sec. 4), the state-space form of
+Sec. 2 Eqs. 4-5 with the adjoint of Sec. 3.1 Eqs. 7-9, and the forward-mode
+sensitivity filter.  A dropped term, a wrong sign or index, or a transposed
+operand anywhere in oracle.c fails at least one of these.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.signal
+
+import oracle
+from paper_2511_14390_amd import workloads as W
+from tests.helpers import chan_rel_err
+
+RTOL = 1e-12
+
+
+def _delta(B, T):
+    x = np.zeros((B, T))
+    x[:, 0] = 1.0
+    return x
+
+
+def test_first_order_impulse_closed_form():
+    # one real pole p: A(z) = 1 - p z^-1  ->  h[n] = p^n
+    p = np.array([0.9, -0.5, 0.3])
+    T = 64
+    y = oracle.forward(_delta(3, T), (-p)[:, None], layout="BT")
+    n = np.arange(T)
+    np.testing.assert_allclose(y, p[:, None] ** n[None, :], rtol=1e-13, atol=1e-300)
+
+
+def test_second_order_impulse_closed_form():
+    # conjugate pair r e^{+-i th}: h[n] = r^n sin((n+1) th) / sin th
+    r = np.array([0.95, 0.5, 0.99])
+    th = np.array([0.3, 2.0, 0.05])
+    a = W.pole_pair_section(r, th)[:, 1:]
+    T = 200
+    y = oracle.forward(_delta(3, T), a, layout="BT")
+    n = np.arange(T)[None, :]
+    h = r[:, None] ** n * np.sin((n + 1) * th[:, None]) / np.sin(th[:, None])
+    np.testing.assert_allclose(y, h, rtol=1e-9, atol=1e-12)
+
+
+def test_first_order_zero_input_response():
+    p = np.array([0.8, -0.7])
+    yi = np.array([[1.5], [-2.0]])
+    T = 40
+    y = oracle.forward(np.zeros((2, T)), (-p)[:, None], yi=yi, layout="BT")
+    n = np.arange(T)
+    np.testing.assert_allclose(y, yi * p[:, None] ** (n[None, :] + 1), rtol=1e-13)
+
+
+def test_second_order_zero_input_equals_impulse_superposition():
+    # With zero input, the initial conditions act as an input
+    # u[0] = -a1 y[-1] - a2 y[-2], u[1] = -a2 y[-1]; y = h * u with the
+    # closed-form h of a pole pair.
+    r, th = 0.9, 0.7
+    a1, a2 = -2 * r * math.cos(th), r * r
+    Y1, Y2 = 0.3, -1.1
+    T = 100
+    y = oracle.forward(np.zeros((1, T)), np.array([[a1, a2]]), yi=np.array([[Y1, Y2]]),
+                       layout="BT")[0]
+    n = np.arange(T)
+    h = r ** n * np.sin((n + 1) * th) / math.sin(th)
+    u0, u1 = -a1 * Y1 - a2 * Y2, -a2 * Y1
+    want = u0 * h
+    want[1:] += u1 * h[:-1]
+    np.testing.assert_allclose(y, want, rtol=1e-10, atol=1e-13)
+
+
+@pytest.mark.parametrize("M,N", [(0, 1), (0, 2), (2, 2), (4, 4), (3, 5), (5, 1), (1, 7)])
+@pytest.mark.parametrize("layout", ["TB", "BT"])
+def test_lti_matches_scipy_lfilter_with_initial_conditions(M, N, layout):
+    p = W.random_problem(10 + M * 10 + N, B=3, T=300, M=M, N=N, time_varying=False,
+                         layout=layout)
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout=layout)
+    xs = p.x.astype(np.float64)
+    if layout == "TB":
+        xs = xs.T
+        y = y.T
+    for c in range(p.B):
+        bb = p.b[c].astype(np.float64)
+        aa = np.concatenate([[1.0], p.a[c].astype(np.float64)])
+        yi = p.yi[c].astype(np.float64)
+        xi = p.xi[c].astype(np.float64) if p.xi is not None else np.zeros(0)
+        zi = scipy.signal.lfiltic(bb, aa, yi, xi)
+        want, _ = scipy.signal.lfilter(bb, aa, xs[c], zi=zi)
+        np.testing.assert_allclose(y[c], want, rtol=1e-10, atol=1e-12)
+
+
+def test_fir_matches_convolve():
+    rng = np.random.default_rng(5)
+    M, T = 6, 50
+    b = rng.standard_normal((2, M + 1))
+    x = rng.standard_normal((2, T))
+    xi = rng.standard_normal((2, M))
+    y = oracle.forward(x, np.zeros((2, 0)), b, xi=xi, layout="BT")
+    for c in range(2):
+        ext = np.concatenate([xi[c][::-1], x[c]])  # x[-M] .. x[T-1]
+        want = np.convolve(ext, b[c])[M:M + T]
+        np.testing.assert_allclose(y[c], want, rtol=1e-12, atol=1e-12)
+
+
+def _dense_operator(a, b, n_T, layout_bt=True):
+    """Dense matrices of one channel's filter: (I + sum_k D(a_k) S^k) y =
+    (sum_k D(b_k) S^k) x + IC terms.  a: [T, N], b: [T, M+1]."""
+    T, N = a.shape
+    M = b.shape[1] - 1
+    Am = np.eye(T)
+    Bm = np.zeros((T, T))
+    for n in range(T):
+        for k in range(1, N + 1):
+            if n - k >= 0:
+                Am[n, n - k] += a[n, k - 1]
+        for k in range(0, M + 1):
+            if n - k >= 0:
+                Bm[n, n - k] += b[n, k]
+    return Am, Bm
+
+
+def _ic_rhs(a, b, xi, yi):
+    T, N = a.shape
+    M = b.shape[1] - 1
+    r = np.zeros(T)
+    for n in range(T):
+        for k in range(1, N + 1):
+            j = k - n  # y[n-k] = y[-j]
+            if j >= 1:
+                r[n] -= a[n, k - 1] * yi[j - 1]
+        for k in range(0, M + 1):
+            j = k - n
+            if j >= 1:
+                r[n] += b[n, k] * xi[j - 1]
+    return r
+
+
+@pytest.mark.parametrize("layout", ["TB", "BT"])
+@pytest.mark.parametrize("M,N", [(0, 3), (2, 4), (3, 1)])
+def test_ltv_forward_matches_dense_solve(layout, M, N):
+    T = 48
+    p = W.random_problem(77 + M + N, B=2, T=T, M=M, N=N, time_varying=True, layout=layout, hop=5)
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout=layout)
+    for c in range(2):
+        if layout == "TB":
+            a, b, x, yc = p.a[:, c], p.b[:, c], p.x[:, c], y[:, c]
+        else:
+            a, b, x, yc = p.a[c], p.b[c], p.x[c], y[c]
+        a, b, x = (v.astype(np.float64) for v in (a, b, x))
+        Am, Bm = _dense_operator(a, b, T)
+        xi = p.xi[c] if p.xi is not None else np.zeros(M)
+        rhs = Bm @ x + _ic_rhs(a, b, xi.astype(np.float64), p.yi[c].astype(np.float64))
+        np.testing.assert_allclose(yc, np.linalg.solve(Am, rhs), rtol=1e-10, atol=1e-12)
+
+
+def test_ltv_with_constant_coefficients_equals_lti():
+    p = W.random_problem(3, B=3, T=120, M=2, N=4, time_varying=False, layout="BT")
+    y_lti = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout="BT")
+    a_tv = np.broadcast_to(p.a[:, None, :], (3, 120, 4))
+    b_tv = np.broadcast_to(p.b[:, None, :], (3, 120, 3))
+    y_tv = oracle.forward(p.x, a_tv, b_tv, p.xi, p.yi, layout="BT")
+    np.testing.assert_array_equal(y_lti, y_tv)
+
+
+def test_layouts_agree():
+    p = W.random_problem(4, B=3, T=90, M=3, N=2, time_varying=True, layout="BT")
+    y_bt = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout="BT")
+    y_tb = oracle.forward(p.x.T, p.a.transpose(1, 0, 2), p.b.transpose(1, 0, 2), p.xi, p.yi,
+                          layout="TB")
+    np.testing.assert_array_equal(y_bt, y_tb.T)
+
+
+def test_lti_shift_invariance():
+    p = W.random_problem(8, B=2, T=100, M=2, N=3, time_varying=False, layout="BT",
+                         with_xi=False, with_yi=False)
+    x = p.x.astype(np.float64)
+    y = oracle.forward(x, p.a, p.b, layout="BT")
+    xs = np.concatenate([np.zeros((2, 7)), x[:, :-7]], axis=1)
+    ys = oracle.forward(xs, p.a, p.b, layout="BT")
+    np.testing.assert_allclose(ys[:, 7:], y[:, :-7], rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(ys[:, :7], 0.0)
+
+
+def test_linearity_superposition():
+    p = W.random_problem(9, B=2, T=80, M=2, N=3, time_varying=True, layout="TB")
+    rng = np.random.default_rng(0)
+    x2 = rng.standard_normal(p.x.shape)
+    xi2 = rng.standard_normal(p.xi.shape)
+    yi2 = rng.standard_normal(p.yi.shape)
+    f = lambda x, xi, yi: oracle.forward(x, p.a, p.b, xi, yi, layout="TB")
+    lhs = f(2.0 * p.x + 3.0 * x2, 2.0 * p.xi + 3.0 * xi2, 2.0 * p.yi + 3.0 * yi2)
+    rhs = 2.0 * f(p.x, p.xi, p.yi) + 3.0 * f(x2, xi2, yi2)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-11)
+
+
+# ----------------------------------------------------------------- backward
+
+def _loss_grads_fd(p, layout, h=1e-6):
+    """Central finite differences of L = <gy, y> w.r.t. every input."""
+    gy = p.gy.astype(np.float64)
+    base = dict(x=p.x.astype(np.float64), a=p.a.astype(np.float64),
+                b=p.b.astype(np.float64), xi=p.xi.astype(np.float64),
+                yi=p.yi.astype(np.float64))
+
+    def loss(args):
+        y = oracle.forward(args["x"], args["a"], args["b"], args["xi"], args["yi"], layout=layout)
+        return float((gy * y).sum())
+
+    out = {}
+    for name, v in base.items():
+        g = np.zeros_like(v)
+        it = np.nditer(v, flags=["multi_index"])
+        for _ in it:
+            idx = it.multi_index
+            args = {k: w.copy() for k, w in base.items()}
+            args[name][idx] += h
+            lp = loss(args)
+            args[name][idx] -= 2 * h
+            lm = loss(args)
+            g[idx] = (lp - lm) / (2 * h)
+        out[name] = g
+    return out
+
+
+@pytest.mark.parametrize("layout", ["TB", "BT"])
+@pytest.mark.parametrize("tv", [False, True])
+def test_backward_matches_central_finite_differences(layout, tv):
+    p = W.random_problem(21 + tv, B=2, T=11, M=2, N=3, time_varying=tv, layout=layout, hop=3)
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout=layout)
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout=layout)
+    fd = _loss_grads_fd(p, layout)
+    for k in ("x", "a", "b", "xi", "yi"):
+        np.testing.assert_allclose(g[k], fd[k], rtol=1e-6, atol=1e-7, err_msg=k)
+
+
+@pytest.mark.parametrize("tv", [False, True])
+def test_adjoint_identity(tv):
+    # y is linear in (x, xi, yi) jointly: <gy, L(x,xi,yi)> = <gx,x> + <gxi,xi> + <gyi,yi>
+    p = W.random_problem(31, B=3, T=200, M=4, N=5, time_varying=tv, layout="BT")
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout="BT")
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout="BT")
+    f64 = lambda v: v.astype(np.float64)
+    for c in range(3):
+        lhs = (f64(p.gy[c]) * y[c]).sum()
+        rhs = ((g["x"][c] * f64(p.x[c])).sum() + (g["xi"][c] * f64(p.xi[c])).sum()
+               + (g["yi"][c] * f64(p.yi[c])).sum())
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs)), (lhs, rhs)
+
+
+@pytest.mark.parametrize("M,N", [(0, 4), (3, 2)])
+def test_backward_input_grad_is_dense_transpose(M, N):
+    T = 40
+    p = W.random_problem(41, B=1, T=T, M=M, N=N, time_varying=True, layout="BT", hop=4)
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout="BT")
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout="BT")
+    a, b = p.a[0].astype(np.float64), p.b[0].astype(np.float64)
+    Am, Bm = _dense_operator(a, b, T)
+    want = Bm.T @ np.linalg.solve(Am.T, p.gy[0].astype(np.float64))
+    np.testing.assert_allclose(g["x"][0], want, rtol=1e-10, atol=1e-12)
+
+
+def test_backward_matches_naive_fp64_autograd_loop():
+    torch = pytest.importorskip("torch")
+    p = W.random_problem(51, B=2, T=25, M=2, N=3, time_varying=True, layout="BT", hop=4)
+    t = lambda v: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True)
+    x, a, b, xi, yi = t(p.x), t(p.a), t(p.b), t(p.xi), t(p.yi)
+    gy = torch.tensor(p.gy.astype(np.float64))
+    outs = []
+    for c in range(2):
+        hist_x = [xi[c, j] for j in range(2)]      # x[-1], x[-2]
+        hist_y = [yi[c, j] for j in range(3)]
+        row = []
+        for n in range(25):
+            xs = [x[c, n]] + hist_x
+            acc = sum(b[c, n, k] * xs[k] for k in range(3))
+            acc = acc - sum(a[c, n, k - 1] * hist_y[k - 1] for k in range(1, 4))
+            row.append(acc)
+            hist_x = [x[c, n]] + hist_x[:-1]
+            hist_y = [acc] + hist_y[:-1]
+        outs.append(torch.stack(row))
+    Y = torch.stack(outs)
+    (Y * gy).sum().backward()
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout="BT")
+    np.testing.assert_allclose(y, Y.detach().numpy(), rtol=1e-12, atol=1e-12)
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout="BT")
+    for name, ten in (("x", x), ("a", a), ("b", b), ("xi", xi), ("yi", yi)):
+        np.testing.assert_allclose(g[name], ten.grad.numpy(), rtol=1e-10, atol=1e-12,
+                                   err_msg=name)
+
+
+def test_backward_matches_state_space_adjoint():
+    """All-pole LTI filter as the state-space recursion of Sec. 2 Eq. 4 with the
+    companion matrix (first row -a), state v(n) = [y(n-1) .. y(n-N)], input
+    z(n) = e1 u(n); gradients from the reverse-time recursion of Eq. 7 and the
+    sums of Eq. 9, all in matrix form."""
+    N, T = 3, 60
+    p = W.random_problem(61, B=1, T=T, M=0, N=N, time_varying=False, layout="BT",
+                         with_b=False)
+    a = p.a[0].astype(np.float64)
+    A = np.zeros((N, N))
+    A[0, :] = -a
+    A[np.arange(1, N), np.arange(N - 1)] = 1.0
+    u = p.x[0].astype(np.float64)
+    gy = p.gy[0].astype(np.float64)
+    v = np.zeros((T + 1, N))
+    v[0] = p.yi[0]
+    for n in range(T):
+        v[n + 1] = A @ v[n] + np.eye(N)[0] * u[n]
+    y_ss = v[1:, 0]
+    # dL/dv(n) for n >= 1 is gy[n-1] e1 (y[n-1] is the first entry of v(n)).
+    gv = np.zeros((T + 1, N))
+    gv[1:, 0] = gy
+    gz = np.zeros((T, N))          # gz[n] = dL/dz(n); z(n) feeds v(n+1)
+    gz[T - 1] = gv[T]
+    for n in range(T - 2, -1, -1):
+        gz[n] = A.T @ gz[n + 1] + gv[n + 1]
+    gv0 = A.T @ gz[0]              # dL/dv(0) (v(0) is not an output here)
+    gA = sum(np.outer(gz[n], v[n]) for n in range(T))
+    y = oracle.forward(p.x, p.a, None, None, p.yi, layout="BT")
+    np.testing.assert_allclose(y[0], y_ss, rtol=1e-11, atol=1e-12)
+    g = oracle.backward(p.gy, p.x, y, p.a, None, None, p.yi, layout="BT")
+    np.testing.assert_allclose(g["x"][0], gz[:, 0], rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(g["yi"][0], gv0, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(g["a"][0], -gA[0, :], rtol=1e-10, atol=1e-12)
+
+
+def test_lti_grad_a_matches_forward_sensitivity_filter():
+    # dy/da_k = allpole(-y[. - k]) with zero initial state (differentiating the
+    # recursion); grad_a_k = <gy, dy/da_k>.  Uses only the oracle's forward.
+    p = W.random_problem(71, B=2, T=150, M=1, N=3, time_varying=False, layout="BT")
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout="BT")
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout="BT")
+    for c in range(2):
+        yext = np.concatenate([p.yi[c][::-1].astype(np.float64), y[c]])  # y[-N] .. y[T-1]
+        for k in range(1, 4):
+            shifted = yext[3 - k:3 - k + 150]   # y[n-k]
+            d = oracle.forward(-shifted[None, :], p.a[c:c + 1], layout="BT")[0]
+            want = (p.gy[c].astype(np.float64) * d).sum()
+            assert abs(g["a"][c, k - 1] - want) <= 1e-10 * max(1, abs(want))
+
+
+def test_edge_cases_empty_and_short():
+    # T = 0 and B = 0 are no-ops; T < N uses only the initial conditions that exist.
+    assert oracle.forward(np.zeros((2, 0)), np.zeros((2, 3)), layout="BT").shape == (2, 0)
+    assert oracle.forward(np.zeros((0, 5)), np.zeros((0, 3)), layout="BT").shape == (0, 5)
+    p = W.random_problem(81, B=2, T=2, M=3, N=5, time_varying=False, layout="BT")
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout="BT")
+    for c in range(2):
+        aa = np.concatenate([[1.0], p.a[c].astype(np.float64)])
+        zi = scipy.signal.lfiltic(p.b[c].astype(np.float64), aa, p.yi[c].astype(np.float64),
+                                  p.xi[c].astype(np.float64))
+        want, _ = scipy.signal.lfilter(p.b[c].astype(np.float64), aa,
+                                       p.x[c].astype(np.float64), zi=zi)
+        np.testing.assert_allclose(y[c], want, rtol=1e-12, atol=1e-13)
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout="BT")
+    fd = _loss_grads_fd(p, "BT")
+    for k in ("x", "a", "b", "xi", "yi"):
+        np.testing.assert_allclose(g[k], fd[k], rtol=1e-6, atol=1e-7, err_msg=k)
+
+
+def test_metric_helper():
+    ref = np.array([[1.0, -2.0], [0.5, 0.25]])
+    got = ref + np.array([[0.0, 2e-4], [0.0, 0.0]])
+    assert abs(chan_rel_err(got, ref, "BT") - 1e-4) < 1e-12
