@@ -1,0 +1,125 @@
+/*
+ * filt.h -- C ABI of the MI355X (gfx950) direct-form filter library libfilt.so.
+ *
+ * The library computes the direct-form IIR recursion of
+ * Yu & Fazekas, "Accelerating Automatic Differentiation of Direct Form
+ * Digital Filters" (arXiv 2511.14390), Sec. 2 Eq. 1 read as a difference
+ * equation with per-sample coefficients and initial conditions,
+ *
+ *     y[n] = sum_{k=0..M} b_k[n] x[n-k] - sum_{k=1..N} a_k[n] y[n-k],
+ *
+ * and its closed-form backward (Sec. 3.1 Eqs. 6-9, Appendix A): an adjoint
+ * filter run in reverse time with the same coefficients plus reductions for
+ * the coefficient and initial-condition gradients.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array pointer is a DEVICE pointer (hipMalloc'd or torch-owned GPU
+ *   memory) unless marked (host).  The caller owns every buffer; the library
+ *   keeps no reference after a call returns.
+ * - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *   NULL = the default stream).  The calls never allocate device memory,
+ *   never synchronise and never read device memory from the host, so they may
+ *   be captured into a HIP graph.  Scratch space is the caller's workspace.
+ * - Signals are FP32 (float) in layout FILT_LAYOUT_TB ([T][B], x[t*B+b]) or
+ *   FILT_LAYOUT_BT ([B][T], x[b*T+t]), dense.
+ * - Coefficients: a holds a_1..a_N (a_0 = 1 is implicit, sign as in Eq. 1;
+ *   callers normalise by a_0), b holds b_0..b_M.  Time-invariant: a[B][N],
+ *   b[B][M+1].  Per-sample (time_varying = 1): the signal layout with the tap
+ *   index innermost, [T][B][K] (TB) or [B][T][K] (BT).
+ * - Initial conditions, most recent first: xi[B][M] with xi[b][j-1] = x[-j],
+ *   yi[B][N] with yi[b][j-1] = y[-j].  NULL means zero.
+ * - Errors: the return value; a thread-local message is available from
+ *   filt_last_error().  Argument errors are detected on the host before any
+ *   GPU work is queued (nothing is written).  FILT_EHIP reports a failed
+ *   launch; outputs are then undefined.
+ */
+#ifndef FILT_H
+#define FILT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FILT_OK = 0,
+    FILT_EINVAL = 1,       /* bad argument (NULL where required, bad size/layout) */
+    FILT_EUNSUPPORTED = 2, /* valid but not implemented (e.g. order above 16) */
+    FILT_EWORKSPACE = 3,   /* workspace NULL or smaller than filt_workspace_bytes */
+    FILT_EHIP = 4          /* a HIP runtime call or kernel launch failed */
+} filt_status;
+
+typedef enum { FILT_LAYOUT_TB = 0, FILT_LAYOUT_BT = 1 } filt_layout;
+
+/* flags */
+#define FILT_F64_STATE 0x1 /* run the recursion in FP64 (I/O stays FP32) */
+
+typedef struct {
+    int64_t B;            /* channels (>= 0); B == 0 or T == 0 is a no-op */
+    int64_t T;            /* samples per channel (>= 0) */
+    int32_t M;            /* feed-forward order: b_0..b_M, 0 <= M <= 16 */
+    int32_t N;            /* feedback order: a_1..a_N, 0 <= N <= 16 */
+    int32_t time_varying; /* 0: coefficients per channel; 1: per sample */
+    int32_t layout;       /* filt_layout of x, y, gy, gx (and per-sample coefficients) */
+    int32_t flags;        /* FILT_F64_STATE */
+    int32_t chunk;        /* time-chunk length for the parallel scan; 0 = automatic,
+                             else a multiple of 32 */
+} filt_problem;
+
+/* Size in bytes of the workspace that filt_forward / filt_backward need for
+ * problem *p (the larger of the two).  bytes is a host pointer. */
+filt_status filt_workspace_bytes(const filt_problem *p, size_t *bytes);
+
+/* Forward filter (Eq. 1 as a difference equation).
+ *   x   [layout]        input signal
+ *   b   coefficients    NULL => b = [1] (then M must be 0)
+ *   a   coefficients    may be NULL only when N == 0
+ *   xi  [B][M] or NULL, yi [B][N] or NULL
+ *   y   [layout]        output, written in full
+ *   ws  workspace of at least filt_workspace_bytes(p) bytes (device) */
+filt_status filt_forward(const filt_problem *p, const float *x, const float *b, const float *a,
+                         const float *xi, const float *yi, float *y, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* Closed-form backward (Eqs. 6-9, App. A), given gy = dL/dy:
+ *   ybar[n] = gy[n] - sum_k a_k[n+k] ybar[n+k]     (reverse time, zero past T-1)
+ *   gx[n]   = sum_k b_k[n+k] ybar[n+k]
+ *   gb_k[n] = ybar[n] x[n-k],  ga_k[n] = -ybar[n] y[n-k]
+ *             (summed over n when time_varying == 0)
+ *   gxi[j-1] = sum_{k>=j} b_k[k-j] ybar[k-j],  gyi[j-1] = -sum_{k>=j} a_k[k-j] ybar[k-j]
+ * x, xi are read only when gb is requested or M > 0 matters for it; y, yi
+ * only when ga is requested.  Each of gx, gb, ga, gxi, gyi may be NULL (not
+ * computed); the others are written in full with the shapes of x, b, a, xi,
+ * yi. */
+filt_status filt_backward(const filt_problem *p, const float *gy, const float *x, const float *y,
+                          const float *b, const float *a, const float *xi, const float *yi,
+                          float *gx, float *gb, float *ga, float *gxi, float *gyi, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* The same two operations on FP64 data, computed in FP64 (for numerical
+ * gradient checks).  Arguments as above with double in place of float. */
+filt_status filt_forward_f64(const filt_problem *p, const double *x, const double *b,
+                             const double *a, const double *xi, const double *yi, double *y,
+                             void *ws, size_t ws_bytes, void *stream);
+filt_status filt_backward_f64(const filt_problem *p, const double *gy, const double *x,
+                              const double *y, const double *b, const double *a,
+                              const double *xi, const double *yi, double *gx, double *gb,
+                              double *ga, double *gxi, double *gyi, void *ws, size_t ws_bytes,
+                              void *stream);
+
+/* Chunk length the library picks for *p when p->chunk == 0 (for tests and
+ * tuning).  Host-only; returns 0 for an invalid problem. */
+int64_t filt_auto_chunk(const filt_problem *p);
+
+/* Text of a status code, and the last error message of the calling thread. */
+const char *filt_strerror(filt_status s);
+const char *filt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FILT_H */

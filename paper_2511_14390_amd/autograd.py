@@ -1,0 +1,56 @@
+"""``torch.autograd.Function`` over the C ABI: differentiable direct-form filter.
+
+Forward calls ``filt_forward``; backward calls ``filt_backward`` (the
+closed-form adjoint of Sec. 3.1 Eqs. 7-9 run in reverse time, fused with the
+gradient reductions).  Only the inputs and the output ``y`` are saved: in the
+direct form the filter state at any chunk boundary is a slice of ``y``
+(the last N outputs) and of ``x``, so nothing else needs to be stored and the
+backward recomputes everything else from them.  Gradients are requested only
+for the inputs that need them (``ctx.needs_input_grad``).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import filt as _f
+
+
+class LFilter(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, a, b, xi, yi, layout, chunk, f64_state):
+        y = _f.filt_forward(x, a, b, xi, yi, layout=layout, chunk=chunk, f64_state=f64_state)
+        ctx.save_for_backward(x, a, b, xi, yi, y)
+        ctx.cfg = (layout, chunk, f64_state)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, a, b, xi, yi, y = ctx.saved_tensors
+        layout, chunk, f64_state = ctx.cfg
+        need = ctx.needs_input_grad
+        want = [k for k, n in zip(("x", "a", "b", "xi", "yi"), need[:5]) if n]
+        if not want:
+            return (None,) * 8
+        g = _f.filt_backward(gy, x, y, a, b, xi, yi, layout=layout, chunk=chunk,
+                             f64_state=f64_state, want=tuple(want))
+        return (g.get("x"), g.get("a"), g.get("b") if b is not None else None,
+                g.get("xi") if xi is not None else None, g.get("yi") if yi is not None else None,
+                None, None, None)
+
+
+def lfilter(x, a, b=None, xi=None, yi=None, layout="BT", chunk=0, f64_state=False):
+    """Differentiable y[n] = sum_k b_k[n] x[n-k] - sum_k a_k[n] y[n-k].
+
+    ``a`` / ``b`` may be per-channel ``[B, K]`` or per-sample (the signal
+    layout plus a trailing tap axis).  Coefficients shared across channels can
+    be passed as ``c.expand(B, K)``; autograd sums the per-channel gradients.
+    """
+    if a is not None:
+        a = a.contiguous()
+    if b is not None:
+        b = b.contiguous()
+    if xi is not None:
+        xi = xi.contiguous()
+    if yi is not None:
+        yi = yi.contiguous()
+    return LFilter.apply(x.contiguous(), a, b, xi, yi, layout, int(chunk), bool(f64_state))

@@ -1,0 +1,91 @@
+"""Build libfilt.so (gfx950) in place from csrc/*.hip.
+
+Each translation unit is compiled by hipcc in parallel, then linked into
+``paper_2511_14390_amd/libfilt.so``.  Object files go to ``_build/`` next to
+the package (not tracked).
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import glob
+import os
+import subprocess
+import sys
+import time
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libfilt.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
+    # no packed FP32 instructions anywhere in the device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", INCLUDE, "-I", CSRC,
+]
+
+
+BUCKETS = (1, 2, 4, 8, 16, 32)
+TYPES = (("float", "float"), ("float", "double"), ("double", "double"))
+
+
+def _instantiation_units():
+    """One generated translation unit per (bucket, type pair, direction):
+    the fully unrolled kernels of the large buckets dominate compile time, so
+    they are spread over as many parallel hipcc processes as possible."""
+    out = []
+    for w in BUCKETS:
+        for io, acc in TYPES:
+            for dirn, macro in (("fwd", "FILT_DECLARE_FWD"), ("bwd", "FILT_DECLARE_BWD")):
+                path = os.path.join(BUILD, f"chunk_w{w}_{io}_{acc}_{dirn}.hip")
+                text = ("#define FILT_INSTANTIATING 1\n#include \"chunk.h\"\n"
+                        f"namespace filt_detail {{ {macro}({w}, {io}, {acc}, ) }}\n")
+                if not os.path.exists(path) or open(path).read() != text:
+                    with open(path, "w") as f:
+                        f.write(text)
+                out.append(path)
+    return out
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + _instantiation_units()
+
+
+def _compile(src):
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    t0 = time.time()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{msg}")
+    return obj, time.time() - t0
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), os.cpu_count() or 1, 16)
+    # longest units first so the pool stays busy
+    srcs.sort(key=lambda p: (-int(p.split("_w")[1].split("_")[0]) if "_w" in p else 0))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_compile, srcs))
+    if verbose:
+        for (obj, dt) in results:
+            print(f"  {os.path.basename(obj)}: {dt:.1f}s", flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    t = time.time()
+    build(verbose=True)
+    print(f"built {LIB} in {time.time() - t:.1f}s", file=sys.stderr)

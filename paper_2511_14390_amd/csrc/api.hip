@@ -1,0 +1,280 @@
+// api.hip -- C ABI entry points of libfilt.so: argument validation,
+// workspace plan and dispatch to the per-bucket kernels.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+
+namespace filt_detail {
+
+thread_local char g_err[512] = "";
+
+filt_status fail(filt_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+filt_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(FILT_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return FILT_OK;
+}
+
+
+inline int pow2_at_least(int v)
+{
+    int w = 1;
+    while (w < v)
+        w <<= 1;
+    return w;
+}
+
+int64_t auto_chunk(int64_t B, int64_t T)
+{
+    // aim for about 32K (channel, chunk) lanes in the apply phase
+    const int64_t target = 32768;
+    int64_t per = (target + B - 1) / std::max<int64_t>(B, 1);
+    int64_t L = (T + per - 1) / std::max<int64_t>(per, 1);
+    L = ((L + 31) / 32) * 32;
+    return std::max<int64_t>(32, std::min<int64_t>(L, 1 << 16));
+}
+
+filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, const void *a)
+{
+    if (p == nullptr)
+        return fail(FILT_EINVAL, "problem is NULL");
+    if (p->B < 0 || p->T < 0)
+        return fail(FILT_EINVAL, "B and T must be >= 0 (B=%lld T=%lld)", (long long)p->B,
+                    (long long)p->T);
+    if (p->M < 0 || p->N < 0)
+        return fail(FILT_EINVAL, "orders must be >= 0 (M=%d N=%d)", p->M, p->N);
+    if (p->M > kMaxOrder || p->N > kMaxOrder)
+        return fail(FILT_EUNSUPPORTED, "orders above %d are not supported (M=%d N=%d)",
+                    kMaxOrder, p->M, p->N);
+    if (p->layout != FILT_LAYOUT_TB && p->layout != FILT_LAYOUT_BT)
+        return fail(FILT_EINVAL, "layout must be FILT_LAYOUT_TB or FILT_LAYOUT_BT");
+    if (p->time_varying != 0 && p->time_varying != 1)
+        return fail(FILT_EINVAL, "time_varying must be 0 or 1");
+    if (p->chunk < 0 || (p->chunk % 32) != 0)
+        return fail(FILT_EINVAL, "chunk must be 0 or a positive multiple of 32 (got %d)",
+                    p->chunk);
+    if (p->flags & ~FILT_F64_STATE)
+        return fail(FILT_EINVAL, "unknown flags 0x%x", p->flags);
+    if (p->B == 0 || p->T == 0)
+        return FILT_OK;
+    if (x_or_gy == nullptr)
+        return fail(FILT_EINVAL, "input signal is NULL");
+    if (b == nullptr && p->M != 0)
+        return fail(FILT_EINVAL, "b is NULL but M=%d (NULL b means b=[1], M=0)", p->M);
+    if (a == nullptr && p->N != 0)
+        return fail(FILT_EINVAL, "a is NULL but N=%d", p->N);
+    return FILT_OK;
+}
+
+Dims make_dims(const filt_problem *p, int has_b)
+{
+    Dims d{};
+    d.B = p->B;
+    d.T = p->T;
+    d.M = p->M;
+    d.N = p->N;
+    d.tv = p->time_varying;
+    d.layout = p->layout;
+    d.has_b = has_b;
+    d.L = p->chunk > 0 ? p->chunk : auto_chunk(p->B, p->T);
+    d.C = (d.T + d.L - 1) / d.L;
+    const int64_t steps = std::max<int64_t>(d.C - 1, 1);
+    int64_t G = 1;
+    while (G * G < steps)
+        ++G;
+    d.G = G;
+    d.NB = (steps + G - 1) / G;
+    return d;
+}
+
+template <typename io_t, typename acc_t>
+filt_status forward_dispatch(const Dims &d, int W, const io_t *x, const io_t *bc, const io_t *ac,
+                             const io_t *xi, const io_t *yi, io_t *y, char *ws, hipStream_t st)
+{
+#define FWD(w)                                                                                     \
+    case w:                                                                                        \
+        return forward_w<w, io_t, acc_t>(d, x, bc, ac, xi, yi, y, ws, st);
+    switch (W) {
+        FWD(1) FWD(2) FWD(4) FWD(8) FWD(16) FWD(32)
+    default:
+        return fail(FILT_EUNSUPPORTED, "register bucket %d", W);
+    }
+#undef FWD
+}
+
+template <typename io_t, typename acc_t>
+filt_status backward_dispatch(const Dims &d, int W, const io_t *gy, const io_t *x, const io_t *y,
+                              const io_t *bc, const io_t *ac, const io_t *xi, const io_t *yi,
+                              io_t *gx, io_t *gb, io_t *ga, io_t *gxi, io_t *gyi, char *ws,
+                              hipStream_t st)
+{
+#define BWD(w)                                                                                     \
+    case w:                                                                                        \
+        return backward_w<w, io_t, acc_t>(d, gy, x, y, bc, ac, xi, yi, gx, gb, ga, gxi, gyi, ws, \
+                                          st);
+    switch (W) {
+        BWD(1) BWD(2) BWD(4) BWD(8) BWD(16) BWD(32)
+    default:
+        return fail(FILT_EUNSUPPORTED, "register bucket %d", W);
+    }
+#undef BWD
+}
+
+
+template <typename io_t>
+filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, const io_t *ac,
+                          const io_t *xi, const io_t *yi, io_t *y, void *ws, size_t ws_bytes,
+                          void *stream)
+{
+    filt_status s = validate(p, x, bc, ac);
+    if (s != FILT_OK)
+        return s;
+    if (p->B == 0 || p->T == 0)
+        return FILT_OK;
+    if (y == nullptr)
+        return fail(FILT_EINVAL, "y is NULL");
+    const Dims d = make_dims(p, bc != nullptr);
+    const WsPlan w = ws_plan(d);
+    if (ws == nullptr || ws_bytes < w.total)
+        return fail(FILT_EWORKSPACE, "workspace of %zu bytes needed, %zu given", w.total,
+                    ws == nullptr ? (size_t)0 : ws_bytes);
+    char *wsa = (char *)(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = sizeof(io_t) == 8 || (p->flags & FILT_F64_STATE);
+    if (f64)
+        return forward_dispatch<io_t, double>(d, W, x, bc, ac, xi, yi, y, wsa, st);
+    return forward_dispatch<io_t, float>(d, W, x, bc, ac, xi, yi, y, wsa, st);
+}
+
+template <typename io_t>
+filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x, const io_t *y,
+                           const io_t *bc, const io_t *ac, const io_t *xi, const io_t *yi,
+                           io_t *gx, io_t *gb, io_t *ga, io_t *gxi, io_t *gyi, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    filt_status s = validate(p, gy, bc, ac);
+    if (s != FILT_OK)
+        return s;
+    if (p->B == 0 || p->T == 0) {
+        if (p->B > 0 && (gxi != nullptr || gyi != nullptr || ga != nullptr || gb != nullptr))
+            return fail(FILT_EUNSUPPORTED, "T == 0 with gradient outputs: caller zero-fills");
+        return FILT_OK;
+    }
+    if (gb != nullptr && bc == nullptr)
+        return fail(FILT_EINVAL, "gb requested but b is NULL");
+    if (gb != nullptr && x == nullptr)
+        return fail(FILT_EINVAL, "gb requested but x is NULL");
+    if (ga != nullptr && (y == nullptr || p->N == 0))
+        return fail(FILT_EINVAL, "ga requested but y is NULL or N == 0");
+    const Dims d = make_dims(p, bc != nullptr);
+    const WsPlan w = ws_plan(d);
+    if (ws == nullptr || ws_bytes < w.total)
+        return fail(FILT_EWORKSPACE, "workspace of %zu bytes needed, %zu given", w.total,
+                    ws == nullptr ? (size_t)0 : ws_bytes);
+    char *wsa = (char *)(((uintptr_t)ws + 255) & ~uintptr_t(255));
+    const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = sizeof(io_t) == 8 || (p->flags & FILT_F64_STATE);
+    if (f64)
+        return backward_dispatch<io_t, double>(d, W, gy, x, y, bc, ac, xi, yi, gx, gb, ga, gxi,
+                                               gyi, wsa, st);
+    return backward_dispatch<io_t, float>(d, W, gy, x, y, bc, ac, xi, yi, gx, gb, ga, gxi, gyi,
+                                          wsa, st);
+}
+
+
+}  // namespace filt_detail
+
+using namespace filt_detail;
+
+
+extern "C" {
+
+filt_status filt_workspace_bytes(const filt_problem *p, size_t *bytes)
+{
+    filt_status s = validate(p, (const void *)1, (const void *)1, (const void *)1);
+    if (s != FILT_OK)
+        return s;
+    if (bytes == nullptr)
+        return fail(FILT_EINVAL, "bytes is NULL");
+    if (p->B == 0 || p->T == 0) {
+        *bytes = 0;
+        return FILT_OK;
+    }
+    *bytes = ws_plan(make_dims(p, 1)).total;
+    return FILT_OK;
+}
+
+int64_t filt_auto_chunk(const filt_problem *p)
+{
+    if (p == nullptr || p->B <= 0 || p->T <= 0)
+        return 0;
+    return p->chunk > 0 ? p->chunk : auto_chunk(p->B, p->T);
+}
+
+filt_status filt_forward(const filt_problem *p, const float *x, const float *b, const float *a,
+                         const float *xi, const float *yi, float *y, void *ws, size_t ws_bytes,
+                         void *stream)
+{
+    return forward_entry<float>(p, x, b, a, xi, yi, y, ws, ws_bytes, stream);
+}
+
+filt_status filt_backward(const filt_problem *p, const float *gy, const float *x, const float *y,
+                          const float *b, const float *a, const float *xi, const float *yi,
+                          float *gx, float *gb, float *ga, float *gxi, float *gyi, void *ws,
+                          size_t ws_bytes, void *stream)
+{
+    return backward_entry<float>(p, gy, x, y, b, a, xi, yi, gx, gb, ga, gxi, gyi, ws, ws_bytes,
+                                 stream);
+}
+
+filt_status filt_forward_f64(const filt_problem *p, const double *x, const double *b,
+                             const double *a, const double *xi, const double *yi, double *y,
+                             void *ws, size_t ws_bytes, void *stream)
+{
+    return forward_entry<double>(p, x, b, a, xi, yi, y, ws, ws_bytes, stream);
+}
+
+filt_status filt_backward_f64(const filt_problem *p, const double *gy, const double *x,
+                              const double *y, const double *b, const double *a,
+                              const double *xi, const double *yi, double *gx, double *gb,
+                              double *ga, double *gxi, double *gyi, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    return backward_entry<double>(p, gy, x, y, b, a, xi, yi, gx, gb, ga, gxi, gyi, ws, ws_bytes,
+                                  stream);
+}
+
+const char *filt_strerror(filt_status s)
+{
+    switch (s) {
+    case FILT_OK:
+        return "ok";
+    case FILT_EINVAL:
+        return "invalid argument";
+    case FILT_EUNSUPPORTED:
+        return "unsupported problem";
+    case FILT_EWORKSPACE:
+        return "workspace too small";
+    case FILT_EHIP:
+        return "HIP error";
+    }
+    return "unknown status";
+}
+
+const char *filt_last_error(void) { return g_err; }
+
+}  // extern "C"

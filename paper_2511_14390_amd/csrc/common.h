@@ -1,0 +1,230 @@
+// common.h -- shared declarations of the filter library (internal).
+//
+// Method: Yu & Fazekas, arXiv 2511.14390.  Forward = Sec. 2 Eq. 1 as a
+// difference equation (per-sample coefficients, initial conditions).
+// Backward = Sec. 3.1 Eqs. 6-9 / Appendix A in scalar form: the adjoint is the
+// transposed (scatter) filter run in reverse time (the "backward of DF is TDF"
+// remark after Eq. 9), fused with the coefficient and initial-condition
+// gradient products.
+//
+// Time parallelism follows the associative-scan idea of Sec. 3.2: the signal
+// is cut into chunks of L samples and every chunk is summarised by the affine
+// map (Phi_c, s_c) that takes the filter state entering the chunk to the state
+// leaving it (Phi_c = the product of the chunk's companion matrices, Eq. 4;
+// s_c = the zero-state end state).  Chunks combine with the operator
+// (Phi, s) + (Phi', s') = (Phi' Phi, Phi' s + s') of Sec. 3.2.  Three phases:
+//   1. summary  -- every (channel, chunk) solves its chunk from zero state
+//                  (s_c) and, for per-sample coefficients, from each unit
+//                  state (the columns of Phi_c); time-invariant filters share
+//                  one Phi per channel.
+//   2. carry    -- a blocked scan over the chunk summaries (FP64) yields the
+//                  exact state entering every chunk.
+//   3. apply    -- every (channel, chunk) reruns its chunk from that state and
+//                  writes the outputs (forward: y; backward: gx and the
+//                  coefficient / initial-condition gradients).
+//
+// Register state: histories live in W = 2^ceil(log2(max(N, M+1))) registers
+// addressed modulo W; the time loop is unrolled by W so every register index
+// is a compile-time constant (no scratch, no shifting).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "filt.h"
+
+namespace filt_detail {
+
+filt_status fail(filt_status s, const char *fmt, ...);
+filt_status check_launch(const char *what);
+
+constexpr int kThreads = 256;
+constexpr int kMaxOrder = 16;
+
+// Device-side description of one problem.
+struct Dims {
+    int64_t B, T;
+    int M, N;
+    int tv, layout;
+    int has_b;
+    int64_t L, C;   // chunk length (multiple of 32) and number of chunks
+    int64_t G, NB;  // carry: steps per block and number of blocks
+};
+
+__device__ __forceinline__ int64_t sig_at(const Dims &d, int64_t b, int64_t t)
+{
+    return d.layout == FILT_LAYOUT_TB ? t * d.B + b : b * d.T + t;
+}
+
+// Start of the coefficient row (K taps) that applies at (channel b, time t).
+__device__ __forceinline__ int64_t row_at(const Dims &d, int64_t b, int64_t t, int K)
+{
+    if (!d.tv)
+        return b * K;
+    return (d.layout == FILT_LAYOUT_TB ? t * d.B + b : b * d.T + t) * (int64_t)K;
+}
+
+// x[t] for any t: negative times from xi (x[-j] = xi[j-1]), past T -> 0.
+template <typename io_t, typename acc_t>
+__device__ __forceinline__ acc_t ld_x(const Dims &d, const io_t *x, const io_t *xi, int64_t b,
+                                      int64_t t)
+{
+    if (t >= 0)
+        return t < d.T ? (acc_t)x[sig_at(d, b, t)] : acc_t(0);
+    const int64_t j = -t;
+    return (xi != nullptr && j <= d.M) ? (acc_t)xi[b * d.M + (j - 1)] : acc_t(0);
+}
+
+template <typename io_t, typename acc_t>
+__device__ __forceinline__ acc_t ld_y(const Dims &d, const io_t *y, const io_t *yi, int64_t b,
+                                      int64_t t)
+{
+    if (t >= 0)
+        return t < d.T ? (acc_t)y[sig_at(d, b, t)] : acc_t(0);
+    const int64_t j = -t;
+    return (yi != nullptr && j <= d.N) ? (acc_t)yi[b * d.N + (j - 1)] : acc_t(0);
+}
+
+// Coefficients of one time step: ca[k] = a_k (k = 1..W, 0 beyond N),
+// cb[k] = b_k (k = 0..W-1, 0 beyond M).  Rows past T read as zero.
+template <int W, typename io_t, typename acc_t>
+__device__ __forceinline__ void ld_coef(const Dims &d, const io_t *bc, const io_t *ac, int64_t b,
+                                        int64_t t, acc_t (&ca)[W + 1], acc_t (&cb)[W])
+{
+    const bool in = t < d.T;
+    const io_t *ar = ac + (d.N > 0 ? row_at(d, b, t, d.N) : 0);
+#pragma unroll
+    for (int k = 1; k <= W; ++k)
+        ca[k] = (in && k <= d.N) ? (acc_t)ar[k - 1] : acc_t(0);
+    ca[0] = acc_t(0);
+    if (d.has_b) {
+        const io_t *br = bc + row_at(d, b, t, d.M + 1);
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            cb[k] = (in && k <= d.M) ? (acc_t)br[k] : acc_t(0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            cb[k] = (in && k == 0) ? acc_t(1) : acc_t(0);
+    }
+}
+
+// Decode a flat item index into (channel, chunk, column).  Channels vary
+// fastest in the [T][B] layout (coalesced rows), chunks in [B][T].
+__device__ __forceinline__ void decode(const Dims &d, int64_t idx, int64_t ncs, int64_t &b,
+                                       int64_t &c, int64_t &j)
+{
+    if (d.layout == FILT_LAYOUT_TB) {
+        b = idx % d.B;
+        const int64_t r = idx / d.B;
+        c = r % ncs;
+        j = r / ncs;
+    } else {
+        c = idx % ncs;
+        const int64_t r = idx / ncs;
+        b = r % d.B;
+        j = r / d.B;
+    }
+}
+
+
+// Affine scan over chunk summaries (state S_{i+1} = Phi_i S_i + s_i).
+//
+// Steps i = 0 .. C-2 map state S_i to S_{i+1} = Phi S_i + s.  Forward: step i
+// uses chunk i's summary and S_i is the state entering chunk i.  Backward:
+// step i uses chunk C-1-i and S_i is the state entering chunk C-1-i from the
+// future.  Blocked in three passes (blocks of G steps): block aggregates,
+// a sequential pass over blocks, then the states inside each block.
+
+struct CarryArgs {
+    const double *summ;   // per-chunk summaries
+    const double *phi;    // per-channel time-invariant Phi (and R), or null
+    int64_t SS;           // stride of one chunk summary (doubles)
+    int D;                // state size N
+    int R;                // extra outputs (M for backward, 0 for forward)
+    int bwd;
+    double *agg;          // [B][NB][D*D + D]
+    double *bstart;       // [B][NB][D] state at each block start
+    double *states;       // [B][C][D+R] state entering each chunk
+};
+
+
+inline unsigned grid_for(int64_t n)
+{
+    return (unsigned)((n + kThreads - 1) / kThreads);
+}
+
+// Workspace carve-up (all FP64), 256-byte aligned regions.
+struct WsPlan {
+    size_t summ, phi, agg, bstart, states, part, total;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+inline WsPlan ws_plan(const Dims &d)
+{
+    const int64_t N = d.N, M = d.M;
+    const int64_t SSf = N * N + N;
+    const int64_t SSb = (N + 1) * (N + M);
+    WsPlan w{};
+    size_t off = 0;
+    auto take = [&](size_t doubles) {
+        size_t o = off;
+        off = align256(off + doubles * sizeof(double));
+        return o;
+    };
+    w.summ = take((size_t)(d.B * d.C * std::max(SSf, SSb)));
+    w.phi = take((size_t)(d.B * (N * N + M * N)));
+    w.agg = take((size_t)(d.B * d.NB * (N * N + N)));
+    w.bstart = take((size_t)(d.B * d.NB * std::max<int64_t>(N, 1)));
+    w.states = take((size_t)(d.B * d.C * (N + M)));
+    w.part = take((size_t)(d.B * d.C * (N + M + 1)));
+    w.total = off + 256;
+    return w;
+}
+
+// carry.hip
+filt_status carry_run(const Dims &d, const CarryArgs &a, const void *init, bool init_f64,
+                      hipStream_t st);
+filt_status fir_states_run(const Dims &d, const double *summ, double *states, hipStream_t st);
+filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb, bool f64,
+                           hipStream_t st);
+
+// chunk_w*.hip: one translation unit per register bucket W
+template <int W, typename io_t, typename acc_t>
+filt_status forward_w(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
+                      const io_t *xi, const io_t *yi, io_t *y, char *ws, hipStream_t st);
+template <int W, typename io_t, typename acc_t>
+filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t *y,
+                       const io_t *bc, const io_t *ac, const io_t *xi, const io_t *yi, io_t *gx,
+                       io_t *gb, io_t *ga, io_t *gxi, io_t *gyi, char *ws, hipStream_t st);
+
+#define FILT_DECLARE_FWD(W, IO, ACC, EXT)                                                          \
+    EXT template filt_status forward_w<W, IO, ACC>(const Dims &, const IO *, const IO *,           \
+                                                   const IO *, const IO *, const IO *, IO *,       \
+                                                   char *, hipStream_t);
+#define FILT_DECLARE_BWD(W, IO, ACC, EXT)                                                          \
+    EXT template filt_status backward_w<W, IO, ACC>(                                               \
+        const Dims &, const IO *, const IO *, const IO *, const IO *, const IO *, const IO *,      \
+        const IO *, IO *, IO *, IO *, IO *, IO *, char *, hipStream_t);
+#define FILT_DECLARE_W(W, IO, ACC, EXT) FILT_DECLARE_FWD(W, IO, ACC, EXT) FILT_DECLARE_BWD(W, IO, ACC, EXT)
+#define FILT_DECLARE_BUCKET(W, EXT)                                                                \
+    FILT_DECLARE_W(W, float, float, EXT)                                                           \
+    FILT_DECLARE_W(W, float, double, EXT)                                                          \
+    FILT_DECLARE_W(W, double, double, EXT)
+
+// The explicit instantiations live in generated translation units (one per
+// bucket, type pair and direction, see build.py); every other unit sees them
+// as extern.
+#ifndef FILT_INSTANTIATING
+FILT_DECLARE_BUCKET(1, extern)
+FILT_DECLARE_BUCKET(2, extern)
+FILT_DECLARE_BUCKET(4, extern)
+FILT_DECLARE_BUCKET(8, extern)
+FILT_DECLARE_BUCKET(16, extern)
+FILT_DECLARE_BUCKET(32, extern)
+#endif
+
+}  // namespace filt_detail

@@ -1,0 +1,196 @@
+"""Thin ctypes binding of libfilt.so (``include/filt.h``).
+
+Argument marshalling only: every step of the filter runs in the HIP library.
+Tensors must live on the GPU; PyTorch provides the memory, the workspace and
+the current HIP stream.  If the library has not been built the first call
+raises -- there is no CPU fallback.
+
+Shapes (same as the C ABI): layout ``"TB"`` signals ``[T, B]``, ``"BT"``
+signals ``[B, T]``; ``a`` is ``[B, N]`` or per-sample ``[T, B, N]`` /
+``[B, T, N]``; ``b`` likewise with ``M + 1`` taps (``None`` means ``b = [1]``);
+``xi`` ``[B, M]``, ``yi`` ``[B, N]`` (``None`` means zero).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfilt.so")
+
+FILT_OK, FILT_EINVAL, FILT_EUNSUPPORTED, FILT_EWORKSPACE, FILT_EHIP = range(5)
+FILT_LAYOUT_TB, FILT_LAYOUT_BT = 0, 1
+FILT_F64_STATE = 0x1
+
+
+class FiltProblem(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int64), ("T", ctypes.c_int64), ("M", ctypes.c_int32),
+                ("N", ctypes.c_int32), ("time_varying", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("flags", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+
+
+class FiltError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        P, S, I64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
+        PP = ctypes.POINTER(FiltProblem)
+        L.filt_workspace_bytes.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+        L.filt_workspace_bytes.restype = ctypes.c_int
+        L.filt_auto_chunk.argtypes = [PP]
+        L.filt_auto_chunk.restype = I64
+        for name in ("filt_forward", "filt_forward_f64"):
+            f = getattr(L, name)
+            f.argtypes = [PP] + [P] * 6 + [P, S, P]
+            f.restype = ctypes.c_int
+        for name in ("filt_backward", "filt_backward_f64"):
+            f = getattr(L, name)
+            f.argtypes = [PP] + [P] * 12 + [P, S, P]
+            f.restype = ctypes.c_int
+        L.filt_strerror.argtypes = [ctypes.c_int]
+        L.filt_strerror.restype = ctypes.c_char_p
+        L.filt_last_error.argtypes = []
+        L.filt_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != FILT_OK:
+        L = lib()
+        raise FiltError(status, f"{L.filt_strerror(status).decode()}: "
+                                f"{L.filt_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _layout_code(layout):
+    if layout == "TB":
+        return FILT_LAYOUT_TB
+    if layout == "BT":
+        return FILT_LAYOUT_BT
+    raise ValueError("layout must be 'TB' or 'BT'")
+
+
+def problem(x, a, b=None, layout="BT", chunk=0, f64_state=False):
+    """Build the filt_problem for these tensors (shapes checked here)."""
+    if x.dim() != 2:
+        raise ValueError("x must be 2-D")
+    T, B = (x.shape[0], x.shape[1]) if layout == "TB" else (x.shape[1], x.shape[0])
+    N = 0 if a is None else a.shape[-1]
+    M = 0 if b is None else b.shape[-1] - 1
+    tv = (a is not None and a.dim() == 3) or (b is not None and b.dim() == 3)
+    for c, K in ((a, N), (b, M + 1)):
+        if c is None:
+            continue
+        want = (B, K) if not tv else ((T, B, K) if layout == "TB" else (B, T, K))
+        if tuple(c.shape) != want:
+            raise ValueError(f"coefficient shape {tuple(c.shape)} != {want}")
+    p = FiltProblem(B, T, M, N, int(tv), _layout_code(layout),
+                    FILT_F64_STATE if f64_state else 0, int(chunk))
+    return p
+
+
+def _prep(t, dtype, device, name):
+    if t is None:
+        return None
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def workspace_bytes(p):
+    n = ctypes.c_size_t(0)
+    _check(lib().filt_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def auto_chunk(p):
+    return int(lib().filt_auto_chunk(ctypes.byref(p)))
+
+
+def _workspace(p, device, ws):
+    need = workspace_bytes(p)
+    if ws is not None and ws.numel() >= need:
+        return ws, need
+    return torch.empty(max(need, 1), dtype=torch.uint8, device=device), need
+
+
+def _stream(device, stream):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def filt_forward(x, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0, f64_state=False,
+                 out=None, ws=None, stream=None):
+    """y = direct-form filter of x (see include/filt.h).  Returns y."""
+    dev, dt = x.device, x.dtype
+    if dt not in (torch.float32, torch.float64):
+        raise ValueError("x must be float32 or float64")
+    if dev.type != "cuda":
+        raise ValueError("filt_forward runs on the GPU only")
+    x = x.contiguous()
+    a, b, xi, yi = (_prep(t, dt, dev, n) for t, n in ((a, "a"), (b, "b"), (xi, "xi"), (yi, "yi")))
+    p = problem(x, a, b, layout, chunk, f64_state)
+    y = out if out is not None else torch.empty_like(x)
+    ws, need = _workspace(p, dev, ws)
+    fn = lib().filt_forward_f64 if dt == torch.float64 else lib().filt_forward
+    _check(fn(ctypes.byref(p), _ptr(x), _ptr(b), _ptr(a), _ptr(xi), _ptr(yi), _ptr(y), _ptr(ws),
+              ctypes.c_size_t(ws.numel()), _stream(dev, stream)))
+    return y
+
+
+def filt_backward(gy, x, y, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0,
+                  f64_state=False, want=("x", "a", "b", "xi", "yi"), ws=None, stream=None):
+    """Closed-form gradients (see include/filt.h).  Returns a dict with the
+    requested keys among x, a, b, xi, yi (b only if b was given; xi / yi
+    always have shapes [B, M] / [B, N])."""
+    dev, dt = gy.device, gy.dtype
+    if dev.type != "cuda":
+        raise ValueError("filt_backward runs on the GPU only")
+    gy = gy.contiguous()
+    x, y, a, b, xi, yi = (_prep(t, dt, dev, n) for t, n in
+                          ((x, "x"), (y, "y"), (a, "a"), (b, "b"), (xi, "xi"), (yi, "yi")))
+    p = problem(gy, a, b, layout, chunk, f64_state)
+    B, M, N = p.B, p.M, p.N
+    gx = torch.empty_like(gy) if "x" in want else None
+    ga = torch.empty_like(a) if ("a" in want and a is not None and N > 0) else None
+    gb = torch.empty_like(b) if ("b" in want and b is not None) else None
+    gxi = torch.empty((B, M), dtype=dt, device=dev) if "xi" in want else None
+    gyi = torch.empty((B, N), dtype=dt, device=dev) if "yi" in want else None
+    if p.T == 0:
+        out = {}
+        for k, v in (("x", gx), ("a", ga), ("b", gb), ("xi", gxi), ("yi", gyi)):
+            if v is not None:
+                out[k] = v.zero_()
+        return out
+    ws, need = _workspace(p, dev, ws)
+    fn = lib().filt_backward_f64 if dt == torch.float64 else lib().filt_backward
+    _check(fn(ctypes.byref(p), _ptr(gy), _ptr(x), _ptr(y), _ptr(b), _ptr(a), _ptr(xi), _ptr(yi),
+              _ptr(gx), _ptr(gb), _ptr(ga), _ptr(gxi if M > 0 else None),
+              _ptr(gyi if N > 0 else None), _ptr(ws), ctypes.c_size_t(ws.numel()),
+              _stream(dev, stream)))
+    out = {}
+    for k, v in (("x", gx), ("a", ga), ("b", gb), ("xi", gxi), ("yi", gyi)):
+        if v is not None:
+            out[k] = v
+    return out

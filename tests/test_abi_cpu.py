@@ -1,0 +1,153 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/filt.h, and rejects bad arguments on the host (before any
+GPU work is queued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2511_14390_amd import filt as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "filt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(filt_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(F.LIB_PATH):
+        pytest.skip("libfilt.so not built")
+    return F.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("filt_forward", "filt_backward", "filt_workspace_bytes", "filt_forward_f64",
+              "filt_backward_f64", "filt_strerror", "filt_last_error", "filt_auto_chunk"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def _prob(**kw):
+    d = dict(B=4, T=100, M=0, N=2, time_varying=0, layout=1, flags=0, chunk=0)
+    d.update(kw)
+    return F.FiltProblem(d["B"], d["T"], d["M"], d["N"], d["time_varying"], d["layout"],
+                         d["flags"], d["chunk"])
+
+
+def _ws(L, p):
+    n = ctypes.c_size_t(0)
+    rc = L.filt_workspace_bytes(ctypes.byref(p), ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_query(L):
+    rc, n = _ws(L, _prob())
+    assert rc == F.FILT_OK and n > 0
+    rc, n = _ws(L, _prob(B=0))
+    assert rc == F.FILT_OK and n == 0
+    # grows with the problem
+    _, small = _ws(L, _prob(T=1000, time_varying=1, N=16))
+    _, big = _ws(L, _prob(T=100000, time_varying=1, N=16))
+    assert big > small
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(B=-1), F.FILT_EINVAL),
+    (dict(T=-5), F.FILT_EINVAL),
+    (dict(N=-1), F.FILT_EINVAL),
+    (dict(N=17), F.FILT_EUNSUPPORTED),
+    (dict(M=20), F.FILT_EUNSUPPORTED),
+    (dict(layout=7), F.FILT_EINVAL),
+    (dict(time_varying=2), F.FILT_EINVAL),
+    (dict(chunk=48), F.FILT_EINVAL),
+    (dict(flags=0x80), F.FILT_EINVAL),
+])
+def test_invalid_problems_rejected(L, kw, code):
+    rc, _ = _ws(L, _prob(**kw))
+    assert rc == code
+    assert L.filt_last_error().decode() != ""
+
+
+def test_forward_argument_errors_on_host(L):
+    p = _prob()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: rejected before any launch
+    # NULL x
+    rc = L.filt_forward(ctypes.byref(p), None, None, fake, None, None, fake, fake,
+                        ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EINVAL
+    # b NULL with M > 0
+    p2 = _prob(M=2)
+    rc = L.filt_forward(ctypes.byref(p2), fake, None, fake, None, None, fake, fake,
+                        ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EINVAL
+    # a NULL with N > 0
+    rc = L.filt_forward(ctypes.byref(p), fake, None, None, None, None, fake, fake,
+                        ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EINVAL
+    # y NULL
+    rc = L.filt_forward(ctypes.byref(p), fake, None, fake, None, None, None, fake,
+                        ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EINVAL
+    # workspace too small / missing
+    rc = L.filt_forward(ctypes.byref(p), fake, None, fake, None, None, fake, fake,
+                        ctypes.c_size_t(8), None)
+    assert rc == F.FILT_EWORKSPACE
+    rc = L.filt_forward(ctypes.byref(p), fake, None, fake, None, None, fake, None,
+                        ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EWORKSPACE
+    # empty problems are no-ops even with NULL buffers
+    p0 = _prob(T=0)
+    assert L.filt_forward(ctypes.byref(p0), None, None, None, None, None, None, None,
+                          ctypes.c_size_t(0), None) == F.FILT_OK
+
+
+def test_backward_argument_errors_on_host(L):
+    p = _prob(M=1)
+    fake = ctypes.c_void_p(0x1000)
+    args = [fake] * 12
+    # gb requested but b NULL
+    a = list(args)
+    a[3] = None  # b
+    rc = L.filt_backward(ctypes.byref(p), *a, fake, ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EINVAL
+    # ga requested but y NULL
+    a = list(args)
+    a[2] = None  # y
+    rc = L.filt_backward(ctypes.byref(p), *a, fake, ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EINVAL
+    # NULL gy
+    a = list(args)
+    a[0] = None
+    rc = L.filt_backward(ctypes.byref(p), *a, fake, ctypes.c_size_t(1 << 20), None)
+    assert rc == F.FILT_EINVAL
+
+
+def test_strerror(L):
+    assert L.filt_strerror(F.FILT_OK).decode() == "ok"
+    assert "workspace" in L.filt_strerror(F.FILT_EWORKSPACE).decode()
+
+
+def test_auto_chunk_multiple_of_32(L):
+    for B, T in ((1, 10), (4, 4096), (64, 48000), (1024, 65536), (2, 1 << 22)):
+        c = L.filt_auto_chunk(ctypes.byref(_prob(B=B, T=T)))
+        assert c >= 32 and c % 32 == 0
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+
+    x = torch.zeros(2, 10)
+    a = torch.zeros(2, 2)
+    with pytest.raises(ValueError):
+        F.filt_forward(x, a)
