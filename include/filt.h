@@ -114,6 +114,18 @@ filt_status filt_backward_f64(const filt_problem *p, const double *gy, const dou
  * tuning).  Host-only; returns 0 for an invalid problem. */
 int64_t filt_auto_chunk(const filt_problem *p);
 
+/* Diagnostics for benchmarking: per-kernel GPU time.  While enabled, the
+ * library records a HIP event pair on the launch stream around every kernel
+ * it launches (no synchronisation).  filt_profile_enable(1) creates the
+ * events on the host (not to be called during graph capture) and clears the
+ * previous records; filt_profile_enable(0) stops recording.
+ * filt_profile_read synchronises the recorded events and fills, per kernel
+ * name, the launch count and the total milliseconds; names is a host buffer
+ * of max_entries * 64 chars, counts / total_ms host arrays of max_entries.
+ * Returns the number of entries filled.  Not thread-safe. */
+filt_status filt_profile_enable(int on);
+int filt_profile_read(char *names, int32_t *counts, double *total_ms, int max_entries);
+
 /* Text of a status code, and the last error message of the calling thread. */
 const char *filt_strerror(filt_status s);
 const char *filt_last_error(void);

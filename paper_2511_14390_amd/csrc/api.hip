@@ -19,6 +19,42 @@ filt_status fail(filt_status s, const char *fmt, ...)
     return s;
 }
 
+// ------------------------------------------------------------ profiling
+//
+// While enabled, every launch is bracketed by two events from a pool created
+// by filt_profile_enable (host side).  When the pool is exhausted further
+// launches are not recorded.
+struct ProfRec {
+    const char *name;
+    int ev;
+};
+constexpr int kProfEvents = 1 << 14;
+bool g_prof_on = false;
+hipEvent_t g_prof_ev[kProfEvents];
+int g_prof_nev = 0;        // events created
+int g_prof_used = 0;       // events handed out
+ProfRec g_prof_rec[kProfEvents / 2];
+int g_prof_nrec = 0;
+
+int prof_begin(const char *name, hipStream_t st)
+{
+    if (!g_prof_on || g_prof_used + 2 > g_prof_nev)
+        return -1;
+    const int r = g_prof_nrec++;
+    g_prof_rec[r].name = name;
+    g_prof_rec[r].ev = g_prof_used;
+    g_prof_used += 2;
+    hipEventRecord(g_prof_ev[g_prof_rec[r].ev], st);
+    return r;
+}
+
+void prof_end(int slot, hipStream_t st)
+{
+    if (slot < 0)
+        return;
+    hipEventRecord(g_prof_ev[g_prof_rec[slot].ev + 1], st);
+}
+
 filt_status check_launch(const char *what)
 {
     hipError_t e = hipGetLastError();
@@ -276,5 +312,47 @@ const char *filt_strerror(filt_status s)
 }
 
 const char *filt_last_error(void) { return g_err; }
+
+filt_status filt_profile_enable(int on)
+{
+    if (on) {
+        while (g_prof_nev < kProfEvents) {
+            if (hipEventCreate(&g_prof_ev[g_prof_nev]) != hipSuccess)
+                return fail(FILT_EHIP, "hipEventCreate failed");
+            ++g_prof_nev;
+        }
+        g_prof_used = 0;
+        g_prof_nrec = 0;
+    }
+    g_prof_on = on != 0;
+    return FILT_OK;
+}
+
+int filt_profile_read(char *names, int32_t *counts, double *total_ms, int max_entries)
+{
+    int n = 0;
+    for (int r = 0; r < g_prof_nrec; ++r) {
+        float ms = 0.f;
+        if (hipEventSynchronize(g_prof_ev[g_prof_rec[r].ev + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, g_prof_ev[g_prof_rec[r].ev], g_prof_ev[g_prof_rec[r].ev + 1]) !=
+                hipSuccess)
+            continue;
+        int k = 0;
+        while (k < n && strncmp(names + 64 * k, g_prof_rec[r].name, 63) != 0)
+            ++k;
+        if (k == n) {
+            if (n >= max_entries)
+                continue;
+            strncpy(names + 64 * k, g_prof_rec[r].name, 63);
+            names[64 * k + 63] = 0;
+            counts[k] = 0;
+            total_ms[k] = 0.0;
+            ++n;
+        }
+        counts[k] += 1;
+        total_ms[k] += ms;
+    }
+    return n;
+}
 
 }  // extern "C"

@@ -183,11 +183,11 @@ template <int DB>
 filt_status run_carry(const Dims &d, const CarryArgs &a, const void *init, bool init_f64,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL((k_carry_agg<DB>), dim3(grid_for(d.B * d.NB * (a.D + 1))),
+    FILT_LAUNCH("carry_agg", (k_carry_agg<DB>), dim3(grid_for(d.B * d.NB * (a.D + 1))),
                        dim3(kThreads), 0, st, d, a);
-    hipLaunchKernelGGL((k_carry_blocks<DB>), dim3(grid_for(d.B)), dim3(kThreads), 0, st, d, a,
+    FILT_LAUNCH("carry_blocks", (k_carry_blocks<DB>), dim3(grid_for(d.B)), dim3(kThreads), 0, st, d, a,
                        init, (int)init_f64);
-    hipLaunchKernelGGL((k_carry_fill<DB>), dim3(grid_for(d.B * d.NB)), dim3(kThreads), 0, st, d,
+    FILT_LAUNCH("carry_fill", (k_carry_fill<DB>), dim3(grid_for(d.B * d.NB)), dim3(kThreads), 0, st, d,
                        a);
     return check_launch("carry");
 }
@@ -256,7 +256,7 @@ filt_status fir_states_run(const Dims &d, const double *summ, double *states, hi
 {
     if (d.C < 2 || d.M == 0)
         return FILT_OK;
-    hipLaunchKernelGGL(k_fir_states, dim3(grid_for(d.B * (d.C - 1) * d.M)), dim3(kThreads), 0, st,
+    FILT_LAUNCH("fir_states", k_fir_states, dim3(grid_for(d.B * (d.C - 1) * d.M)), dim3(kThreads), 0, st,
                        d, summ, states);
     return check_launch("fir states");
 }
@@ -266,10 +266,10 @@ filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb
 {
     const int64_t n = d.B * (d.N + d.M + 1);
     if (f64)
-        hipLaunchKernelGGL((k_reduce_lti<double>), dim3(grid_for(n)), dim3(kThreads), 0, st, d,
+        FILT_LAUNCH("reduce_lti", (k_reduce_lti<double>), dim3(grid_for(n)), dim3(kThreads), 0, st, d,
                            part, (double *)ga, (double *)gb);
     else
-        hipLaunchKernelGGL((k_reduce_lti<float>), dim3(grid_for(n)), dim3(kThreads), 0, st, d,
+        FILT_LAUNCH("reduce_lti", (k_reduce_lti<float>), dim3(grid_for(n)), dim3(kThreads), 0, st, d,
                            part, (float *)ga, (float *)gb);
     return check_launch("reduce");
 }

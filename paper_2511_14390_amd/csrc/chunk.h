@@ -60,7 +60,9 @@ __device__ __forceinline__ void lti_coef(const Dims &d, const io_t *bc, const io
     ld_coef<W>(d, bc, ac, b, 0, la, lb);
 }
 
-// Phase 1 (forward).  Items (b, c, j): j < N solves chunk c from the unit
+// Phase 1 (forward), always in FP64: the companion-form transition of a chunk
+// has entries far above 1 when poles cluster near the unit circle, so an FP32
+// Phi would lose the digits the carry needs.  Items (b, c, j): j < N solves chunk c from the unit
 // state e_j (column j of Phi_c), j == N solves it from zero state with the
 // real input (s_c).  summ[(b*C + c)*SS + i*N + j] = Phi_c[i][j],
 // summ[(b*C + c)*SS + N*N + i] = s_c[i]; state index i = 0..N-1 is y(t-1-i).
@@ -269,7 +271,7 @@ __device__ __forceinline__ void bwd_chunk(const Dims &d, int64_t b, int64_t t0, 
     }
 }
 
-// Phase 1 (backward).  Items (b, c, j) for chunks c = c_first.. : j < N runs
+// Phase 1 (backward), always in FP64 (see the forward summary).  Items (b, c, j) for chunks c = c_first.. : j < N runs
 // the adjoint over chunk c from the unit state s_{j+1} = 1 (gy = 0), j == N
 // from zero state with the real gy.  The chunk's outgoing (s, r) is written
 // as column j: summ[(b*C+c)*SB + i*N + j] = s_{i+1} (i < N),
@@ -421,15 +423,15 @@ filt_status forward_impl(const Dims &d, const io_t *x, const io_t *bc, const io_
     const int N = d.N;
     if (d.C > 1 && N > 0) {
         const int64_t ncs = d.C - 1;  // chunks with a successor
-        hipLaunchKernelGGL((k_fwd_summary<W, TV, true, io_t, acc_t>), dim3(grid_for(d.B * ncs)),
+        FILT_LAUNCH("fwd_summary_part", (k_fwd_summary<W, TV, true, io_t, double>), dim3(grid_for(d.B * ncs)),
                            dim3(kThreads), 0, st, d, x, xi, bc, ac, (int64_t)0, ncs, N, 1, summ,
                            phi);
         if (TV)
-            hipLaunchKernelGGL((k_fwd_summary<W, TV, false, io_t, acc_t>),
+            FILT_LAUNCH("fwd_summary_homog", (k_fwd_summary<W, TV, false, io_t, double>),
                                dim3(grid_for(d.B * ncs * N)), dim3(kThreads), 0, st, d, x, xi,
                                bc, ac, (int64_t)0, ncs, 0, N, summ, phi);
         else
-            hipLaunchKernelGGL((k_fwd_summary<W, TV, false, io_t, acc_t>),
+            FILT_LAUNCH("fwd_summary_homog", (k_fwd_summary<W, TV, false, io_t, double>),
                                dim3(grid_for(d.B * N)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
                                (int64_t)0, (int64_t)1, 0, N, summ, phi);
         filt_status s = check_launch("forward summary");
@@ -449,7 +451,7 @@ filt_status forward_impl(const Dims &d, const io_t *x, const io_t *bc, const io_
         if (s != FILT_OK)
             return s;
     }
-    hipLaunchKernelGGL((k_fwd_apply<W, TV, io_t, acc_t>), dim3(grid_for(d.B * d.C)),
+    FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, TV, io_t, acc_t>), dim3(grid_for(d.B * d.C)),
                        dim3(kThreads), 0, st, d, x, xi, bc, ac, yi, states, y);
     return check_launch("forward apply");
 }
@@ -468,16 +470,16 @@ filt_status backward_impl(const Dims &d, const io_t *gy, const io_t *x, const io
     const int N = d.N, M = d.M;
     if (d.C > 1 && N + M > 0) {
         const int64_t ncs = d.C - 1;  // chunks 1..C-1 pass a state to an earlier chunk
-        hipLaunchKernelGGL((k_bwd_summary<W, TV, true, io_t, acc_t>), dim3(grid_for(d.B * ncs)),
+        FILT_LAUNCH("bwd_summary_part", (k_bwd_summary<W, TV, true, io_t, double>), dim3(grid_for(d.B * ncs)),
                            dim3(kThreads), 0, st, d, gy, bc, ac, (int64_t)1, ncs, N, 1, summ,
                            phi);
         if (N > 0) {
             if (TV)
-                hipLaunchKernelGGL((k_bwd_summary<W, TV, false, io_t, acc_t>),
+                FILT_LAUNCH("bwd_summary_homog", (k_bwd_summary<W, TV, false, io_t, double>),
                                    dim3(grid_for(d.B * ncs * N)), dim3(kThreads), 0, st, d, gy,
                                    bc, ac, (int64_t)1, ncs, 0, N, summ, phi);
             else
-                hipLaunchKernelGGL((k_bwd_summary<W, TV, false, io_t, acc_t>),
+                FILT_LAUNCH("bwd_summary_homog", (k_bwd_summary<W, TV, false, io_t, double>),
                                    dim3(grid_for(d.B * N)), dim3(kThreads), 0, st, d, gy, bc, ac,
                                    (int64_t)0, (int64_t)1, 0, N, summ, phi);
         }
@@ -506,11 +508,11 @@ filt_status backward_impl(const Dims &d, const io_t *gy, const io_t *x, const io
     }
     const bool coef = (ga != nullptr) || (gb != nullptr);
     if (coef)
-        hipLaunchKernelGGL((k_bwd_apply<W, TV, true, io_t, acc_t>), dim3(grid_for(d.B * d.C)),
+        FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TV, true, io_t, acc_t>), dim3(grid_for(d.B * d.C)),
                            dim3(kThreads), 0, st, d, gy, x, xi, y, yi, bc, ac, states, gx, gb, ga,
                            gxi, gyi, part);
     else
-        hipLaunchKernelGGL((k_bwd_apply<W, TV, false, io_t, acc_t>), dim3(grid_for(d.B * d.C)),
+        FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TV, false, io_t, acc_t>), dim3(grid_for(d.B * d.C)),
                            dim3(kThreads), 0, st, d, gy, x, xi, y, yi, bc, ac, states, gx, gb, ga,
                            gxi, gyi, part);
     filt_status s = check_launch("backward apply");

@@ -40,6 +40,19 @@ namespace filt_detail {
 filt_status fail(filt_status s, const char *fmt, ...);
 filt_status check_launch(const char *what);
 
+// Optional per-kernel timing (filt_profile_*): a HIP event pair recorded on
+// the launch stream around every kernel while enabled; free otherwise.
+int prof_begin(const char *name, hipStream_t st);
+void prof_end(int slot, hipStream_t st);
+
+#define FILT_LAUNCH(NAME, ...)                                                                     \
+    do {                                                                                           \
+        const int filt_prof_slot_ = prof_begin(NAME, FILT_LAUNCH_STREAM_(__VA_ARGS__));            \
+        hipLaunchKernelGGL(__VA_ARGS__);                                                           \
+        prof_end(filt_prof_slot_, FILT_LAUNCH_STREAM_(__VA_ARGS__));                               \
+    } while (0)
+#define FILT_LAUNCH_STREAM_(K, G, B, S, ST, ...) ST
+
 constexpr int kThreads = 256;
 constexpr int kMaxOrder = 16;
 

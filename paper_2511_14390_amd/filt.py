@@ -194,3 +194,28 @@ def filt_backward(gy, x, y, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0
         if v is not None:
             out[k] = v
     return out
+
+
+def profile_enable(on: bool):
+    """Start (True) or stop (False) per-kernel event timing inside the library."""
+    L = lib()
+    L.filt_profile_enable.argtypes = [ctypes.c_int]
+    L.filt_profile_enable.restype = ctypes.c_int
+    _check(L.filt_profile_enable(1 if on else 0))
+
+
+def profile_read(max_entries: int = 64):
+    """{kernel name: (launches, total ms)} of the recorded launches (synchronises)."""
+    L = lib()
+    L.filt_profile_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.filt_profile_read.restype = ctypes.c_int
+    names = ctypes.create_string_buffer(64 * max_entries)
+    counts = (ctypes.c_int32 * max_entries)()
+    ms = (ctypes.c_double * max_entries)()
+    n = L.filt_profile_read(names, counts, ms, max_entries)
+    out = {}
+    for i in range(n):
+        nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[nm] = (int(counts[i]), float(ms[i]))
+    return out
