@@ -35,7 +35,7 @@ def parse():
                     choices=["ltv-allpole-n16", "lti-allpole-n2", "lti-df-m4n4",
                              "lti-allpole-n4-long"])
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--f64-state", action="store_true")
+    ap.add_argument("--f32-state", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
@@ -96,7 +96,7 @@ def main():
 
     def step():
         y = AG.lfilter(x, a, b, xi, yi, layout=p.layout, chunk=args.chunk,
-                       f64_state=args.f64_state)
+                       f32_state=args.f32_state)
         inputs = [v for v in (x, a, b, xi, yi) if v is not None]
         torch.autograd.grad(y, inputs, gy)
 
@@ -154,9 +154,9 @@ def main():
         "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64-state" if args.f64_state else "f32 (chunk transitions f64)",
+        "dtype": "f32-state" if args.f32_state else "f64",
         "data": "synthetic",
-        "config": {"workload": p.name, "B": p.B, "T": p.T, "M": p.M, "N": p.N,
+        "config": {"workload": p.name, "io": "f32", "B": p.B, "T": p.T, "M": p.M, "N": p.N,
                    "time_varying": bool(p.time_varying), "layout": p.layout,
                    "chunk": F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk)),
                    "parallelism": "single GPU"},

@@ -54,8 +54,12 @@ typedef enum {
 
 typedef enum { FILT_LAYOUT_TB = 0, FILT_LAYOUT_BT = 1 } filt_layout;
 
-/* flags */
-#define FILT_F64_STATE 0x1 /* run the recursion in FP64 (I/O stays FP32) */
+/* flags.  By default every recursion runs in FP64 registers (I/O stays
+ * FP32): on gfx950 an FP64 FMA issues at the rate of an unpacked FP32 FMA, and
+ * FP32 state misses the 1e-4 output tolerance on high-order filters whose
+ * poles cluster near the unit circle.  FILT_F32_STATE runs the per-sample
+ * output pass in FP32 instead (the chunk transitions and the carry stay FP64). */
+#define FILT_F32_STATE 0x2
 
 typedef struct {
     int64_t B;            /* channels (>= 0); B == 0 or T == 0 is a no-op */
@@ -64,7 +68,7 @@ typedef struct {
     int32_t N;            /* feedback order: a_1..a_N, 0 <= N <= 16 */
     int32_t time_varying; /* 0: coefficients per channel; 1: per sample */
     int32_t layout;       /* filt_layout of x, y, gy, gx (and per-sample coefficients) */
-    int32_t flags;        /* FILT_F64_STATE */
+    int32_t flags;        /* FILT_F32_STATE or 0 */
     int32_t chunk;        /* time-chunk length for the parallel scan; 0 = automatic,
                              else a multiple of 32 */
 } filt_problem;

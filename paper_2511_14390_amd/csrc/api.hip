@@ -101,7 +101,7 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
     if (p->chunk < 0 || (p->chunk % 32) != 0)
         return fail(FILT_EINVAL, "chunk must be 0 or a positive multiple of 32 (got %d)",
                     p->chunk);
-    if (p->flags & ~FILT_F64_STATE)
+    if (p->flags & ~FILT_F32_STATE)
         return fail(FILT_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->B == 0 || p->T == 0)
         return FILT_OK;
@@ -189,7 +189,7 @@ filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, 
     char *wsa = (char *)(((uintptr_t)ws + 255) & ~uintptr_t(255));
     const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
     hipStream_t st = (hipStream_t)stream;
-    const bool f64 = sizeof(io_t) == 8 || (p->flags & FILT_F64_STATE);
+    const bool f64 = sizeof(io_t) == 8 || !(p->flags & FILT_F32_STATE);
     if (f64)
         return forward_dispatch<io_t, double>(d, W, x, bc, ac, xi, yi, y, wsa, st);
     return forward_dispatch<io_t, float>(d, W, x, bc, ac, xi, yi, y, wsa, st);
@@ -223,7 +223,7 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
     char *wsa = (char *)(((uintptr_t)ws + 255) & ~uintptr_t(255));
     const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
     hipStream_t st = (hipStream_t)stream;
-    const bool f64 = sizeof(io_t) == 8 || (p->flags & FILT_F64_STATE);
+    const bool f64 = sizeof(io_t) == 8 || !(p->flags & FILT_F32_STATE);
     if (f64)
         return backward_dispatch<io_t, double>(d, W, gy, x, y, bc, ac, xi, yi, gx, gb, ga, gxi,
                                                gyi, wsa, st);

@@ -24,13 +24,13 @@ def _dev(v, dev, dtype=torch.float32):
     return None if v is None else torch.from_numpy(np.ascontiguousarray(v)).to(dev, dtype)
 
 
-def run_gpu(p, dev, chunk=0, f64_state=False, dtype=torch.float32,
+def run_gpu(p, dev, chunk=0, f32_state=False, dtype=torch.float32,
             want=("x", "a", "b", "xi", "yi")):
     t = lambda v: _dev(v, dev, dtype)
     x, a, b, xi, yi, gy = map(t, (p.x, p.a, p.b, p.xi, p.yi, p.gy))
-    y = F.filt_forward(x, a, b, xi, yi, layout=p.layout, chunk=chunk, f64_state=f64_state)
+    y = F.filt_forward(x, a, b, xi, yi, layout=p.layout, chunk=chunk, f32_state=f32_state)
     g = F.filt_backward(gy, x, y, a, b, xi, yi, layout=p.layout, chunk=chunk,
-                        f64_state=f64_state, want=want)
+                        f32_state=f32_state, want=want)
     torch.cuda.synchronize()
     return y.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}
 
@@ -91,20 +91,22 @@ def _case(M, N, tv, layout, T):
 
 @pytest.mark.parametrize("M,N,tv,layout,T,chunk", CASES)
 def test_random_problems_several_chunks_ragged_tail(gpu_device, M, N, tv, layout, T, chunk):
+    # default FP64 state with FP32 I/O: only the final FP32 rounding differs
+    # from the oracle, so any algorithmic slip (wrong carry, index or boundary)
+    # shows up well above this tolerance
     p = _case(M, N, tv, layout, T)
     yg, gg = run_gpu(p, gpu_device, chunk=chunk)
     yo, go = run_oracle(p)
-    compare(p, yg, gg, yo, go, label=f"chunk={chunk}")
+    compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6, label=f"chunk={chunk}")
 
 
 @pytest.mark.parametrize("M,N,tv,layout,T,chunk", CASES)
-def test_random_problems_fp64_state_tight(gpu_device, M, N, tv, layout, T, chunk):
-    # FP64 recursion with FP32 I/O: only the final FP32 rounding differs from the
-    # oracle, so any algorithmic slip (wrong carry, index or boundary) shows up
+def test_random_problems_fp32_state(gpu_device, M, N, tv, layout, T, chunk):
+    # opt-in FP32 output pass: the benchmark spec's tolerances on well-conditioned filters
     p = _case(M, N, tv, layout, T)
-    yg, gg = run_gpu(p, gpu_device, chunk=chunk, f64_state=True)
+    yg, gg = run_gpu(p, gpu_device, chunk=chunk, f32_state=True)
     yo, go = run_oracle(p)
-    compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6, label=f"f64state chunk={chunk}")
+    compare(p, yg, gg, yo, go, label=f"f32state chunk={chunk}")
 
 
 @pytest.mark.parametrize("T", [1, 2, 5, 31, 32, 33, 95])
@@ -161,11 +163,18 @@ def test_config3_reduced(gpu_device):
     compare(p, yg, gg, yo, go, label="config3-reduced")
 
 
-def test_config4_reduced_fp64_state(gpu_device):
-    p = W.config4(T=1 << 18)
-    yg, gg = run_gpu(p, gpu_device, f64_state=True, want=("x", "a"))
+def test_config3_full(gpu_device):
+    p = W.config3()
+    yg, gg = run_gpu(p, gpu_device)
     yo, go = run_oracle(p)
-    compare(p, yg, gg, yo, go, label="config4-reduced-f64state")
+    compare(p, yg, gg, yo, go, label="config3")
+
+
+def test_config4_full(gpu_device):
+    p = W.config4()
+    yg, gg = run_gpu(p, gpu_device, want=("x", "a"))
+    yo, go = run_oracle(p)
+    compare(p, yg, gg, yo, go, label="config4")
 
 
 def test_fp64_io_path_matches_oracle_tightly(gpu_device):
