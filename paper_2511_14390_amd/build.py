@@ -34,21 +34,35 @@ BUCKETS = (1, 2, 4, 8, 16, 32)
 TYPES = (("float", "float"), ("float", "double"), ("double", "double"))
 
 
+def _unit(name, header, body):
+    path = os.path.join(BUILD, name)
+    text = f"#define FILT_INSTANTIATING 1\n#include \"{header}\"\nnamespace filt_detail {{ {body} }}\n"
+    if not os.path.exists(path) or open(path).read() != text:
+        with open(path, "w") as f:
+            f.write(text)
+    return path
+
+
 def _instantiation_units():
-    """One generated translation unit per (bucket, type pair, direction):
-    the fully unrolled kernels of the large buckets dominate compile time, so
-    they are spread over as many parallel hipcc processes as possible."""
+    """Generated translation units, one per (bucket, types, direction): the
+    fully unrolled kernels of the large buckets dominate compile time, so they
+    are spread over as many parallel hipcc processes as possible."""
     out = []
     for w in BUCKETS:
+        for io in ("float", "double"):
+            out.append(_unit(f"summary_w{w}_{io}_fwd.hip", "summary.h",
+                             f"template filt_status fwd_summary_w<{w}, {io}>(const Dims &, "
+                             f"const {io} *, const {io} *, const {io} *, const {io} *, double *, "
+                             f"double *, hipStream_t);"))
+            out.append(_unit(f"summary_w{w}_{io}_bwd.hip", "summary.h",
+                             f"template filt_status bwd_summary_w<{w}, {io}>(const Dims &, "
+                             f"const {io} *, const {io} *, const {io} *, double *, double *, "
+                             f"hipStream_t);"))
         for io, acc in TYPES:
-            for dirn, macro in (("fwd", "FILT_DECLARE_FWD"), ("bwd", "FILT_DECLARE_BWD")):
-                path = os.path.join(BUILD, f"chunk_w{w}_{io}_{acc}_{dirn}.hip")
-                text = ("#define FILT_INSTANTIATING 1\n#include \"chunk.h\"\n"
-                        f"namespace filt_detail {{ {macro}({w}, {io}, {acc}, ) }}\n")
-                if not os.path.exists(path) or open(path).read() != text:
-                    with open(path, "w") as f:
-                        f.write(text)
-                out.append(path)
+            out.append(_unit(f"apply_w{w}_{io}_{acc}_fwd.hip", "apply.h",
+                             f"FILT_DECLARE_FWD({w}, {io}, {acc}, )"))
+            out.append(_unit(f"apply_w{w}_{io}_{acc}_bwd.hip", "apply.h",
+                             f"FILT_DECLARE_BWD({w}, {io}, {acc}, )"))
     return out
 
 

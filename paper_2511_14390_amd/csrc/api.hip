@@ -72,12 +72,18 @@ inline int pow2_at_least(int v)
     return w;
 }
 
-int64_t auto_chunk(int64_t B, int64_t T)
+int64_t auto_chunk(const filt_problem *p)
 {
+    const int64_t B = p->B, T = p->T;
     // aim for about 32K (channel, chunk) lanes in the apply phase
     const int64_t target = 32768;
     int64_t per = (target + B - 1) / std::max<int64_t>(B, 1);
     int64_t L = (T + per - 1) / std::max<int64_t>(per, 1);
+    if (p->time_varying) {
+        // every chunk stores an N x N FP64 transition: keep its 8 N^2 / L bytes
+        // per sample well below the 4 (N + M + 1) bytes of coefficients read
+        L = std::max<int64_t>(L, 12 * (int64_t)p->N);
+    }
     L = ((L + 31) / 32) * 32;
     return std::max<int64_t>(32, std::min<int64_t>(L, 1 << 16));
 }
@@ -124,7 +130,7 @@ Dims make_dims(const filt_problem *p, int has_b)
     d.tv = p->time_varying;
     d.layout = p->layout;
     d.has_b = has_b;
-    d.L = p->chunk > 0 ? p->chunk : auto_chunk(p->B, p->T);
+    d.L = p->chunk > 0 ? p->chunk : auto_chunk(p);
     d.C = (d.T + d.L - 1) / d.L;
     const int64_t steps = std::max<int64_t>(d.C - 1, 1);
     int64_t G = 1;
@@ -181,7 +187,9 @@ filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, 
         return FILT_OK;
     if (y == nullptr)
         return fail(FILT_EINVAL, "y is NULL");
-    const Dims d = make_dims(p, bc != nullptr);
+    Dims d = make_dims(p, bc != nullptr);
+    d.a_vec4 = (p->N % 4 == 0) && ((uintptr_t)ac % 16 == 0);
+    d.b_vec4 = ((p->M + 1) % 4 == 0) && ((uintptr_t)bc % 16 == 0);
     const WsPlan w = ws_plan(d);
     if (ws == nullptr || ws_bytes < w.total)
         return fail(FILT_EWORKSPACE, "workspace of %zu bytes needed, %zu given", w.total,
@@ -215,7 +223,9 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
         return fail(FILT_EINVAL, "gb requested but x is NULL");
     if (ga != nullptr && (y == nullptr || p->N == 0))
         return fail(FILT_EINVAL, "ga requested but y is NULL or N == 0");
-    const Dims d = make_dims(p, bc != nullptr);
+    Dims d = make_dims(p, bc != nullptr);
+    d.a_vec4 = (p->N % 4 == 0) && ((uintptr_t)ac % 16 == 0);
+    d.b_vec4 = ((p->M + 1) % 4 == 0) && ((uintptr_t)bc % 16 == 0);
     const WsPlan w = ws_plan(d);
     if (ws == nullptr || ws_bytes < w.total)
         return fail(FILT_EWORKSPACE, "workspace of %zu bytes needed, %zu given", w.total,
@@ -258,7 +268,7 @@ int64_t filt_auto_chunk(const filt_problem *p)
 {
     if (p == nullptr || p->B <= 0 || p->T <= 0)
         return 0;
-    return p->chunk > 0 ? p->chunk : auto_chunk(p->B, p->T);
+    return p->chunk > 0 ? p->chunk : auto_chunk(p);
 }
 
 filt_status filt_forward(const filt_problem *p, const float *x, const float *b, const float *a,

@@ -1,0 +1,406 @@
+// apply.h -- phase 3 of the chunked scan and the per-direction driver.
+//
+// Every (channel, chunk) reruns its chunk from the exact entering state that
+// the carry produced and writes the outputs: the forward writes y; the
+// backward runs the adjoint in transposed form (the backward of a direct
+// form is a transposed direct form run in reverse time, Sec. 3.1 after
+// Eq. 9) and fuses the gradient products of Eqs. 6, 8 and 9: gx, the
+// per-sample (or, for time-invariant filters, per-chunk partial sums of the)
+// coefficient gradients, and the initial-condition gradients from the state
+// left after time 0.
+#pragma once
+
+#include "common.h"
+
+namespace filt_detail {
+
+// ---------------------------------------------------------------- forward
+
+template <int W, bool TV, bool FIR, typename io_t, typename acc_t>
+__global__ void __launch_bounds__(kThreads)
+k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
+            const io_t *__restrict__ bc, const io_t *__restrict__ ac,
+            const io_t *__restrict__ yi, const double *__restrict__ hin, io_t *__restrict__ y)
+{
+    constexpr int m = W - 1;
+    const int64_t total = d.B * d.C;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total)
+        return;
+    int64_t b, c, jj;
+    decode(d, idx, d.C, b, c, jj);
+    const int64_t t0 = c * d.L;
+    acc_t la[W + 1], lb[W];
+    if constexpr (!TV)
+        ld_row<W, FIR>(d, bc, ac, b, 0, la, lb);
+    // y history: hy[t mod W] = y[t]; x history likewise
+    acc_t hy[W], hx[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        hy[q] = acc_t(0);
+        hx[q] = acc_t(0);
+    }
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        if (i < d.N) {
+            acc_t v;
+            if (c == 0)
+                v = (yi != nullptr) ? (acc_t)yi[b * d.N + i] : acc_t(0);
+            else
+                v = (acc_t)hin[(b * d.C + c) * d.N + i];
+            hy[(-(i + 1)) & m] = v;
+        }
+    }
+    if constexpr (FIR) {
+#pragma unroll
+        for (int k = 1; k < W; ++k)
+            hx[(-k) & m] = ld_x<io_t, acc_t>(d, x, xi, b, t0 - k);
+    }
+    const int64_t tend = t0 + d.L;
+    for (int64_t tb = t0; tb < tend; tb += W) {
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            const int64_t t = tb + s;
+            acc_t ca[W + 1], cb[W];
+            if constexpr (TV) {
+                ld_row<W, FIR>(d, bc, ac, b, t, ca, cb);
+            } else {
+#pragma unroll
+                for (int k = 0; k <= W; ++k)
+                    ca[k] = la[k];
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    cb[k] = lb[k];
+            }
+            hx[s & m] = t < d.T ? (acc_t)x[sig_at(d, b, t)] : acc_t(0);
+            acc_t p0 = acc_t(0), p1 = acc_t(0);
+            if constexpr (FIR) {
+#pragma unroll
+                for (int k = W - 1; k >= 0; --k) {
+                    if (k & 1)
+                        p1 += cb[k] * hx[(s - k) & m];
+                    else
+                        p0 += cb[k] * hx[(s - k) & m];
+                }
+            } else {
+                p0 = cb[0] * hx[s & m];
+            }
+            // oldest taps first; the newest output is the last dependency
+#pragma unroll
+            for (int k = W; k >= 2; --k) {
+                if (k & 1)
+                    p1 -= ca[k] * hy[(s - k) & m];
+                else
+                    p0 -= ca[k] * hy[(s - k) & m];
+            }
+            const acc_t v = (p0 + p1) - ca[1] * hy[(s - 1) & m];
+            hy[s & m] = v;
+            if (t < d.T)
+                y[sig_at(d, b, t)] = (io_t)v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- backward
+
+// gin[(b*C + c)*(N+M)] holds the (s, r) state entering chunk c from the
+// future (zero for the last chunk).  Adjoint state slots as in the summary:
+// before processing t, s_k is in ss[(k - t) mod W] and r_k in rs[(k - t) mod W].
+// Per step: ybar = gy[t] + s_1, gx[t] = b_0 ybar + r_1, then the scatter
+// updates; COEF also forms gb_k[t] = ybar x[t-k] and ga_k[t] = -ybar y[t-k]
+// from windows wx[t mod W] = x[t], wy[t mod W] = y[t] that slide down in time.
+// Time-invariant filters write per-(b, c) FP64 partial sums to
+// part[(b*C + c)*(N+M+1)] = (ga_1..ga_N, gb_0..gb_M).  Chunk 0 writes gyi / gxi.
+template <int W, bool TV, bool FIR, bool COEF, typename io_t, typename acc_t>
+__global__ void __launch_bounds__(kThreads)
+k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
+            const io_t *__restrict__ xi, const io_t *__restrict__ y,
+            const io_t *__restrict__ yi, const io_t *__restrict__ bc,
+            const io_t *__restrict__ ac, const double *__restrict__ gin, io_t *__restrict__ gx,
+            io_t *__restrict__ gb, io_t *__restrict__ ga, io_t *__restrict__ gxi,
+            io_t *__restrict__ gyi, double *__restrict__ part)
+{
+    constexpr int m = W - 1;
+    const int64_t total = d.B * d.C;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total)
+        return;
+    int64_t b, c, jj;
+    decode(d, idx, d.C, b, c, jj);
+    const int64_t t0 = c * d.L;
+    const int N = d.N, M = d.M;
+    acc_t la[W + 1], lb[W];
+    if constexpr (!TV)
+        ld_row<W, FIR>(d, bc, ac, b, 0, la, lb);
+    acc_t ss[W], rs[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        ss[q] = acc_t(0);
+        rs[q] = acc_t(0);
+    }
+    if (c + 1 < d.C) {
+        const double *g = gin + (b * d.C + c) * (int64_t)(N + M);
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            if (i < N)
+                ss[(i + 2) & m] = (acc_t)g[i];
+            if (FIR && i < M)
+                rs[(i + 2) & m] = (acc_t)g[N + i];
+        }
+    }
+    double sga[W + 1], sgb[W];
+#pragma unroll
+    for (int k = 0; k <= W; ++k)
+        sga[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        sgb[k] = 0.0;
+    acc_t wx[W], wy[W];
+    const int64_t thi = t0 + d.L - 1;
+    const bool want_gb = COEF && gb != nullptr;
+    const bool want_ga = COEF && ga != nullptr;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        wx[q] = acc_t(0);
+        wy[q] = acc_t(0);
+    }
+    if (want_gb) {
+#pragma unroll
+        for (int k = 0; k < W - 1; ++k)
+            wx[(thi - k) & m] = ld_x<io_t, acc_t>(d, x, xi, b, thi - k);
+    }
+    if (want_ga) {
+#pragma unroll
+        for (int k = 1; k < W; ++k)
+            wy[(thi - k) & m] = ld_y<io_t, acc_t>(d, y, yi, b, thi - k);
+    }
+    for (int64_t tb = t0 + d.L - W; tb >= t0; tb -= W) {
+#pragma unroll
+        for (int s = W - 1; s >= 0; --s) {
+            const int64_t t = tb + s;
+            const bool in = t < d.T;
+            acc_t ca[W + 1], cb[W];
+            if constexpr (TV) {
+                ld_row<W, FIR>(d, bc, ac, b, t, ca, cb);
+            } else {
+#pragma unroll
+                for (int k = 0; k <= W; ++k)
+                    ca[k] = la[k];
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    cb[k] = lb[k];
+            }
+            const acc_t g = in ? (acc_t)gy[sig_at(d, b, t)] : acc_t(0);
+            const acc_t yb = g + ss[(1 - s) & m];
+            if (gx != nullptr && in) {
+                acc_t gxv = cb[0] * yb;
+                if constexpr (FIR)
+                    gxv += rs[(1 - s) & m];
+                gx[sig_at(d, b, t)] = (io_t)gxv;
+            }
+            ss[(1 - s) & m] = -ca[W] * yb;
+#pragma unroll
+            for (int k = 1; k < W; ++k)
+                ss[(k + 1 - s) & m] -= ca[k] * yb;
+            if constexpr (FIR) {
+                rs[(1 - s) & m] = acc_t(0);
+#pragma unroll
+                for (int k = 1; k < W; ++k)
+                    rs[(k + 1 - s) & m] += cb[k] * yb;
+            }
+            if constexpr (COEF) {
+                if (want_gb) {
+                    wx[(s + 1) & m] = ld_x<io_t, acc_t>(d, x, xi, b, t - (W - 1));
+                    if constexpr (TV) {
+                        if (in) {
+                            io_t *o = gb + row_at(d, b, t, M + 1);
+#pragma unroll
+                            for (int k = 0; k < W; ++k)
+                                if (k <= M)
+                                    o[k] = (io_t)(yb * wx[(s - k) & m]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < W; ++k)
+                            sgb[k] += (double)(yb * wx[(s - k) & m]);
+                    }
+                }
+                if (want_ga) {
+                    wy[s & m] = ld_y<io_t, acc_t>(d, y, yi, b, t - W);
+                    if constexpr (TV) {
+                        if (in) {
+                            io_t *o = ga + row_at(d, b, t, N);
+                            if constexpr (sizeof(io_t) == 4 && W % 4 == 0) {
+                                if (d.a_vec4) {
+#pragma unroll
+                                    for (int q = 0; q < W / 4; ++q) {
+                                        if (4 * q < N) {
+                                            float4 v;
+                                            v.x = (float)(-yb * wy[(s - 4 * q - 1) & m]);
+                                            v.y = (float)(-yb * wy[(s - 4 * q - 2) & m]);
+                                            v.z = (float)(-yb * wy[(s - 4 * q - 3) & m]);
+                                            v.w = (float)(-yb * wy[(s - 4 * q - 4) & m]);
+                                            *reinterpret_cast<float4 *>(o + 4 * q) = v;
+                                        }
+                                    }
+                                    continue;
+                                }
+                            }
+#pragma unroll
+                            for (int k = 1; k <= W; ++k)
+                                if (k <= N)
+                                    o[k - 1] = (io_t)(-yb * wy[(s - k) & m]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 1; k <= W; ++k)
+                            sga[k] -= (double)(yb * wy[(s - k) & m]);
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (!TV && COEF) {
+        double *o = part + (b * d.C + c) * (int64_t)(N + M + 1);
+#pragma unroll
+        for (int k = 1; k <= W; ++k)
+            if (k <= N)
+                o[k - 1] = sga[k];
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            if (k <= M)
+                o[N + k] = sgb[k];
+    }
+    if (c == 0) {
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            if (gyi != nullptr && i < N)
+                gyi[b * N + i] = (io_t)ss[(i + 2) & m];
+            if (FIR && gxi != nullptr && i < M)
+                gxi[b * M + i] = (io_t)rs[(i + 2) & m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- drivers
+
+template <int W, bool FIR, typename io_t, typename acc_t>
+filt_status fwd_apply(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
+                      const io_t *xi, const io_t *yi, const double *states, io_t *y,
+                      hipStream_t st)
+{
+    if (d.tv)
+        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, true, FIR, io_t, acc_t>),
+                    dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
+                    states, y);
+    else
+        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, false, FIR, io_t, acc_t>),
+                    dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
+                    states, y);
+    return check_launch("forward apply");
+}
+
+template <int W, typename io_t, typename acc_t>
+filt_status forward_w(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
+                      const io_t *xi, const io_t *yi, io_t *y, char *ws, hipStream_t st)
+{
+    const WsPlan w = ws_plan(d);
+    double *summ = (double *)(ws + w.summ);
+    double *phi = (double *)(ws + w.phi);
+    double *states = (double *)(ws + w.states);
+    const int N = d.N;
+    if (d.C > 1 && N > 0) {
+        filt_status s = fwd_summary_w<W, io_t>(d, x, xi, bc, ac, summ, phi, st);
+        if (s != FILT_OK)
+            return s;
+        CarryArgs a{};
+        a.summ = summ;
+        a.phi = phi;
+        a.SS = (int64_t)N * N + N;
+        a.D = N;
+        a.R = 0;
+        a.bwd = 0;
+        a.agg = (double *)(ws + w.agg);
+        a.bstart = (double *)(ws + w.bstart);
+        a.states = states;
+        s = carry_run(d, a, yi, sizeof(io_t) == 8, st);
+        if (s != FILT_OK)
+            return s;
+    }
+    if (d.M > 0)
+        return fwd_apply<W, true, io_t, acc_t>(d, x, bc, ac, xi, yi, states, y, st);
+    return fwd_apply<W, false, io_t, acc_t>(d, x, bc, ac, xi, yi, states, y, st);
+}
+
+template <int W, bool FIR, typename io_t, typename acc_t>
+filt_status bwd_apply(const Dims &d, const io_t *gy, const io_t *x, const io_t *y,
+                      const io_t *bc, const io_t *ac, const io_t *xi, const io_t *yi,
+                      const double *states, io_t *gx, io_t *gb, io_t *ga, io_t *gxi, io_t *gyi,
+                      double *part, hipStream_t st)
+{
+    const bool coef = (ga != nullptr) || (gb != nullptr);
+#define FILT_BWD_APPLY(TVV, COEFV)                                                                 \
+    FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, COEFV, io_t, acc_t>),                       \
+                dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, gy, x, xi, y, yi, bc, ac,     \
+                states, gx, gb, ga, gxi, gyi, part)
+    if (d.tv) {
+        if (coef)
+            FILT_BWD_APPLY(true, true);
+        else
+            FILT_BWD_APPLY(true, false);
+    } else {
+        if (coef)
+            FILT_BWD_APPLY(false, true);
+        else
+            FILT_BWD_APPLY(false, false);
+    }
+#undef FILT_BWD_APPLY
+    return check_launch("backward apply");
+}
+
+template <int W, typename io_t, typename acc_t>
+filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t *y,
+                       const io_t *bc, const io_t *ac, const io_t *xi, const io_t *yi, io_t *gx,
+                       io_t *gb, io_t *ga, io_t *gxi, io_t *gyi, char *ws, hipStream_t st)
+{
+    const WsPlan w = ws_plan(d);
+    double *summ = (double *)(ws + w.summ);
+    double *phi = (double *)(ws + w.phi);
+    double *states = (double *)(ws + w.states);
+    double *part = (double *)(ws + w.part);
+    const int N = d.N, M = d.M;
+    if (d.C > 1 && N + M > 0) {
+        filt_status s = bwd_summary_w<W, io_t>(d, gy, bc, ac, summ, phi, st);
+        if (s != FILT_OK)
+            return s;
+        if (N > 0) {
+            CarryArgs a{};
+            a.summ = summ;
+            a.phi = phi;
+            a.SS = (int64_t)(N + 1) * (N + M);
+            a.D = N;
+            a.R = M;
+            a.bwd = 1;
+            a.agg = (double *)(ws + w.agg);
+            a.bstart = (double *)(ws + w.bstart);
+            a.states = states;
+            s = carry_run(d, a, nullptr, false, st);
+        } else {
+            s = fir_states_run(d, summ, states, st);
+        }
+        if (s != FILT_OK)
+            return s;
+    }
+    filt_status s = (M > 0) ? bwd_apply<W, true, io_t, acc_t>(d, gy, x, y, bc, ac, xi, yi, states,
+                                                              gx, gb, ga, gxi, gyi, part, st)
+                            : bwd_apply<W, false, io_t, acc_t>(d, gy, x, y, bc, ac, xi, yi,
+                                                               states, gx, gb, ga, gxi, gyi, part,
+                                                               st);
+    if (s != FILT_OK)
+        return s;
+    if (!d.tv && (ga != nullptr || gb != nullptr))
+        s = reduce_lti_run(d, part, ga, gb, sizeof(io_t) == 8, st);
+    return s;
+}
+
+}  // namespace filt_detail

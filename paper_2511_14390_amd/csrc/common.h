@@ -64,6 +64,8 @@ struct Dims {
     int has_b;
     int64_t L, C;   // chunk length (multiple of 32) and number of chunks
     int64_t G, NB;  // carry: steps per block and number of blocks
+    int a_vec4;     // a rows can be read as aligned float4 (N % 4 == 0, 16-B aligned)
+    int b_vec4;     // same for b rows (M + 1 taps)
 };
 
 __device__ __forceinline__ int64_t sig_at(const Dims &d, int64_t b, int64_t t)
@@ -100,27 +102,93 @@ __device__ __forceinline__ acc_t ld_y(const Dims &d, const io_t *y, const io_t *
     return (yi != nullptr && j <= d.N) ? (acc_t)yi[b * d.N + (j - 1)] : acc_t(0);
 }
 
-// Coefficients of one time step: ca[k] = a_k (k = 1..W, 0 beyond N),
-// cb[k] = b_k (k = 0..W-1, 0 beyond M).  Rows past T read as zero.
-template <int W, typename io_t, typename acc_t>
-__device__ __forceinline__ void ld_coef(const Dims &d, const io_t *bc, const io_t *ac, int64_t b,
-                                        int64_t t, acc_t (&ca)[W + 1], acc_t (&cb)[W])
+// Coefficients of time step t: ca[k] = a_k (k = 1..W, 0 beyond N), cb[k] = b_k
+// (k = 0..W-1, 0 beyond M; b = [1] when no b is given).  Rows past T read as
+// zero.  FIR: the filter has feed-forward taps beyond b_0 (M > 0).  Rows are
+// fetched as float4 when their length is a multiple of 4 and they are aligned.
+template <int W, bool FIR, typename io_t, typename acc_t>
+__device__ __forceinline__ void ld_row(const Dims &d, const io_t *bc, const io_t *ac, int64_t b,
+                                       int64_t t, acc_t (&ca)[W + 1], acc_t (&cb)[W])
 {
     const bool in = t < d.T;
-    const io_t *ar = ac + (d.N > 0 ? row_at(d, b, t, d.N) : 0);
 #pragma unroll
-    for (int k = 1; k <= W; ++k)
-        ca[k] = (in && k <= d.N) ? (acc_t)ar[k - 1] : acc_t(0);
-    ca[0] = acc_t(0);
-    if (d.has_b) {
-        const io_t *br = bc + row_at(d, b, t, d.M + 1);
+    for (int k = 0; k <= W; ++k)
+        ca[k] = acc_t(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        cb[k] = acc_t(0);
+    if (!in)
+        return;
+    if (d.N > 0) {
+        const io_t *ar = ac + row_at(d, b, t, d.N);
+        if constexpr (sizeof(io_t) == 4 && W % 4 == 0) {
+            if (d.a_vec4) {
+#pragma unroll
+                for (int q = 0; q < W / 4; ++q) {
+                    if (4 * q < d.N) {
+                        const float4 v = *reinterpret_cast<const float4 *>(ar + 4 * q);
+                        ca[4 * q + 1] = (acc_t)v.x;
+                        ca[4 * q + 2] = (acc_t)v.y;
+                        ca[4 * q + 3] = (acc_t)v.z;
+                        ca[4 * q + 4] = (acc_t)v.w;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 1; k <= W; ++k)
+                    if (k <= d.N)
+                        ca[k] = (acc_t)ar[k - 1];
+            }
+        } else {
+#pragma unroll
+            for (int k = 1; k <= W; ++k)
+                if (k <= d.N)
+                    ca[k] = (acc_t)ar[k - 1];
+        }
+    }
+    if (!d.has_b) {
+        cb[0] = acc_t(1);
+        return;
+    }
+    const io_t *br = bc + row_at(d, b, t, d.M + 1);
+    if constexpr (FIR) {
+        if constexpr (sizeof(io_t) == 4 && W % 4 == 0) {
+            if (d.b_vec4) {
+#pragma unroll
+                for (int q = 0; q < W / 4; ++q) {
+                    if (4 * q <= d.M) {
+                        const float4 v = *reinterpret_cast<const float4 *>(br + 4 * q);
+                        cb[4 * q + 0] = (acc_t)v.x;
+                        cb[4 * q + 1] = (acc_t)v.y;
+                        cb[4 * q + 2] = (acc_t)v.z;
+                        cb[4 * q + 3] = (acc_t)v.w;
+                    }
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < W; ++k)
-            cb[k] = (in && k <= d.M) ? (acc_t)br[k] : acc_t(0);
+            if (k <= d.M)
+                cb[k] = (acc_t)br[k];
     } else {
-#pragma unroll
-        for (int k = 0; k < W; ++k)
-            cb[k] = (in && k == 0) ? acc_t(1) : acc_t(0);
+        cb[0] = (acc_t)br[0];
+    }
+}
+
+// Decode a flat item index into (lane-in-chunk r, channel, chunk) with the
+// nl lanes of a chunk adjacent, then channels (TB) or chunks (BT) fastest.
+__device__ __forceinline__ void decode_lanes(const Dims &d, int64_t idx, int64_t ncs, int nl,
+                                             int64_t &b, int64_t &c, int &r)
+{
+    r = (int)(idx % nl);
+    const int64_t q = idx / nl;
+    if (d.layout == FILT_LAYOUT_TB) {
+        b = q % d.B;
+        c = q / d.B;
+    } else {
+        c = q % ncs;
+        b = q / ncs;
     }
 }
 
@@ -205,7 +273,23 @@ filt_status fir_states_run(const Dims &d, const double *summ, double *states, hi
 filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb, bool f64,
                            hipStream_t st);
 
-// chunk_w*.hip: one translation unit per register bucket W
+// Solves per lane in the per-sample chunk summaries: the lanes of one chunk
+// share every coefficient row among their solves.
+template <int W>
+struct SummarySlots {
+    static constexpr int value = W == 1 ? 2 : (W == 2 ? 3 : 5);
+};
+
+// summary.h: chunk summaries, one translation unit per (bucket, I/O type,
+// direction).  They write summ/phi (see the kernels).
+template <int W, typename io_t>
+filt_status fwd_summary_w(const Dims &d, const io_t *x, const io_t *xi, const io_t *bc,
+                          const io_t *ac, double *summ, double *phi, hipStream_t st);
+template <int W, typename io_t>
+filt_status bwd_summary_w(const Dims &d, const io_t *gy, const io_t *bc, const io_t *ac,
+                          double *summ, double *phi, hipStream_t st);
+
+// apply.h: whole forward / backward for one bucket and type pair.
 template <int W, typename io_t, typename acc_t>
 filt_status forward_w(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
                       const io_t *xi, const io_t *yi, io_t *y, char *ws, hipStream_t st);
@@ -214,6 +298,12 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
                        const io_t *bc, const io_t *ac, const io_t *xi, const io_t *yi, io_t *gx,
                        io_t *gb, io_t *ga, io_t *gxi, io_t *gyi, char *ws, hipStream_t st);
 
+#define FILT_DECLARE_SUMMARY(W, IO, EXT)                                                           \
+    EXT template filt_status fwd_summary_w<W, IO>(const Dims &, const IO *, const IO *,            \
+                                                  const IO *, const IO *, double *, double *,      \
+                                                  hipStream_t);                                    \
+    EXT template filt_status bwd_summary_w<W, IO>(const Dims &, const IO *, const IO *,            \
+                                                  const IO *, double *, double *, hipStream_t);
 #define FILT_DECLARE_FWD(W, IO, ACC, EXT)                                                          \
     EXT template filt_status forward_w<W, IO, ACC>(const Dims &, const IO *, const IO *,           \
                                                    const IO *, const IO *, const IO *, IO *,       \
@@ -222,15 +312,18 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
     EXT template filt_status backward_w<W, IO, ACC>(                                               \
         const Dims &, const IO *, const IO *, const IO *, const IO *, const IO *, const IO *,      \
         const IO *, IO *, IO *, IO *, IO *, IO *, char *, hipStream_t);
-#define FILT_DECLARE_W(W, IO, ACC, EXT) FILT_DECLARE_FWD(W, IO, ACC, EXT) FILT_DECLARE_BWD(W, IO, ACC, EXT)
 #define FILT_DECLARE_BUCKET(W, EXT)                                                                \
-    FILT_DECLARE_W(W, float, float, EXT)                                                           \
-    FILT_DECLARE_W(W, float, double, EXT)                                                          \
-    FILT_DECLARE_W(W, double, double, EXT)
+    FILT_DECLARE_SUMMARY(W, float, EXT)                                                            \
+    FILT_DECLARE_SUMMARY(W, double, EXT)                                                           \
+    FILT_DECLARE_FWD(W, float, float, EXT)                                                         \
+    FILT_DECLARE_BWD(W, float, float, EXT)                                                         \
+    FILT_DECLARE_FWD(W, float, double, EXT)                                                        \
+    FILT_DECLARE_BWD(W, float, double, EXT)                                                        \
+    FILT_DECLARE_FWD(W, double, double, EXT)                                                       \
+    FILT_DECLARE_BWD(W, double, double, EXT)
 
-// The explicit instantiations live in generated translation units (one per
-// bucket, type pair and direction, see build.py); every other unit sees them
-// as extern.
+// The explicit instantiations live in generated translation units (see
+// build.py); every other unit sees them as extern.
 #ifndef FILT_INSTANTIATING
 FILT_DECLARE_BUCKET(1, extern)
 FILT_DECLARE_BUCKET(2, extern)
