@@ -63,10 +63,8 @@ def kernel_bytes(p, name):
         # the per-sample coefficient gradients
         "bwd_apply": 4 + 4 + fir + 4 + 2 * coef,
         # chunk summaries read their phase's inputs once
-        "fwd_summary_part": 4 + coef,
-        "fwd_summary_homog": coef,
-        "bwd_summary_part": 4 + coef,
-        "bwd_summary_homog": coef,
+        "fwd_summary": 4 + coef,
+        "bwd_summary": 4 + coef,
     }
     return table.get(name)
 

@@ -188,8 +188,12 @@ filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, 
     if (y == nullptr)
         return fail(FILT_EINVAL, "y is NULL");
     Dims d = make_dims(p, bc != nullptr);
-    d.a_vec4 = (p->N % 4 == 0) && ((uintptr_t)ac % 16 == 0);
-    d.b_vec4 = ((p->M + 1) % 4 == 0) && ((uintptr_t)bc % 16 == 0);
+    {
+        const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
+        const size_t vec = W >= 4 ? 16 : (size_t)W * sizeof(*ac);
+        d.a_vec = (p->N == W) && ((uintptr_t)ac % vec == 0);
+        d.ga_vec = 0;
+    }
     const WsPlan w = ws_plan(d);
     if (ws == nullptr || ws_bytes < w.total)
         return fail(FILT_EWORKSPACE, "workspace of %zu bytes needed, %zu given", w.total,
@@ -197,10 +201,12 @@ filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, 
     char *wsa = (char *)(((uintptr_t)ws + 255) & ~uintptr_t(255));
     const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
     hipStream_t st = (hipStream_t)stream;
+    // without b the kernels read b_0 = 1 but still need a valid address
+    const io_t *bvalid = bc != nullptr ? bc : (ac != nullptr ? ac : x);
     const bool f64 = sizeof(io_t) == 8 || !(p->flags & FILT_F32_STATE);
     if (f64)
-        return forward_dispatch<io_t, double>(d, W, x, bc, ac, xi, yi, y, wsa, st);
-    return forward_dispatch<io_t, float>(d, W, x, bc, ac, xi, yi, y, wsa, st);
+        return forward_dispatch<io_t, double>(d, W, x, bvalid, ac, xi, yi, y, wsa, st);
+    return forward_dispatch<io_t, float>(d, W, x, bvalid, ac, xi, yi, y, wsa, st);
 }
 
 template <typename io_t>
@@ -224,8 +230,12 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
     if (ga != nullptr && (y == nullptr || p->N == 0))
         return fail(FILT_EINVAL, "ga requested but y is NULL or N == 0");
     Dims d = make_dims(p, bc != nullptr);
-    d.a_vec4 = (p->N % 4 == 0) && ((uintptr_t)ac % 16 == 0);
-    d.b_vec4 = ((p->M + 1) % 4 == 0) && ((uintptr_t)bc % 16 == 0);
+    {
+        const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
+        const size_t vec = W >= 4 ? 16 : (size_t)W * sizeof(*ac);
+        d.a_vec = (p->N == W) && ((uintptr_t)ac % vec == 0);
+        d.ga_vec = d.a_vec && ((uintptr_t)ga % vec == 0);
+    }
     const WsPlan w = ws_plan(d);
     if (ws == nullptr || ws_bytes < w.total)
         return fail(FILT_EWORKSPACE, "workspace of %zu bytes needed, %zu given", w.total,
@@ -233,11 +243,13 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
     char *wsa = (char *)(((uintptr_t)ws + 255) & ~uintptr_t(255));
     const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
     hipStream_t st = (hipStream_t)stream;
+    // without b the kernels read b_0 = 1 but still need a valid address
+    const io_t *bvalid = bc != nullptr ? bc : (ac != nullptr ? ac : gy);
     const bool f64 = sizeof(io_t) == 8 || !(p->flags & FILT_F32_STATE);
     if (f64)
-        return backward_dispatch<io_t, double>(d, W, gy, x, y, bc, ac, xi, yi, gx, gb, ga, gxi,
+        return backward_dispatch<io_t, double>(d, W, gy, x, y, bvalid, ac, xi, yi, gx, gb, ga, gxi,
                                                gyi, wsa, st);
-    return backward_dispatch<io_t, float>(d, W, gy, x, y, bc, ac, xi, yi, gx, gb, ga, gxi, gyi,
+    return backward_dispatch<io_t, float>(d, W, gy, x, y, bvalid, ac, xi, yi, gx, gb, ga, gxi, gyi,
                                           wsa, st);
 }
 

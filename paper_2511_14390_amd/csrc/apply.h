@@ -16,7 +16,7 @@ namespace filt_detail {
 
 // ---------------------------------------------------------------- forward
 
-template <int W, bool TV, bool FIR, typename io_t, typename acc_t>
+template <int W, bool TV, bool FIR, bool AV, typename io_t, typename acc_t>
 __global__ void __launch_bounds__(kThreads)
 k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
             const io_t *__restrict__ bc, const io_t *__restrict__ ac,
@@ -32,7 +32,12 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
     const int64_t t0 = c * d.L;
     acc_t la[W + 1], lb[W];
     if constexpr (!TV)
-        ld_row<W, FIR>(d, bc, ac, b, 0, la, lb);
+        ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
+    const Cursor<io_t> xc = cursor(d, x, b, t0, 1);
+    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
+    io_t *yrow = y + sig_at(d, b, t0);
+    const int64_t ystride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
     // y history: hy[t mod W] = y[t]; x history likewise
     acc_t hy[W], hx[W];
 #pragma unroll
@@ -57,13 +62,25 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
             hx[(-k) & m] = ld_x<io_t, acc_t>(d, x, xi, b, t0 - k);
     }
     const int64_t tend = t0 + d.L;
+    using PF = Prefetch<W, TV, FIR, io_t>;
+    auto fetch = [&](int64_t t, PF &p) {
+        if constexpr (TV)
+            ld_raw<W, FIR, AV>(d, acur.at(t0, t), bcur.at(t0, t), p.ra, p.rb);
+        p.s0 = *xc.at(t0, t);  // outputs past T are not written
+    };
+    PF n1, n2;
+    fetch(t0, n1);
+    fetch(t0 + 1, n2);
     for (int64_t tb = t0; tb < tend; tb += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
             const int64_t t = tb + s;
+            const PF cur = n1;
+            n1 = n2;
+            fetch(t + 2, n2);
             acc_t ca[W + 1], cb[W];
             if constexpr (TV) {
-                ld_row<W, FIR>(d, bc, ac, b, t, ca, cb);
+                cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
             } else {
 #pragma unroll
                 for (int k = 0; k <= W; ++k)
@@ -72,7 +89,7 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
                 for (int k = 0; k < W; ++k)
                     cb[k] = lb[k];
             }
-            hx[s & m] = t < d.T ? (acc_t)x[sig_at(d, b, t)] : acc_t(0);
+            hx[s & m] = (acc_t)cur.s0;
             acc_t p0 = acc_t(0), p1 = acc_t(0);
             if constexpr (FIR) {
 #pragma unroll
@@ -96,7 +113,8 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
             const acc_t v = (p0 + p1) - ca[1] * hy[(s - 1) & m];
             hy[s & m] = v;
             if (t < d.T)
-                y[sig_at(d, b, t)] = (io_t)v;
+                yrow[(t - t0) * ystride] = (io_t)v;
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -111,7 +129,7 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
 // from windows wx[t mod W] = x[t], wy[t mod W] = y[t] that slide down in time.
 // Time-invariant filters write per-(b, c) FP64 partial sums to
 // part[(b*C + c)*(N+M+1)] = (ga_1..ga_N, gb_0..gb_M).  Chunk 0 writes gyi / gxi.
-template <int W, bool TV, bool FIR, bool COEF, typename io_t, typename acc_t>
+template <int W, bool TV, bool FIR, bool COEF, bool AV, typename io_t, typename acc_t>
 __global__ void __launch_bounds__(kThreads)
 k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
             const io_t *__restrict__ xi, const io_t *__restrict__ y,
@@ -131,7 +149,12 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
     const int N = d.N, M = d.M;
     acc_t la[W + 1], lb[W];
     if constexpr (!TV)
-        ld_row<W, FIR>(d, bc, ac, b, 0, la, lb);
+        ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
+    const Cursor<io_t> gc = cursor(d, gy, b, t0, 1);
+    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
+    const int64_t sstride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
+    io_t *gxrow = gx != nullptr ? gx + sig_at(d, b, t0) : nullptr;
     acc_t ss[W], rs[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) {
@@ -174,14 +197,29 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
         for (int k = 1; k < W; ++k)
             wy[(thi - k) & m] = ld_y<io_t, acc_t>(d, y, yi, b, thi - k);
     }
+    using PF = Prefetch<W, TV, FIR, io_t>;
+    auto fetch = [&](int64_t t, PF &p) {
+        if constexpr (TV)
+            ld_raw<W, FIR, AV>(d, acur.at(t0, t), bcur.at(t0, t), p.ra, p.rb);
+        const io_t g = *gc.at(t0, t);
+        p.s0 = t < d.T ? g : io_t(0);
+        p.s1 = want_gb ? ld_x<io_t, io_t>(d, x, xi, b, t - (W - 1)) : io_t(0);
+        p.s2 = want_ga ? ld_y<io_t, io_t>(d, y, yi, b, t - W) : io_t(0);
+    };
+    PF n1, n2;
+    fetch(thi, n1);
+    fetch(thi - 1, n2);
     for (int64_t tb = t0 + d.L - W; tb >= t0; tb -= W) {
 #pragma unroll
         for (int s = W - 1; s >= 0; --s) {
             const int64_t t = tb + s;
             const bool in = t < d.T;
+            const PF cur = n1;
+            n1 = n2;
+            fetch(t - 2, n2);
             acc_t ca[W + 1], cb[W];
             if constexpr (TV) {
-                ld_row<W, FIR>(d, bc, ac, b, t, ca, cb);
+                cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
             } else {
 #pragma unroll
                 for (int k = 0; k <= W; ++k)
@@ -190,13 +228,12 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                 for (int k = 0; k < W; ++k)
                     cb[k] = lb[k];
             }
-            const acc_t g = in ? (acc_t)gy[sig_at(d, b, t)] : acc_t(0);
-            const acc_t yb = g + ss[(1 - s) & m];
-            if (gx != nullptr && in) {
+            const acc_t yb = (acc_t)cur.s0 + ss[(1 - s) & m];
+            if (gxrow != nullptr && in) {
                 acc_t gxv = cb[0] * yb;
                 if constexpr (FIR)
                     gxv += rs[(1 - s) & m];
-                gx[sig_at(d, b, t)] = (io_t)gxv;
+                gxrow[(t - t0) * sstride] = (io_t)gxv;
             }
             ss[(1 - s) & m] = -ca[W] * yb;
 #pragma unroll
@@ -210,7 +247,7 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
             }
             if constexpr (COEF) {
                 if (want_gb) {
-                    wx[(s + 1) & m] = ld_x<io_t, acc_t>(d, x, xi, b, t - (W - 1));
+                    wx[(s + 1) & m] = (acc_t)cur.s1;
                     if constexpr (TV) {
                         if (in) {
                             io_t *o = gb + row_at(d, b, t, M + 1);
@@ -226,12 +263,13 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                     }
                 }
                 if (want_ga) {
-                    wy[s & m] = ld_y<io_t, acc_t>(d, y, yi, b, t - W);
+                    wy[s & m] = (acc_t)cur.s2;
                     if constexpr (TV) {
                         if (in) {
                             io_t *o = ga + row_at(d, b, t, N);
-                            if constexpr (sizeof(io_t) == 4 && W % 4 == 0) {
-                                if (d.a_vec4) {
+                            bool done = false;
+                            if constexpr (AV && sizeof(io_t) == 4 && W % 4 == 0) {
+                                if (d.ga_vec) {
 #pragma unroll
                                     for (int q = 0; q < W / 4; ++q) {
                                         if (4 * q < N) {
@@ -243,13 +281,15 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                                             *reinterpret_cast<float4 *>(o + 4 * q) = v;
                                         }
                                     }
-                                    continue;
+                                    done = true;
                                 }
                             }
+                            if (!done) {
 #pragma unroll
-                            for (int k = 1; k <= W; ++k)
-                                if (k <= N)
-                                    o[k - 1] = (io_t)(-yb * wy[(s - k) & m]);
+                                for (int k = 1; k <= W; ++k)
+                                    if (k <= N)
+                                        o[k - 1] = (io_t)(-yb * wy[(s - k) & m]);
+                            }
                         }
                     } else {
 #pragma unroll
@@ -258,6 +298,7 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                     }
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     if constexpr (!TV && COEF) {
@@ -289,12 +330,16 @@ filt_status fwd_apply(const Dims &d, const io_t *x, const io_t *bc, const io_t *
                       const io_t *xi, const io_t *yi, const double *states, io_t *y,
                       hipStream_t st)
 {
-    if (d.tv)
-        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, true, FIR, io_t, acc_t>),
+    if (d.tv && d.a_vec)
+        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, true, FIR, true, io_t, acc_t>),
+                    dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
+                    states, y);
+    else if (d.tv)
+        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, true, FIR, false, io_t, acc_t>),
                     dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
                     states, y);
     else
-        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, false, FIR, io_t, acc_t>),
+        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, false, FIR, false, io_t, acc_t>),
                     dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
                     states, y);
     return check_launch("forward apply");
@@ -339,20 +384,25 @@ filt_status bwd_apply(const Dims &d, const io_t *gy, const io_t *x, const io_t *
                       double *part, hipStream_t st)
 {
     const bool coef = (ga != nullptr) || (gb != nullptr);
-#define FILT_BWD_APPLY(TVV, COEFV)                                                                 \
-    FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, COEFV, io_t, acc_t>),                       \
+#define FILT_BWD_APPLY(TVV, COEFV, AVV)                                                            \
+    FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, COEFV, AVV, io_t, acc_t>),                  \
                 dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, gy, x, xi, y, yi, bc, ac,     \
                 states, gx, gb, ga, gxi, gyi, part)
-    if (d.tv) {
+    if (d.tv && d.a_vec) {
         if (coef)
-            FILT_BWD_APPLY(true, true);
+            FILT_BWD_APPLY(true, true, true);
         else
-            FILT_BWD_APPLY(true, false);
+            FILT_BWD_APPLY(true, false, true);
+    } else if (d.tv) {
+        if (coef)
+            FILT_BWD_APPLY(true, true, false);
+        else
+            FILT_BWD_APPLY(true, false, false);
     } else {
         if (coef)
-            FILT_BWD_APPLY(false, true);
+            FILT_BWD_APPLY(false, true, false);
         else
-            FILT_BWD_APPLY(false, false);
+            FILT_BWD_APPLY(false, false, false);
     }
 #undef FILT_BWD_APPLY
     return check_launch("backward apply");

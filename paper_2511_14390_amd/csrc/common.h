@@ -64,8 +64,8 @@ struct Dims {
     int has_b;
     int64_t L, C;   // chunk length (multiple of 32) and number of chunks
     int64_t G, NB;  // carry: steps per block and number of blocks
-    int a_vec4;     // a rows can be read as aligned float4 (N % 4 == 0, 16-B aligned)
-    int b_vec4;     // same for b rows (M + 1 taps)
+    int a_vec;      // a rows are exactly W wide and vector-aligned (full-row loads)
+    int ga_vec;     // same for the per-sample ga rows written by the backward
 };
 
 __device__ __forceinline__ int64_t sig_at(const Dims &d, int64_t b, int64_t t)
@@ -102,79 +102,121 @@ __device__ __forceinline__ acc_t ld_y(const Dims &d, const io_t *y, const io_t *
     return (yi != nullptr && j <= d.N) ? (acc_t)yi[b * d.N + (j - 1)] : acc_t(0);
 }
 
-// Coefficients of time step t: ca[k] = a_k (k = 1..W, 0 beyond N), cb[k] = b_k
-// (k = 0..W-1, 0 beyond M; b = [1] when no b is given).  Rows past T read as
-// zero.  FIR: the filter has feed-forward taps beyond b_0 (M > 0).  Rows are
-// fetched as float4 when their length is a multiple of 4 and they are aligned.
-template <int W, bool FIR, typename io_t, typename acc_t>
-__device__ __forceinline__ void ld_row(const Dims &d, const io_t *bc, const io_t *ac, int64_t b,
-                                       int64_t t, acc_t (&ca)[W + 1], acc_t (&cb)[W])
+// Walks one per-(channel) sequence -- a signal or a coefficient row -- in
+// time from chunk start t0: at(t) is the element (row start) of time t, with
+// t - t0 clamped into [lo, hi] so every address stays inside [0, T-1].  Steps
+// fetched past the end of a signal are only ever used with zero input and
+// zero state, or not at all.  One multiply-add per access, no layout branch.
+template <typename T>
+struct Cursor {
+    const T *p0;     // element of time t0
+    int64_t stride;  // elements per time step
+    int lo, hi;      // clamp of t - t0
+
+    __device__ __forceinline__ const T *at(int64_t t0, int64_t t) const
+    {
+        int r = (int)(t - t0);
+        r = r < lo ? lo : (r > hi ? hi : r);
+        return p0 + (int64_t)r * stride;
+    }
+};
+
+// Cursor over a signal [layout] (K = 1) or over per-sample rows of K taps.
+template <typename T>
+__device__ __forceinline__ Cursor<T> cursor(const Dims &d, const T *base, int64_t b, int64_t t0,
+                                            int K)
 {
-    const bool in = t < d.T;
-#pragma unroll
-    for (int k = 0; k <= W; ++k)
-        ca[k] = acc_t(0);
-#pragma unroll
-    for (int k = 0; k < W; ++k)
-        cb[k] = acc_t(0);
-    if (!in)
-        return;
-    if (d.N > 0) {
-        const io_t *ar = ac + row_at(d, b, t, d.N);
+    Cursor<T> c;
+    c.p0 = base + (d.layout == FILT_LAYOUT_TB ? t0 * d.B + b : b * d.T + t0) * (int64_t)K;
+    c.stride = (d.layout == FILT_LAYOUT_TB ? d.B : 1) * (int64_t)K;
+    const int64_t lo = -t0 < -4 ? -4 : -t0;
+    const int64_t hi = d.T - 1 - t0 > d.L + 4 ? d.L + 4 : d.T - 1 - t0;
+    c.lo = (int)lo;
+    c.hi = (int)hi;
+    return c;
+}
+
+// Raw (unconverted) coefficient row: ra[k-1] = a_k (k = 1..W, 0 beyond N),
+// rb[k] = b_k (k = 0.., 0 beyond M; b = [1] when no b is given).  FIR: the
+// filter has feed-forward taps beyond b_0 (M > 0).  AV: the a rows are
+// exactly W wide and aligned, read as whole vectors with no per-tap checks.
+// br must be a valid address even without b (then only b_0 = 1 is used).
+template <int W, bool FIR>
+constexpr int kRawB = FIR ? W : 1;
+
+template <int W, bool FIR, bool AV, typename io_t>
+__device__ __forceinline__ void ld_raw(const Dims &d, const io_t *ar, const io_t *br,
+                                       io_t (&ra)[W], io_t (&rb)[kRawB<W, FIR>])
+{
+    if constexpr (AV) {
         if constexpr (sizeof(io_t) == 4 && W % 4 == 0) {
-            if (d.a_vec4) {
 #pragma unroll
-                for (int q = 0; q < W / 4; ++q) {
-                    if (4 * q < d.N) {
-                        const float4 v = *reinterpret_cast<const float4 *>(ar + 4 * q);
-                        ca[4 * q + 1] = (acc_t)v.x;
-                        ca[4 * q + 2] = (acc_t)v.y;
-                        ca[4 * q + 3] = (acc_t)v.z;
-                        ca[4 * q + 4] = (acc_t)v.w;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int k = 1; k <= W; ++k)
-                    if (k <= d.N)
-                        ca[k] = (acc_t)ar[k - 1];
+            for (int q = 0; q < W / 4; ++q) {
+                const float4 v = *reinterpret_cast<const float4 *>(ar + 4 * q);
+                ra[4 * q + 0] = v.x;
+                ra[4 * q + 1] = v.y;
+                ra[4 * q + 2] = v.z;
+                ra[4 * q + 3] = v.w;
             }
+        } else if constexpr (sizeof(io_t) == 4 && W == 2) {
+            const float2 v = *reinterpret_cast<const float2 *>(ar);
+            ra[0] = v.x;
+            ra[1] = v.y;
         } else {
 #pragma unroll
-            for (int k = 1; k <= W; ++k)
-                if (k <= d.N)
-                    ca[k] = (acc_t)ar[k - 1];
+            for (int k = 0; k < W; ++k)
+                ra[k] = ar[k];
         }
-    }
-    if (!d.has_b) {
-        cb[0] = acc_t(1);
-        return;
-    }
-    const io_t *br = bc + row_at(d, b, t, d.M + 1);
-    if constexpr (FIR) {
-        if constexpr (sizeof(io_t) == 4 && W % 4 == 0) {
-            if (d.b_vec4) {
-#pragma unroll
-                for (int q = 0; q < W / 4; ++q) {
-                    if (4 * q <= d.M) {
-                        const float4 v = *reinterpret_cast<const float4 *>(br + 4 * q);
-                        cb[4 * q + 0] = (acc_t)v.x;
-                        cb[4 * q + 1] = (acc_t)v.y;
-                        cb[4 * q + 2] = (acc_t)v.z;
-                        cb[4 * q + 3] = (acc_t)v.w;
-                    }
-                }
-                return;
-            }
-        }
+    } else {
 #pragma unroll
         for (int k = 0; k < W; ++k)
-            if (k <= d.M)
-                cb[k] = (acc_t)br[k];
+            ra[k] = (k < d.N) ? ar[k] : io_t(0);
+    }
+    if constexpr (FIR) {
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            rb[k] = (k <= d.M) ? br[k] : io_t(0);
     } else {
-        cb[0] = (acc_t)br[0];
+        const io_t b0 = br[0];
+        rb[0] = d.has_b ? b0 : io_t(1);
     }
 }
+
+// ca[k] = a_k (k = 1..W, ca[0] = 0), cb[k] = b_k (k = 0..W-1) in acc_t.
+template <int W, bool FIR, typename io_t, typename acc_t>
+__device__ __forceinline__ void cvt_row(const io_t (&ra)[W], const io_t (&rb)[kRawB<W, FIR>],
+                                        acc_t (&ca)[W + 1], acc_t (&cb)[W])
+{
+    ca[0] = acc_t(0);
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        ca[k + 1] = (acc_t)ra[k];
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+        cb[k] = (k < kRawB<W, FIR>) ? (acc_t)rb[k < kRawB<W, FIR> ? k : 0] : acc_t(0);
+}
+
+// Converted time-invariant row of channel b (ac/bc are [B][K]; bc must be a
+// valid address even without b).
+template <int W, bool FIR, typename io_t, typename acc_t>
+__device__ __forceinline__ void ld_row_lti(const Dims &d, const io_t *bc, const io_t *ac,
+                                           int64_t b, acc_t (&ca)[W + 1], acc_t (&cb)[W])
+{
+    io_t ra[W], rb[kRawB<W, FIR>];
+    ld_raw<W, FIR, false>(d, ac + (d.N > 0 ? b * d.N : 0), bc + (d.has_b ? b * (d.M + 1) : 0),
+                          ra, rb);
+    cvt_row<W, FIR>(ra, rb, ca, cb);
+}
+
+// Everything one time step reads from memory, fetched ahead of its use so the
+// loads of step t + 2 overlap the arithmetic of step t.  TV: the coefficient
+// row; s0..s2: signal samples whose meaning the caller sets.
+template <int W, bool TV, bool FIR, typename io_t>
+struct Prefetch {
+    io_t ra[TV ? W : 1];
+    io_t rb[TV ? kRawB<W, FIR> : 1];
+    io_t s0, s1, s2;
+};
 
 // Decode a flat item index into (lane-in-chunk r, channel, chunk) with the
 // nl lanes of a chunk adjacent, then channels (TB) or chunks (BT) fastest.
@@ -277,7 +319,7 @@ filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb
 // share every coefficient row among their solves.
 template <int W>
 struct SummarySlots {
-    static constexpr int value = W == 1 ? 2 : (W == 2 ? 3 : 5);
+    static constexpr int value = W == 1 ? 2 : 3;
 };
 
 // summary.h: chunk summaries, one translation unit per (bucket, I/O type,

@@ -11,8 +11,9 @@
 // Per-sample coefficients: every chunk needs N + 1 solves.  Each lane runs S
 // of them side by side, so one coefficient row fetched (and converted) per
 // step feeds S recursions; nl = ceil((N + 1) / S) adjacent lanes cover one
-// chunk.  Time-invariant coefficients: one particular solve per chunk, and
-// the N homogeneous solves once per channel (Phi is the same for every chunk).
+// chunk.  Rows are fetched two steps ahead of their use.  Time-invariant
+// coefficients: one particular solve per chunk, and the N homogeneous solves
+// once per channel (Phi is the same for every chunk).
 //
 // Register histories live in W registers addressed modulo W; the time loop
 // is unrolled by W so every index is a compile-time constant.
@@ -26,21 +27,35 @@ namespace filt_detail {
 
 // S forward recursions over [t0, t0 + L).  h[q][t mod W] = y_q[t]; hx[t mod
 // W] = x[t].  Slot q is driven by wgt[q] * (b * x)[t] (XIN) and its history.
-template <int W, int S, bool TV, bool FIR, bool XIN, typename io_t>
-__device__ __forceinline__ void fwd_solves(const Dims &d, int64_t b, int64_t t0, const io_t *x,
-                                           const io_t *bc, const io_t *ac, double (&h)[S][W],
-                                           double (&hx)[W], const double (&wgt)[S],
-                                           const double (&la)[W + 1], const double (&lb)[W])
+template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t>
+__device__ __forceinline__ void fwd_solves(const Dims &d, int64_t t0, const Cursor<io_t> &xc,
+                                           const Cursor<io_t> &acur, const Cursor<io_t> &bcur,
+                                           double (&h)[S][W], double (&hx)[W],
+                                           const double (&wgt)[S], const double (&la)[W + 1],
+                                           const double (&lb)[W])
 {
     constexpr int m = W - 1;
     const int64_t tend = t0 + d.L;
+    using PF = Prefetch<W, TV, FIR, io_t>;
+    auto fetch = [&](int64_t t, PF &p) {
+        if constexpr (TV)
+            ld_raw<W, FIR, AV>(d, acur.at(t0, t), bcur.at(t0, t), p.ra, p.rb);
+        if constexpr (XIN)
+            p.s0 = *xc.at(t0, t);  // steps past T are never summarised
+    };
+    PF n1, n2;
+    fetch(t0, n1);
+    fetch(t0 + 1, n2);
     for (int64_t tb = t0; tb < tend; tb += W) {
 #pragma unroll
         for (int s = 0; s < W; ++s) {
             const int64_t t = tb + s;
+            const PF cur = n1;
+            n1 = n2;
+            fetch(t + 2, n2);
             double ca[W + 1], cb[W];
             if constexpr (TV) {
-                ld_row<W, FIR>(d, bc, ac, b, t, ca, cb);
+                cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
             } else {
 #pragma unroll
                 for (int k = 0; k <= W; ++k)
@@ -51,7 +66,7 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t b, int64_t t0,
             }
             double u = 0.0;
             if constexpr (XIN) {
-                hx[s & m] = t < d.T ? (double)x[sig_at(d, b, t)] : 0.0;
+                hx[s & m] = (double)cur.s0;
                 if constexpr (FIR) {
 #pragma unroll
                     for (int k = W - 1; k >= 0; --k)
@@ -72,6 +87,9 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t b, int64_t t0,
                 }
                 h[q][s & m] = (p0 + p1) - ca[1] * h[q][(s - 1) & m];
             }
+            // keep each step's live range to itself (bounded registers); the
+            // prefetch above already covers the load latency
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -83,7 +101,7 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t b, int64_t t0,
 //   summ[(b*C + c)*(N*N + N) + i*N + j] = Phi_c[i][j] (per-sample coefficients)
 //   phi[b*N*N + i*N + j]                = Phi[i][j]   (time-invariant)
 //   summ[(b*C + c)*(N*N + N) + N*N + i] = s_c[i]
-template <int W, int S, bool TV, bool FIR, bool XIN, typename io_t>
+template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t>
 __global__ void __launch_bounds__(kThreads)
 k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
               const io_t *__restrict__ bc, const io_t *__restrict__ ac, int64_t c_first,
@@ -105,7 +123,10 @@ k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
 
     double la[W + 1], lb[W];
     if constexpr (!TV)
-        ld_row<W, FIR>(d, bc, ac, b, 0, la, lb);
+        ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
+    const Cursor<io_t> xc = cursor(d, x, b, t0, 1);
+    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     double h[S][W], hx[W], wgt[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) {
@@ -123,7 +144,7 @@ k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
         for (int k = 1; k < W; ++k)
             hx[(-k) & m] = ld_x<io_t, double>(d, x, xi, b, t0 - k);
     }
-    fwd_solves<W, S, TV, FIR, XIN>(d, b, t0, x, bc, ac, h, hx, wgt, la, lb);
+    fwd_solves<W, S, TV, FIR, XIN, AV>(d, t0, xc, acur, bcur, h, hx, wgt, la, lb);
     const int64_t SS = (int64_t)N * N + N;
 #pragma unroll
     for (int q = 0; q < S; ++q) {
@@ -155,20 +176,37 @@ k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
 // rs[q][(k - t) mod W].  Per step:
 //   ybar = wgt[q] gy[t] + s_1,  s_k <- s_{k+1} - a_k[t] ybar,
 //   r_k <- r_{k+1} + b_k[t] ybar.
-template <int W, int S, bool TV, bool FIR, bool GIN, typename io_t>
-__device__ __forceinline__ void bwd_solves(const Dims &d, int64_t b, int64_t t0, const io_t *gy,
-                                           const io_t *bc, const io_t *ac, double (&ss)[S][W],
-                                           double (&rs)[S][W], const double (&wgt)[S],
-                                           const double (&la)[W + 1], const double (&lb)[W])
+template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t>
+__device__ __forceinline__ void bwd_solves(const Dims &d, int64_t t0, const Cursor<io_t> &gc,
+                                           const Cursor<io_t> &acur, const Cursor<io_t> &bcur,
+                                           double (&ss)[S][W], double (&rs)[S][W],
+                                           const double (&wgt)[S], const double (&la)[W + 1],
+                                           const double (&lb)[W])
 {
     constexpr int m = W - 1;
+    using PF = Prefetch<W, TV, FIR, io_t>;
+    auto fetch = [&](int64_t t, PF &p) {
+        if constexpr (TV)
+            ld_raw<W, FIR, AV>(d, acur.at(t0, t), bcur.at(t0, t), p.ra, p.rb);
+        if constexpr (GIN) {
+            const io_t g = *gc.at(t0, t);
+            p.s0 = t < d.T ? g : io_t(0);
+        }
+    };
+    const int64_t thi = t0 + d.L - 1;
+    PF n1, n2;
+    fetch(thi, n1);
+    fetch(thi - 1, n2);
     for (int64_t tb = t0 + d.L - W; tb >= t0; tb -= W) {
 #pragma unroll
         for (int s = W - 1; s >= 0; --s) {
             const int64_t t = tb + s;
+            const PF cur = n1;
+            n1 = n2;
+            fetch(t - 2, n2);
             double ca[W + 1], cb[W];
             if constexpr (TV) {
-                ld_row<W, FIR>(d, bc, ac, b, t, ca, cb);
+                cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
             } else {
 #pragma unroll
                 for (int k = 0; k <= W; ++k)
@@ -179,7 +217,7 @@ __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t b, int64_t t0,
             }
             double g = 0.0;
             if constexpr (GIN)
-                g = t < d.T ? (double)gy[sig_at(d, b, t)] : 0.0;
+                g = (double)cur.s0;
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 const double yb = (GIN ? wgt[q] * g : 0.0) + ss[q][(1 - s) & m];
@@ -194,6 +232,7 @@ __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t b, int64_t t0,
                         rs[q][(k + 1 - s) & m] += cb[k] * yb;
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -208,7 +247,7 @@ __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t b, int64_t t0,
 // Time-invariant Phi' and R go to phi[b*(N*N + M*N) + ...].
 // Before the first (highest) time and after the last, s_k sits in slot
 // (k + 1) mod W.
-template <int W, int S, bool TV, bool FIR, bool GIN, typename io_t>
+template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t>
 __global__ void __launch_bounds__(kThreads)
 k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
               const io_t *__restrict__ ac, int64_t c_first, int64_t ncs, int j_first, int nj,
@@ -228,7 +267,10 @@ k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
     const int N = d.N, M = d.M;
     double la[W + 1], lb[W];
     if constexpr (!TV)
-        ld_row<W, FIR>(d, bc, ac, b, 0, la, lb);
+        ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
+    const Cursor<io_t> gc = cursor(d, gy, b, t0, 1);
+    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     double ss[S][W], rs[S][W], wgt[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) {
@@ -240,7 +282,7 @@ k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
             rs[q][e] = 0.0;
         }
     }
-    bwd_solves<W, S, TV, FIR, GIN>(d, b, t0, gy, bc, ac, ss, rs, wgt, la, lb);
+    bwd_solves<W, S, TV, FIR, GIN, AV>(d, t0, gc, acur, bcur, ss, rs, wgt, la, lb);
     const int64_t SB = (int64_t)(N + 1) * (N + M);
     double *base = summ + (b * d.C + c) * SB;
 #pragma unroll
@@ -281,14 +323,19 @@ filt_status fwd_summary_fir(const Dims &d, const io_t *x, const io_t *xi, const 
     if (d.tv) {
         constexpr int S = SummarySlots<W>::value;
         const int nl = (N + 1 + S - 1) / S;
-        FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, S, true, FIR, true, io_t>),
-                    dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
-                    (int64_t)0, ncs, 0, N + 1, summ, phi);
+        if (d.a_vec)
+            FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, S, true, FIR, true, true, io_t>),
+                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
+                        (int64_t)0, ncs, 0, N + 1, summ, phi);
+        else
+            FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, S, true, FIR, true, false, io_t>),
+                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
+                        (int64_t)0, ncs, 0, N + 1, summ, phi);
     } else {
-        FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, 1, false, FIR, true, io_t>),
+        FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, 1, false, FIR, true, false, io_t>),
                     dim3(grid_for(d.B * ncs)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
                     (int64_t)0, ncs, N, 1, summ, phi);
-        FILT_LAUNCH("fwd_summary_phi", (k_fwd_summary<W, 1, false, false, false, io_t>),
+        FILT_LAUNCH("fwd_summary_phi", (k_fwd_summary<W, 1, false, false, false, false, io_t>),
                     dim3(grid_for(d.B * N)), dim3(kThreads), 0, st, d, x, xi, bc, ac, (int64_t)0,
                     (int64_t)1, 0, N, summ, phi);
     }
@@ -313,15 +360,20 @@ filt_status bwd_summary_fir(const Dims &d, const io_t *gy, const io_t *bc, const
     if (d.tv) {
         constexpr int S = SummarySlots<W>::value;
         const int nl = (N + 1 + S - 1) / S;
-        FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, S, true, FIR, true, io_t>),
-                    dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, gy, bc, ac,
-                    (int64_t)1, ncs, 0, N + 1, summ, phi);
+        if (d.a_vec)
+            FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, S, true, FIR, true, true, io_t>),
+                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, gy, bc, ac,
+                        (int64_t)1, ncs, 0, N + 1, summ, phi);
+        else
+            FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, S, true, FIR, true, false, io_t>),
+                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, gy, bc, ac,
+                        (int64_t)1, ncs, 0, N + 1, summ, phi);
     } else {
-        FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, 1, false, FIR, true, io_t>),
+        FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, 1, false, FIR, true, false, io_t>),
                     dim3(grid_for(d.B * ncs)), dim3(kThreads), 0, st, d, gy, bc, ac, (int64_t)1,
                     ncs, N, 1, summ, phi);
         if (N > 0)
-            FILT_LAUNCH("bwd_summary_phi", (k_bwd_summary<W, 1, false, FIR, false, io_t>),
+            FILT_LAUNCH("bwd_summary_phi", (k_bwd_summary<W, 1, false, FIR, false, false, io_t>),
                         dim3(grid_for(d.B * N)), dim3(kThreads), 0, st, d, gy, bc, ac,
                         (int64_t)0, (int64_t)1, 0, N, summ, phi);
     }
