@@ -111,6 +111,10 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
         return fail(FILT_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->B == 0 || p->T == 0)
         return FILT_OK;
+    if (p->layout == FILT_LAYOUT_TB &&
+        p->B * (int64_t)(std::max(p->N, p->M + 1) + 1) >= ((int64_t)1 << 31))
+        return fail(FILT_EUNSUPPORTED, "[T][B] layout with B * taps >= 2^31 (B=%lld)",
+                    (long long)p->B);
     if (x_or_gy == nullptr)
         return fail(FILT_EINVAL, "input signal is NULL");
     if (b == nullptr && p->M != 0)
@@ -234,7 +238,9 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
         const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
         const size_t vec = W >= 4 ? 16 : (size_t)W * sizeof(*ac);
         d.a_vec = (p->N == W) && ((uintptr_t)ac % vec == 0);
-        d.ga_vec = d.a_vec && ((uintptr_t)ga % vec == 0);
+        // full-row kernels also store ga rows as vectors
+        d.a_vec = d.a_vec && (ga == nullptr || ((uintptr_t)ga % vec == 0));
+        d.ga_vec = d.a_vec;
     }
     const WsPlan w = ws_plan(d);
     if (ws == nullptr || ws_bytes < w.total)

@@ -125,11 +125,11 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
 // future (zero for the last chunk).  Adjoint state slots as in the summary:
 // before processing t, s_k is in ss[(k - t) mod W] and r_k in rs[(k - t) mod W].
 // Per step: ybar = gy[t] + s_1, gx[t] = b_0 ybar + r_1, then the scatter
-// updates; COEF also forms gb_k[t] = ybar x[t-k] and ga_k[t] = -ybar y[t-k]
+// updates; GB / GA also form gb_k[t] = ybar x[t-k] and ga_k[t] = -ybar y[t-k]
 // from windows wx[t mod W] = x[t], wy[t mod W] = y[t] that slide down in time.
 // Time-invariant filters write per-(b, c) FP64 partial sums to
 // part[(b*C + c)*(N+M+1)] = (ga_1..ga_N, gb_0..gb_M).  Chunk 0 writes gyi / gxi.
-template <int W, bool TV, bool FIR, bool COEF, bool AV, typename io_t, typename acc_t>
+template <int W, bool TV, bool FIR, bool GA, bool GB, bool AV, typename io_t, typename acc_t>
 __global__ void __launch_bounds__(kThreads)
 k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
             const io_t *__restrict__ xi, const io_t *__restrict__ y,
@@ -155,6 +155,20 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
     const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     const int64_t sstride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
     io_t *gxrow = gx != nullptr ? gx + sig_at(d, b, t0) : nullptr;
+    // per-sample gradient rows: row of time t at grow + (t - t0) * gstride
+    const int64_t gstride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
+    io_t *garow = (TV && GA) ? ga + row_at(d, b, t0, N) : nullptr;
+    io_t *gbrow = (TV && GB) ? gb + row_at(d, b, t0, M + 1) : nullptr;
+    // coefficient-gradient windows read x[t-(W-1)] and y[t-W]; times before 0
+    // (chunk 0, first block only) come from the initial conditions instead
+    const Cursor<io_t> xw = cursor(d, x, b, t0, 1, W + 4);
+    const Cursor<io_t> yw = cursor(d, y, b, t0, 1, W + 4);
+    io_t xic[W], yic[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        xic[q] = (GB && xi != nullptr && q < M) ? xi[b * M + q] : io_t(0);
+        yic[q] = (GA && yi != nullptr && q < N) ? yi[b * N + q] : io_t(0);
+    }
     acc_t ss[W], rs[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) {
@@ -180,19 +194,20 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
         sgb[k] = 0.0;
     acc_t wx[W], wy[W];
     const int64_t thi = t0 + d.L - 1;
-    const bool want_gb = COEF && gb != nullptr;
-    const bool want_ga = COEF && ga != nullptr;
+    constexpr bool want_gb = GB;
+    constexpr bool want_ga = GA;
+    constexpr bool COEF = GA || GB;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
         wx[q] = acc_t(0);
         wy[q] = acc_t(0);
     }
-    if (want_gb) {
+    if constexpr (want_gb) {
 #pragma unroll
         for (int k = 0; k < W - 1; ++k)
             wx[(thi - k) & m] = ld_x<io_t, acc_t>(d, x, xi, b, thi - k);
     }
-    if (want_ga) {
+    if constexpr (want_ga) {
 #pragma unroll
         for (int k = 1; k < W; ++k)
             wy[(thi - k) & m] = ld_y<io_t, acc_t>(d, y, yi, b, thi - k);
@@ -203,8 +218,10 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
             ld_raw<W, FIR, AV>(d, acur.at(t0, t), bcur.at(t0, t), p.ra, p.rb);
         const io_t g = *gc.at(t0, t);
         p.s0 = t < d.T ? g : io_t(0);
-        p.s1 = want_gb ? ld_x<io_t, io_t>(d, x, xi, b, t - (W - 1)) : io_t(0);
-        p.s2 = want_ga ? ld_y<io_t, io_t>(d, y, yi, b, t - W) : io_t(0);
+        if constexpr (want_gb)
+            p.s1 = *xw.at(t0, t - (W - 1));
+        if constexpr (want_ga)
+            p.s2 = *yw.at(t0, t - W);
     };
     PF n1, n2;
     fetch(thi, n1);
@@ -246,11 +263,15 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                     rs[(k + 1 - s) & m] += cb[k] * yb;
             }
             if constexpr (COEF) {
-                if (want_gb) {
-                    wx[(s + 1) & m] = (acc_t)cur.s1;
+                // only chunk 0's first block reaches times before 0
+                const bool pre0 = (c == 0) && (tb == 0);
+                if constexpr (want_gb) {
+                    // x[t-(W-1)] = x[s-(W-1)] = xi[W-2-s] when it is before time 0
+                    const io_t xv = (s < W - 1) ? xic[(W - 2 - s) < 0 ? 0 : (W - 2 - s)] : io_t(0);
+                    wx[(s + 1) & m] = (acc_t)((pre0 && s < W - 1) ? xv : cur.s1);
                     if constexpr (TV) {
                         if (in) {
-                            io_t *o = gb + row_at(d, b, t, M + 1);
+                            io_t *o = gbrow + (t - t0) * gstride * (M + 1);
 #pragma unroll
                             for (int k = 0; k < W; ++k)
                                 if (k <= M)
@@ -262,14 +283,15 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                             sgb[k] += (double)(yb * wx[(s - k) & m]);
                     }
                 }
-                if (want_ga) {
-                    wy[s & m] = (acc_t)cur.s2;
+                if constexpr (want_ga) {
+                    // y[t-W] = y[s-W] = yi[W-1-s] when it is before time 0
+                    wy[s & m] = (acc_t)(pre0 ? yic[W - 1 - s] : cur.s2);
                     if constexpr (TV) {
                         if (in) {
-                            io_t *o = ga + row_at(d, b, t, N);
+                            io_t *o = garow + (t - t0) * gstride * N;
                             bool done = false;
                             if constexpr (AV && sizeof(io_t) == 4 && W % 4 == 0) {
-                                if (d.ga_vec) {
+                                {
 #pragma unroll
                                     for (int q = 0; q < W / 4; ++q) {
                                         if (4 * q < N) {
@@ -383,27 +405,28 @@ filt_status bwd_apply(const Dims &d, const io_t *gy, const io_t *x, const io_t *
                       const double *states, io_t *gx, io_t *gb, io_t *ga, io_t *gxi, io_t *gyi,
                       double *part, hipStream_t st)
 {
-    const bool coef = (ga != nullptr) || (gb != nullptr);
-#define FILT_BWD_APPLY(TVV, COEFV, AVV)                                                            \
-    FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, COEFV, AVV, io_t, acc_t>),                  \
+#define FILT_BWD_APPLY(TVV, GAV, GBV, AVV)                                                         \
+    FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, GAV, GBV, AVV, io_t, acc_t>),               \
                 dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, gy, x, xi, y, yi, bc, ac,     \
                 states, gx, gb, ga, gxi, gyi, part)
-    if (d.tv && d.a_vec) {
-        if (coef)
-            FILT_BWD_APPLY(true, true, true);
-        else
-            FILT_BWD_APPLY(true, false, true);
-    } else if (d.tv) {
-        if (coef)
-            FILT_BWD_APPLY(true, true, false);
-        else
-            FILT_BWD_APPLY(true, false, false);
-    } else {
-        if (coef)
-            FILT_BWD_APPLY(false, true, false);
-        else
-            FILT_BWD_APPLY(false, false, false);
-    }
+#define FILT_BWD_APPLY_G(TVV, AVV)                                                                 \
+    do {                                                                                           \
+        if (ga != nullptr && gb != nullptr)                                                        \
+            FILT_BWD_APPLY(TVV, true, true, AVV);                                                  \
+        else if (ga != nullptr)                                                                    \
+            FILT_BWD_APPLY(TVV, true, false, AVV);                                                 \
+        else if (gb != nullptr)                                                                    \
+            FILT_BWD_APPLY(TVV, false, true, AVV);                                                 \
+        else                                                                                       \
+            FILT_BWD_APPLY(TVV, false, false, AVV);                                                \
+    } while (0)
+    if (d.tv && d.a_vec)
+        FILT_BWD_APPLY_G(true, true);
+    else if (d.tv)
+        FILT_BWD_APPLY_G(true, false);
+    else
+        FILT_BWD_APPLY_G(false, false);
+#undef FILT_BWD_APPLY_G
 #undef FILT_BWD_APPLY
     return check_launch("backward apply");
 }

@@ -110,26 +110,26 @@ __device__ __forceinline__ acc_t ld_y(const Dims &d, const io_t *y, const io_t *
 template <typename T>
 struct Cursor {
     const T *p0;     // element of time t0
-    int64_t stride;  // elements per time step
+    int stride;      // elements per time step (the host checks it fits)
     int lo, hi;      // clamp of t - t0
 
     __device__ __forceinline__ const T *at(int64_t t0, int64_t t) const
     {
-        int r = (int)(t - t0);
-        r = r < lo ? lo : (r > hi ? hi : r);
+        const int r = min(max((int)(t - t0), lo), hi);
         return p0 + (int64_t)r * stride;
     }
 };
 
-// Cursor over a signal [layout] (K = 1) or over per-sample rows of K taps.
+// Cursor over a signal [layout] (K = 1) or over per-sample rows of K taps;
+// it may reach `back` steps before t0 (never before time 0).
 template <typename T>
 __device__ __forceinline__ Cursor<T> cursor(const Dims &d, const T *base, int64_t b, int64_t t0,
-                                            int K)
+                                            int K, int back = 4)
 {
     Cursor<T> c;
     c.p0 = base + (d.layout == FILT_LAYOUT_TB ? t0 * d.B + b : b * d.T + t0) * (int64_t)K;
-    c.stride = (d.layout == FILT_LAYOUT_TB ? d.B : 1) * (int64_t)K;
-    const int64_t lo = -t0 < -4 ? -4 : -t0;
+    c.stride = (int)((d.layout == FILT_LAYOUT_TB ? d.B : 1) * (int64_t)K);
+    const int64_t lo = -t0 < -back ? -(int64_t)back : -t0;
     const int64_t hi = d.T - 1 - t0 > d.L + 4 ? d.L + 4 : d.T - 1 - t0;
     c.lo = (int)lo;
     c.hi = (int)hi;
