@@ -68,16 +68,20 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
             ld_raw<W, FIR, AV>(d, acur.at(t0, t), bcur.at(t0, t), p.ra, p.rb);
         p.s0 = *xc.at(t0, t);  // outputs past T are not written
     };
-    PF n1, n2;
-    fetch(t0, n1);
-    fetch(t0 + 1, n2);
-    for (int64_t tb = t0; tb < tend; tb += W) {
+    // circular prefetch: step t's data is fetched P steps ahead into buf[t % P];
+    // the loop is unrolled by U = max(W, P) so every index is static
+    constexpr int P = kApplyPrefetch;
+    constexpr int U = W > P ? W : P;
+    PF buf[P];
 #pragma unroll
-        for (int s = 0; s < W; ++s) {
+    for (int q = 0; q < P; ++q)
+        fetch(t0 + q, buf[q]);
+    for (int64_t tb = t0; tb < tend; tb += U) {
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
             const int64_t t = tb + s;
-            const PF cur = n1;
-            n1 = n2;
-            fetch(t + 2, n2);
+            const PF cur = buf[s % P];
+            fetch(t + P, buf[s % P]);
             acc_t ca[W + 1], cb[W];
             if constexpr (TV) {
                 cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
@@ -223,17 +227,21 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
         if constexpr (want_ga)
             p.s2 = *yw.at(t0, t - W);
     };
-    PF n1, n2;
-    fetch(thi, n1);
-    fetch(thi - 1, n2);
-    for (int64_t tb = t0 + d.L - W; tb >= t0; tb -= W) {
+    // circular prefetch in decreasing time: the i-th step processed (time
+    // thi - i) reads buf[i % P], fetched P steps earlier
+    constexpr int P = kApplyPrefetch;
+    constexpr int U = W > P ? W : P;
+    PF buf[P];
 #pragma unroll
-        for (int s = W - 1; s >= 0; --s) {
+    for (int q = 0; q < P; ++q)
+        fetch(thi - q, buf[q]);
+    for (int64_t tb = t0 + d.L - U; tb >= t0; tb -= U) {
+#pragma unroll
+        for (int s = U - 1; s >= 0; --s) {
             const int64_t t = tb + s;
             const bool in = t < d.T;
-            const PF cur = n1;
-            n1 = n2;
-            fetch(t - 2, n2);
+            const PF cur = buf[(U - 1 - s) % P];
+            fetch(t - P, buf[(U - 1 - s) % P]);
             acc_t ca[W + 1], cb[W];
             if constexpr (TV) {
                 cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
@@ -285,7 +293,8 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                 }
                 if constexpr (want_ga) {
                     // y[t-W] = y[s-W] = yi[W-1-s] when it is before time 0
-                    wy[s & m] = (acc_t)(pre0 ? yic[W - 1 - s] : cur.s2);
+                    const io_t yv = yic[(s < W) ? (W - 1 - s) : 0];
+                    wy[s & m] = (acc_t)((pre0 && s < W) ? yv : cur.s2);
                     if constexpr (TV) {
                         if (in) {
                             io_t *o = garow + (t - t0) * gstride * N;

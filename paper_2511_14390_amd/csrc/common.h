@@ -208,6 +208,12 @@ __device__ __forceinline__ void ld_row_lti(const Dims &d, const io_t *bc, const 
     cvt_row<W, FIR>(ra, rb, ca, cb);
 }
 
+// Prefetch depth (time steps) of the summary and apply loops.  The apply
+// kernels run one long sequential chain per (channel, chunk) and are
+// latency-bound, so they keep more steps in flight.
+constexpr int kSummaryPrefetch = 4;
+constexpr int kApplyPrefetch = 8;
+
 // Everything one time step reads from memory, fetched ahead of its use so the
 // loads of step t + 2 overlap the arithmetic of step t.  TV: the coefficient
 // row; s0..s2: signal samples whose meaning the caller sets.

@@ -43,16 +43,20 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t t0, const Curs
         if constexpr (XIN)
             p.s0 = *xc.at(t0, t);  // steps past T are never summarised
     };
-    PF n1, n2;
-    fetch(t0, n1);
-    fetch(t0 + 1, n2);
-    for (int64_t tb = t0; tb < tend; tb += W) {
+    // circular prefetch: step t's data is fetched P steps ahead into buf[t % P];
+    // the loop is unrolled by U = max(W, P) so every index is static
+    constexpr int P = kSummaryPrefetch;
+    constexpr int U = W > P ? W : P;
+    PF buf[P];
 #pragma unroll
-        for (int s = 0; s < W; ++s) {
+    for (int q = 0; q < P; ++q)
+        fetch(t0 + q, buf[q]);
+    for (int64_t tb = t0; tb < tend; tb += U) {
+#pragma unroll
+        for (int s = 0; s < U; ++s) {
             const int64_t t = tb + s;
-            const PF cur = n1;
-            n1 = n2;
-            fetch(t + 2, n2);
+            const PF cur = buf[s % P];
+            fetch(t + P, buf[s % P]);
             double ca[W + 1], cb[W];
             if constexpr (TV) {
                 cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
@@ -194,16 +198,20 @@ __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t t0, const Curs
         }
     };
     const int64_t thi = t0 + d.L - 1;
-    PF n1, n2;
-    fetch(thi, n1);
-    fetch(thi - 1, n2);
-    for (int64_t tb = t0 + d.L - W; tb >= t0; tb -= W) {
+    // circular prefetch in decreasing time: the i-th step processed (time
+    // thi - i) reads buf[i % P], fetched P steps earlier
+    constexpr int P = kSummaryPrefetch;
+    constexpr int U = W > P ? W : P;
+    PF buf[P];
 #pragma unroll
-        for (int s = W - 1; s >= 0; --s) {
+    for (int q = 0; q < P; ++q)
+        fetch(thi - q, buf[q]);
+    for (int64_t tb = t0 + d.L - U; tb >= t0; tb -= U) {
+#pragma unroll
+        for (int s = U - 1; s >= 0; --s) {
             const int64_t t = tb + s;
-            const PF cur = n1;
-            n1 = n2;
-            fetch(t - 2, n2);
+            const PF cur = buf[(U - 1 - s) % P];
+            fetch(t - P, buf[(U - 1 - s) % P]);
             double ca[W + 1], cb[W];
             if constexpr (TV) {
                 cvt_row<W, FIR>(cur.ra, cur.rb, ca, cb);
