@@ -363,15 +363,15 @@ filt_status fwd_apply(const Dims &d, const io_t *x, const io_t *bc, const io_t *
 {
     if (d.tv && d.a_vec)
         FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, true, FIR, true, io_t, acc_t>),
-                    dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
+                    dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, x, xi, bc, ac, yi,
                     states, y);
     else if (d.tv)
         FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, true, FIR, false, io_t, acc_t>),
-                    dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
+                    dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, x, xi, bc, ac, yi,
                     states, y);
     else
         FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, false, FIR, false, io_t, acc_t>),
-                    dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, x, xi, bc, ac, yi,
+                    dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, x, xi, bc, ac, yi,
                     states, y);
     return check_launch("forward apply");
 }
@@ -416,7 +416,7 @@ filt_status bwd_apply(const Dims &d, const io_t *gy, const io_t *x, const io_t *
 {
 #define FILT_BWD_APPLY(TVV, GAV, GBV, AVV)                                                         \
     FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, GAV, GBV, AVV, io_t, acc_t>),               \
-                dim3(grid_for(d.B * d.C)), dim3(kThreads), 0, st, d, gy, x, xi, y, yi, bc, ac,     \
+                dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, gy, x, xi, y, yi, bc, ac,     \
                 states, gx, gb, ga, gxi, gyi, part)
 #define FILT_BWD_APPLY_G(TVV, AVV)                                                                 \
     do {                                                                                           \

@@ -218,7 +218,7 @@ filt_status fir_states_run(const Dims &d, const double *summ, double *states, hi
 {
     if (d.C < 2 || d.M == 0)
         return FILT_OK;
-    FILT_LAUNCH("fir_states", k_fir_states, dim3(grid_for(d.B * (d.C - 1) * d.M)), dim3(kThreads),
+    FILT_LAUNCH("fir_states", k_fir_states, dim3(blocks_for(d.B * (d.C - 1) * d.M)), dim3(block_for(d.B * (d.C - 1) * d.M)),
                 0, st, d, summ, states);
     return check_launch("fir states");
 }
@@ -228,10 +228,10 @@ filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb
 {
     const int64_t n = d.B * (d.N + d.M + 1);
     if (f64)
-        FILT_LAUNCH("reduce_lti", (k_reduce_lti<double>), dim3(grid_for(n)), dim3(kThreads), 0, st,
+        FILT_LAUNCH("reduce_lti", (k_reduce_lti<double>), dim3(blocks_for(n)), dim3(block_for(n)), 0, st,
                     d, part, (double *)ga, (double *)gb);
     else
-        FILT_LAUNCH("reduce_lti", (k_reduce_lti<float>), dim3(grid_for(n)), dim3(kThreads), 0, st,
+        FILT_LAUNCH("reduce_lti", (k_reduce_lti<float>), dim3(blocks_for(n)), dim3(block_for(n)), 0, st,
                     d, part, (float *)ga, (float *)gb);
     return check_launch("reduce");
 }

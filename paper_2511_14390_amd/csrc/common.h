@@ -285,6 +285,21 @@ inline unsigned grid_for(int64_t n)
     return (unsigned)((n + kThreads - 1) / kThreads);
 }
 
+// Workgroup size for a launch of n independent items: full 256-thread groups
+// only when that still gives every CU several groups; otherwise one
+// wavefront per group so the few items spread over all CUs instead of piling
+// onto a quarter of them.
+constexpr int64_t kCUs = 256;
+inline unsigned block_for(int64_t n)
+{
+    return n >= kCUs * 4 * kThreads ? (unsigned)kThreads : 64u;
+}
+inline unsigned blocks_for(int64_t n)
+{
+    const unsigned bs = block_for(n);
+    return (unsigned)((n + bs - 1) / bs);
+}
+
 // Workspace carve-up (all FP64), 256-byte aligned regions.
 struct WsPlan {
     size_t summ, phi, agg, bstart, states, part, total;

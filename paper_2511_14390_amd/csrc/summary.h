@@ -333,18 +333,18 @@ filt_status fwd_summary_fir(const Dims &d, const io_t *x, const io_t *xi, const 
         const int nl = (N + 1 + S - 1) / S;
         if (d.a_vec)
             FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, S, true, FIR, true, true, io_t>),
-                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
+                        dim3(blocks_for(d.B * ncs * nl)), dim3(block_for(d.B * ncs * nl)), 0, st, d, x, xi, bc, ac,
                         (int64_t)0, ncs, 0, N + 1, summ, phi);
         else
             FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, S, true, FIR, true, false, io_t>),
-                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
+                        dim3(blocks_for(d.B * ncs * nl)), dim3(block_for(d.B * ncs * nl)), 0, st, d, x, xi, bc, ac,
                         (int64_t)0, ncs, 0, N + 1, summ, phi);
     } else {
         FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, 1, false, FIR, true, false, io_t>),
-                    dim3(grid_for(d.B * ncs)), dim3(kThreads), 0, st, d, x, xi, bc, ac,
+                    dim3(blocks_for(d.B * ncs)), dim3(block_for(d.B * ncs)), 0, st, d, x, xi, bc, ac,
                     (int64_t)0, ncs, N, 1, summ, phi);
         FILT_LAUNCH("fwd_summary_phi", (k_fwd_summary<W, 1, false, false, false, false, io_t>),
-                    dim3(grid_for(d.B * N)), dim3(kThreads), 0, st, d, x, xi, bc, ac, (int64_t)0,
+                    dim3(blocks_for(d.B * N)), dim3(block_for(d.B * N)), 0, st, d, x, xi, bc, ac, (int64_t)0,
                     (int64_t)1, 0, N, summ, phi);
     }
     return check_launch("forward summary");
@@ -370,19 +370,19 @@ filt_status bwd_summary_fir(const Dims &d, const io_t *gy, const io_t *bc, const
         const int nl = (N + 1 + S - 1) / S;
         if (d.a_vec)
             FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, S, true, FIR, true, true, io_t>),
-                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, gy, bc, ac,
+                        dim3(blocks_for(d.B * ncs * nl)), dim3(block_for(d.B * ncs * nl)), 0, st, d, gy, bc, ac,
                         (int64_t)1, ncs, 0, N + 1, summ, phi);
         else
             FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, S, true, FIR, true, false, io_t>),
-                        dim3(grid_for(d.B * ncs * nl)), dim3(kThreads), 0, st, d, gy, bc, ac,
+                        dim3(blocks_for(d.B * ncs * nl)), dim3(block_for(d.B * ncs * nl)), 0, st, d, gy, bc, ac,
                         (int64_t)1, ncs, 0, N + 1, summ, phi);
     } else {
         FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, 1, false, FIR, true, false, io_t>),
-                    dim3(grid_for(d.B * ncs)), dim3(kThreads), 0, st, d, gy, bc, ac, (int64_t)1,
+                    dim3(blocks_for(d.B * ncs)), dim3(block_for(d.B * ncs)), 0, st, d, gy, bc, ac, (int64_t)1,
                     ncs, N, 1, summ, phi);
         if (N > 0)
             FILT_LAUNCH("bwd_summary_phi", (k_bwd_summary<W, 1, false, FIR, false, false, io_t>),
-                        dim3(grid_for(d.B * N)), dim3(kThreads), 0, st, d, gy, bc, ac,
+                        dim3(blocks_for(d.B * N)), dim3(block_for(d.B * N)), 0, st, d, gy, bc, ac,
                         (int64_t)0, (int64_t)1, 0, N, summ, phi);
     }
     return check_launch("backward summary");
