@@ -70,8 +70,16 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + _instantiation_units()
 
 
-def _compile(src):
+def _headers():
+    return glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        newest = max(os.path.getmtime(p) for p in [src] + _headers())
+        if os.path.getmtime(obj) >= newest:
+            return obj, 0.0
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -81,14 +89,16 @@ def _compile(src):
     return obj, time.time() - t0
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit (incremental=True skips objects newer
+    than their sources and all headers -- a development shortcut)."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 1, 16)
     # longest units first so the pool stays busy
     srcs.sort(key=lambda p: (-int(p.split("_w")[1].split("_")[0]) if "_w" in p else 0))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda p: _compile(p, incremental), srcs))
     if verbose:
         for (obj, dt) in results:
             print(f"  {os.path.basename(obj)}: {dt:.1f}s", flush=True)
@@ -101,5 +111,5 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     t = time.time()
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     print(f"built {LIB} in {time.time() - t:.1f}s", file=sys.stderr)

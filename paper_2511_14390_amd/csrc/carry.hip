@@ -21,21 +21,38 @@ constexpr int kMaxD = 16;
 // Shared-memory budget (doubles) for staging a run of chunk summaries.
 constexpr int kStage = 4608;  // 36 KB
 
-// Copy summaries of steps [st0, st0 + n) of channel b into LDS (coalesced:
-// consecutive chunks are contiguous in summ, in either scan direction).
-// stage[q*SS + e] = summary of step st0 + q, element e.
+// Copy n consecutive chunk summaries of channel b into LDS with 16-byte
+// loads.  The chunks of steps [st0, st0 + n) are contiguous in summ in either
+// scan direction; stage_at() gives step st0 + q's copy.
+__device__ __forceinline__ void copy_lds(const double *__restrict__ src, double *dst,
+                                         int64_t count)
+{
+    // summaries start on 16-byte boundaries when SS is even; fall back otherwise
+    if (((uintptr_t)src & 15) == 0 && (count & 1) == 0) {
+        const double2 *s2 = reinterpret_cast<const double2 *>(src);
+        double2 *d2 = reinterpret_cast<double2 *>(dst);
+        const int64_t n2 = count >> 1;
+#pragma unroll 4
+        for (int64_t e = threadIdx.x; e < n2; e += blockDim.x)
+            d2[e] = s2[e];
+    } else {
+#pragma unroll 4
+        for (int64_t e = threadIdx.x; e < count; e += blockDim.x)
+            dst[e] = src[e];
+    }
+}
+
 __device__ __forceinline__ void stage_steps(const Dims &d, const CarryArgs &a, int64_t b,
                                             int64_t st0, int n, double *stage)
 {
     const int64_t c_first = a.bwd ? d.C - 1 - (st0 + n - 1) : st0;
-    const double *src = a.summ + (b * d.C + c_first) * a.SS;
-    const int64_t total = (int64_t)n * a.SS;
-    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-        const int64_t q = e / a.SS;  // chunk offset from c_first
-        const int64_t r = e - q * a.SS;
-        const int64_t slot = a.bwd ? (n - 1 - q) : q;
-        stage[slot * a.SS + r] = src[e];
-    }
+    copy_lds(a.summ + (b * d.C + c_first) * a.SS, stage, (int64_t)n * a.SS);
+}
+
+__device__ __forceinline__ const double *stage_at(const CarryArgs &a, const double *stage, int n,
+                                                  int q)
+{
+    return stage + (int64_t)(a.bwd ? n - 1 - q : q) * a.SS;
 }
 
 // (1) Block aggregates.  Workgroup (b, blk); thread e = i*(D+1) + j holds
@@ -44,7 +61,7 @@ __device__ __forceinline__ void stage_steps(const Dims &d, const CarryArgs &a, i
 __global__ void __launch_bounds__(320) k_carry_agg(Dims d, CarryArgs a)
 {
     __shared__ double Pm[2][kMaxD][kMaxD + 1];
-    __shared__ double stage[kStage];
+    __shared__ __align__(16) double stage[kStage];
     __shared__ double phi_lti[kMaxD * kMaxD];
     const int D = a.D;
     const int64_t DD = (int64_t)D * D;
@@ -69,8 +86,8 @@ __global__ void __launch_bounds__(320) k_carry_agg(Dims d, CarryArgs a)
         stage_steps(d, a, b, st0, n, stage);
         __syncthreads();
         for (int q = 0; q < n; ++q) {
-            const double *P = d.tv ? stage + (int64_t)q * a.SS : phi_lti;
-            const double *sv = stage + (int64_t)q * a.SS + DD;
+            const double *P = d.tv ? stage_at(a, stage, n, q) : phi_lti;
+            const double *sv = stage_at(a, stage, n, q) + DD;
             if (act) {
                 double acc = (j == D) ? sv[i] : 0.0;
                 for (int k = 0; k < D; ++k)
@@ -97,7 +114,7 @@ __global__ void __launch_bounds__(64)
 k_carry_blocks(Dims d, CarryArgs a, const void *init, int init_f64)
 {
     __shared__ double v[2][kMaxD];
-    __shared__ double stage[kStage];
+    __shared__ __align__(16) double stage[kStage];
     const int D = a.D;
     const int64_t AS = (int64_t)D * D + D;
     const int64_t b = blockIdx.x;
@@ -115,9 +132,7 @@ k_carry_blocks(Dims d, CarryArgs a, const void *init, int init_f64)
     for (int64_t blk0 = 0; blk0 < d.NB; blk0 += per) {
         const int n = (int)min((int64_t)per, d.NB - blk0);
         __syncthreads();
-        const double *src = a.agg + (b * d.NB + blk0) * AS;
-        for (int64_t e = threadIdx.x; e < n * AS; e += blockDim.x)
-            stage[e] = src[e];
+        copy_lds(a.agg + (b * d.NB + blk0) * AS, stage, n * AS);
         __syncthreads();
         for (int q = 0; q < n; ++q) {
             if (act) {
@@ -142,7 +157,7 @@ k_carry_blocks(Dims d, CarryArgs a, const void *init, int init_f64)
 __global__ void __launch_bounds__(64) k_carry_fill(Dims d, CarryArgs a)
 {
     __shared__ double v[2][kMaxD];
-    __shared__ double stage[kStage];
+    __shared__ __align__(16) double stage[kStage];
     __shared__ double phi_lti[kMaxD * kMaxD + kMaxD * kMaxD];
     const int D = a.D;
     const int R = a.R;
@@ -167,7 +182,7 @@ __global__ void __launch_bounds__(64) k_carry_fill(Dims d, CarryArgs a)
         __syncthreads();
         for (int q = 0; q < n; ++q) {
             const int64_t st = st0 + q;
-            const double *base = stage + (int64_t)q * a.SS;
+            const double *base = stage_at(a, stage, n, q);
             const double *P = d.tv ? base : phi_lti;
             const int64_t cn = a.bwd ? d.C - 2 - st : st + 1;
             double *o = a.states + (b * d.C + cn) * SD;
