@@ -18,41 +18,20 @@ namespace {
 
 constexpr int kMaxD = 16;
 
-// Shared-memory budget (doubles) for staging a run of chunk summaries.
-constexpr int kStage = 4608;  // 36 KB
-
-// Copy n consecutive chunk summaries of channel b into LDS with 16-byte
-// loads.  The chunks of steps [st0, st0 + n) are contiguous in summ in either
-// scan direction; stage_at() gives step st0 + q's copy.
-__device__ __forceinline__ void copy_lds(const double *__restrict__ src, double *dst,
-                                         int64_t count)
+__device__ __forceinline__ int64_t step_chunk(const Dims &d, const CarryArgs &a, int64_t i)
 {
-    // summaries start on 16-byte boundaries when SS is even; fall back otherwise
-    if (((uintptr_t)src & 15) == 0 && (count & 1) == 0) {
-        const double2 *s2 = reinterpret_cast<const double2 *>(src);
-        double2 *d2 = reinterpret_cast<double2 *>(dst);
-        const int64_t n2 = count >> 1;
-#pragma unroll 4
-        for (int64_t e = threadIdx.x; e < n2; e += blockDim.x)
-            d2[e] = s2[e];
-    } else {
-#pragma unroll 4
-        for (int64_t e = threadIdx.x; e < count; e += blockDim.x)
-            dst[e] = src[e];
-    }
+    return a.bwd ? d.C - 1 - i : i;
 }
 
-__device__ __forceinline__ void stage_steps(const Dims &d, const CarryArgs &a, int64_t b,
-                                            int64_t st0, int n, double *stage)
+// Phi (D x D, row-major) and s of scan step i.
+__device__ __forceinline__ void step_ops(const Dims &d, const CarryArgs &a, int64_t b, int64_t i,
+                                         const double *&P, const double *&s)
 {
-    const int64_t c_first = a.bwd ? d.C - 1 - (st0 + n - 1) : st0;
-    copy_lds(a.summ + (b * d.C + c_first) * a.SS, stage, (int64_t)n * a.SS);
-}
-
-__device__ __forceinline__ const double *stage_at(const CarryArgs &a, const double *stage, int n,
-                                                  int q)
-{
-    return stage + (int64_t)(a.bwd ? n - 1 - q : q) * a.SS;
+    const int64_t c = step_chunk(d, a, i);
+    const double *base = a.summ + (b * d.C + c) * a.SS;
+    const int64_t DD = (int64_t)a.D * a.D;
+    P = d.tv ? base : a.phi + b * (DD + (int64_t)a.R * a.D);
+    s = base + DD;
 }
 
 // (1) Block aggregates.  Workgroup (b, blk); thread e = i*(D+1) + j holds
@@ -61,10 +40,7 @@ __device__ __forceinline__ const double *stage_at(const CarryArgs &a, const doub
 __global__ void __launch_bounds__(320) k_carry_agg(Dims d, CarryArgs a)
 {
     __shared__ double Pm[2][kMaxD][kMaxD + 1];
-    __shared__ __align__(16) double stage[kStage];
-    __shared__ double phi_lti[kMaxD * kMaxD];
     const int D = a.D;
-    const int64_t DD = (int64_t)D * D;
     const int64_t blk = blockIdx.x % d.NB;
     const int64_t b = blockIdx.x / d.NB;
     const int e = threadIdx.x;
@@ -73,30 +49,21 @@ __global__ void __launch_bounds__(320) k_carry_agg(Dims d, CarryArgs a)
     const int j = act ? e % (D + 1) : 0;
     if (act)
         Pm[0][i][j] = (j == i) ? 1.0 : 0.0;
-    if (!d.tv)
-        for (int q = e; q < DD; q += blockDim.x)
-            phi_lti[q] = a.phi[b * (DD + (int64_t)a.R * D) + q];
+    __syncthreads();
     const int64_t i0 = blk * d.G;
     const int64_t i1 = min(i0 + d.G, d.C - 1);
-    const int per = (int)max((int64_t)1, (int64_t)kStage / a.SS);
     int cur = 0;
-    for (int64_t st0 = i0; st0 < i1; st0 += per) {
-        const int n = (int)min((int64_t)per, i1 - st0);
-        __syncthreads();
-        stage_steps(d, a, b, st0, n, stage);
-        __syncthreads();
-        for (int q = 0; q < n; ++q) {
-            const double *P = d.tv ? stage_at(a, stage, n, q) : phi_lti;
-            const double *sv = stage_at(a, stage, n, q) + DD;
-            if (act) {
-                double acc = (j == D) ? sv[i] : 0.0;
-                for (int k = 0; k < D; ++k)
-                    acc += P[i * D + k] * Pm[cur][k][j];
-                Pm[cur ^ 1][i][j] = acc;
-            }
-            cur ^= 1;
-            __syncthreads();
+    for (int64_t st = i0; st < i1; ++st) {
+        const double *P, *s;
+        step_ops(d, a, b, st, P, s);
+        if (act) {
+            double acc = (j == D) ? s[i] : 0.0;
+            for (int k = 0; k < D; ++k)
+                acc += P[i * D + k] * Pm[cur][k][j];
+            Pm[cur ^ 1][i][j] = acc;
         }
+        cur ^= 1;
+        __syncthreads();
     }
     if (act) {
         double *o = a.agg + (b * d.NB + blk) * (int64_t)(D * D + D);
@@ -114,9 +81,7 @@ __global__ void __launch_bounds__(64)
 k_carry_blocks(Dims d, CarryArgs a, const void *init, int init_f64)
 {
     __shared__ double v[2][kMaxD];
-    __shared__ __align__(16) double stage[kStage];
     const int D = a.D;
-    const int64_t AS = (int64_t)D * D + D;
     const int64_t b = blockIdx.x;
     const int i = threadIdx.x;
     const bool act = i < D;
@@ -127,25 +92,19 @@ k_carry_blocks(Dims d, CarryArgs a, const void *init, int init_f64)
                           : (double)((const float *)init)[b * D + i];
         v[0][i] = x0;
     }
-    const int per = (int)max((int64_t)1, (int64_t)kStage / AS);
+    __syncthreads();
     int cur = 0;
-    for (int64_t blk0 = 0; blk0 < d.NB; blk0 += per) {
-        const int n = (int)min((int64_t)per, d.NB - blk0);
-        __syncthreads();
-        copy_lds(a.agg + (b * d.NB + blk0) * AS, stage, n * AS);
-        __syncthreads();
-        for (int q = 0; q < n; ++q) {
-            if (act) {
-                a.bstart[(b * d.NB + blk0 + q) * D + i] = v[cur][i];
-                const double *o = stage + q * AS;
-                double acc = o[D * D + i];
-                for (int k = 0; k < D; ++k)
-                    acc += o[i * D + k] * v[cur][k];
-                v[cur ^ 1][i] = acc;
-            }
-            cur ^= 1;
-            __syncthreads();
+    for (int64_t blk = 0; blk < d.NB; ++blk) {
+        if (act) {
+            a.bstart[(b * d.NB + blk) * D + i] = v[cur][i];
+            const double *o = a.agg + (b * d.NB + blk) * (int64_t)(D * D + D);
+            double acc = o[D * D + i];
+            for (int k = 0; k < D; ++k)
+                acc += o[i * D + k] * v[cur][k];
+            v[cur ^ 1][i] = acc;
         }
+        cur ^= 1;
+        __syncthreads();
     }
 }
 
@@ -157,8 +116,6 @@ k_carry_blocks(Dims d, CarryArgs a, const void *init, int init_f64)
 __global__ void __launch_bounds__(64) k_carry_fill(Dims d, CarryArgs a)
 {
     __shared__ double v[2][kMaxD];
-    __shared__ __align__(16) double stage[kStage];
-    __shared__ double phi_lti[kMaxD * kMaxD + kMaxD * kMaxD];
     const int D = a.D;
     const int R = a.R;
     const int SD = D + R;
@@ -168,42 +125,34 @@ __global__ void __launch_bounds__(64) k_carry_fill(Dims d, CarryArgs a)
     const int i = threadIdx.x;
     if (i < D)
         v[0][i] = a.bstart[(b * d.NB + blk) * D + i];
-    if (!d.tv)
-        for (int q = i; q < DD + (int64_t)R * D; q += blockDim.x)
-            phi_lti[q] = a.phi[b * (DD + (int64_t)R * D) + q];
+    __syncthreads();
     const int64_t i0 = blk * d.G;
     const int64_t i1 = min(i0 + d.G, d.C - 1);
-    const int per = (int)max((int64_t)1, (int64_t)kStage / a.SS);
     int cur = 0;
-    for (int64_t st0 = i0; st0 < i1; st0 += per) {
-        const int n = (int)min((int64_t)per, i1 - st0);
-        __syncthreads();
-        stage_steps(d, a, b, st0, n, stage);
-        __syncthreads();
-        for (int q = 0; q < n; ++q) {
-            const int64_t st = st0 + q;
-            const double *base = stage_at(a, stage, n, q);
-            const double *P = d.tv ? base : phi_lti;
-            const int64_t cn = a.bwd ? d.C - 2 - st : st + 1;
-            double *o = a.states + (b * d.C + cn) * SD;
-            if (i < D) {
-                double acc = base[DD + i];
-                for (int k = 0; k < D; ++k)
-                    acc += P[i * D + k] * v[cur][k];
-                v[cur ^ 1][i] = acc;
-                o[i] = acc;
-            } else if (i < SD) {
-                const int qq = i - D;
-                const double *Rm = d.tv ? base + DD + D : phi_lti + DD;
-                const double *r0 = base + DD + D + (int64_t)R * D;
-                double acc = r0[qq];
-                for (int k = 0; k < D; ++k)
-                    acc += Rm[qq * D + k] * v[cur][k];
-                o[D + qq] = acc;
-            }
-            cur ^= 1;
-            __syncthreads();
+    for (int64_t st = i0; st < i1; ++st) {
+        const double *P, *s;
+        step_ops(d, a, b, st, P, s);
+        const int64_t cn = a.bwd ? d.C - 2 - st : st + 1;
+        double *o = a.states + (b * d.C + cn) * SD;
+        if (i < D) {
+            double acc = s[i];
+            for (int k = 0; k < D; ++k)
+                acc += P[i * D + k] * v[cur][k];
+            v[cur ^ 1][i] = acc;
+            o[i] = acc;
+        } else if (i < SD) {
+            const int q = i - D;
+            const int64_t c = step_chunk(d, a, st);
+            const double *base = a.summ + (b * d.C + c) * a.SS;
+            const double *Rm = d.tv ? base + DD + D : a.phi + b * (DD + (int64_t)R * D) + DD;
+            const double *r0 = base + DD + D + (int64_t)R * D;
+            double acc = r0[q];
+            for (int k = 0; k < D; ++k)
+                acc += Rm[q * D + k] * v[cur][k];
+            o[D + q] = acc;
         }
+        cur ^= 1;
+        __syncthreads();
     }
 }
 
@@ -254,7 +203,7 @@ filt_status carry_run(const Dims &d, const CarryArgs &a, const void *init, bool 
 {
     if (d.C < 2)
         return FILT_OK;
-    if (a.D < 1 || a.D > kMaxD || a.D + a.R > 64 || a.SS > kStage)
+    if (a.D < 1 || a.D > kMaxD || a.D + a.R > 64)
         return fail(FILT_EUNSUPPORTED, "carry order %d (+%d)", a.D, a.R);
     const int agg_threads = ((a.D * (a.D + 1) + 63) / 64) * 64;
     FILT_LAUNCH("carry_agg", k_carry_agg, dim3((unsigned)(d.B * d.NB)), dim3(agg_threads), 0, st,
