@@ -114,6 +114,63 @@ filt_status filt_backward_f64(const filt_problem *p, const double *gy, const dou
                               double *ga, double *gxi, double *gyi, void *ws, size_t ws_bytes,
                               void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched ragged filtering: many independent all-pole filters (M = 0,
+ * b = [1]) with per-sample coefficients, of different lengths and orders,
+ * packed into flat arrays and run by one plan.  This is the batching of the
+ * method across uneven filters (one launch per phase and order bucket,
+ * optionally replayed as one HIP graph) with chunk lengths picked by an
+ * autotuner; each filter computes exactly what filt_forward / filt_backward
+ * compute for it with B = 1 in the [B][T] layout.
+ *
+ * Segment i covers samples [x_off, x_off + T) of x / y / gy / gx, its
+ * coefficient rows a[a_off + t*N .. a_off + t*N + N) for t < T (a_1..a_N of
+ * time t) and its initial conditions yi[ic_off .. ic_off + N) (y[-1] first).
+ * Segments must not overlap in the outputs.  Coefficient blocks that start on
+ * a multiple of 4 floats (16 bytes) are read as whole vectors.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t x_off;  /* first sample in x, y, gy, gx */
+    int64_t T;      /* samples (>= 0) */
+    int64_t a_off;  /* first coefficient in a / ga */
+    int64_t ic_off; /* first initial condition in yi / gyi */
+    int32_t N;      /* order, 0 <= N <= 16 */
+    int32_t reserved;
+} filt_segment;
+
+typedef struct filt_plan filt_plan;
+
+/* Build a plan (host call; allocates its device tables and workspace and
+ * synchronises).  segs is a host array of nseg segments.  chunks: NULL for
+ * the defaults, else a host array of 5 chunk lengths (multiples of 32) for
+ * the order buckets N <= 1, 2, 4, 8, 16. */
+filt_status filt_plan_create(const filt_segment *segs, int32_t nseg, const int32_t *chunks,
+                             filt_plan **out);
+void filt_plan_destroy(filt_plan *p);
+
+/* Forward / backward of every segment, asynchronous on stream, no
+ * allocation.  Backward: ga (per-sample, the layout of a) and gyi may be NULL;
+ * y is needed for ga.  gx may be NULL. */
+filt_status filt_plan_forward(filt_plan *p, const float *x, const float *a, const float *yi,
+                              float *y, void *stream);
+filt_status filt_plan_backward(filt_plan *p, const float *gy, const float *y, const float *a,
+                               const float *yi, float *gx, float *ga, float *gyi, void *stream);
+
+/* Autotuner: for each order bucket, time forward + backward of that bucket's
+ * segments for several chunk lengths (HIP events, median of 3) and keep the
+ * fastest; then re-lay the plan.  Synchronises; the outputs are scratch. */
+filt_status filt_plan_tune(filt_plan *p, const float *x, const float *a, const float *yi,
+                           const float *gy, float *y, float *gx, float *ga, float *gyi,
+                           void *stream);
+filt_status filt_plan_get_chunks(const filt_plan *p, int32_t *chunks /* host, 5 */);
+
+/* Capture forward + backward on these buffers into a HIP graph (the stream
+ * must not be capturing already), and replay it. */
+filt_status filt_plan_capture(filt_plan *p, const float *x, const float *a, const float *yi,
+                              const float *gy, float *y, float *gx, float *ga, float *gyi,
+                              void *stream);
+filt_status filt_plan_replay(filt_plan *p, void *stream);
+
 /* Chunk length the library picks for *p when p->chunk == 0 (for tests and
  * tuning).  Host-only; returns 0 for an invalid problem. */
 int64_t filt_auto_chunk(const filt_problem *p);

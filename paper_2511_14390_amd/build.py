@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import re
 import os
 import subprocess
 import sys
@@ -63,6 +64,8 @@ def _instantiation_units():
                              f"FILT_DECLARE_FWD({w}, {io}, {acc}, )"))
             out.append(_unit(f"apply_w{w}_{io}_{acc}_bwd.hip", "apply.h",
                              f"FILT_DECLARE_BWD({w}, {io}, {acc}, )"))
+    for w in (1, 2, 4, 8, 16):
+        out.append(_unit(f"batched_w{w}.hip", "batched.h", f"FILT_DECLARE_BATCHED({w}, )"))
     return out
 
 
@@ -96,7 +99,11 @@ def build(jobs: int | None = None, verbose: bool = False, incremental: bool = Fa
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 1, 16)
     # longest units first so the pool stays busy
-    srcs.sort(key=lambda p: (-int(p.split("_w")[1].split("_")[0]) if "_w" in p else 0))
+    def cost(p):
+        m = re.search(r"_w(\d+)", os.path.basename(p))
+        return -int(m.group(1)) if m else 0
+
+    srcs.sort(key=cost)
     with cf.ThreadPoolExecutor(jobs) as ex:
         results = list(ex.map(lambda p: _compile(p, incremental), srcs))
     if verbose:

@@ -17,18 +17,15 @@ namespace filt_detail {
 // ---------------------------------------------------------------- forward
 
 template <int W, bool TV, bool FIR, bool AV, typename io_t, typename acc_t>
-__global__ void __launch_bounds__(kThreads)
-k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
-            const io_t *__restrict__ bc, const io_t *__restrict__ ac,
-            const io_t *__restrict__ yi, const double *__restrict__ hin, io_t *__restrict__ y)
+__device__ __forceinline__ void fwd_apply_item(const Dims &d, const io_t *__restrict__ x,
+                                               const io_t *__restrict__ xi,
+                                               const io_t *__restrict__ bc,
+                                               const io_t *__restrict__ ac,
+                                               const io_t *__restrict__ yi,
+                                               const double *__restrict__ hin,
+                                               io_t *__restrict__ y, int64_t b, int64_t c)
 {
     constexpr int m = W - 1;
-    const int64_t total = d.B * d.C;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total)
-        return;
-    int64_t b, c, jj;
-    decode(d, idx, d.C, b, c, jj);
     const int64_t t0 = c * d.L;
     acc_t la[W + 1], lb[W];
     if constexpr (!TV)
@@ -123,6 +120,20 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
     }
 }
 
+template <int W, bool TV, bool FIR, bool AV, typename io_t, typename acc_t>
+__global__ void __launch_bounds__(kThreads)
+k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
+            const io_t *__restrict__ bc, const io_t *__restrict__ ac,
+            const io_t *__restrict__ yi, const double *__restrict__ hin, io_t *__restrict__ y)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= d.B * d.C)
+        return;
+    int64_t b, c, jj;
+    decode(d, idx, d.C, b, c, jj);
+    fwd_apply_item<W, TV, FIR, AV, io_t, acc_t>(d, x, xi, bc, ac, yi, hin, y, b, c);
+}
+
 // ---------------------------------------------------------------- backward
 
 // gin[(b*C + c)*(N+M)] holds the (s, r) state entering chunk c from the
@@ -134,21 +145,14 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
 // Time-invariant filters write per-(b, c) FP64 partial sums to
 // part[(b*C + c)*(N+M+1)] = (ga_1..ga_N, gb_0..gb_M).  Chunk 0 writes gyi / gxi.
 template <int W, bool TV, bool FIR, bool GA, bool GB, bool AV, typename io_t, typename acc_t>
-__global__ void __launch_bounds__(kThreads)
-k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
-            const io_t *__restrict__ xi, const io_t *__restrict__ y,
-            const io_t *__restrict__ yi, const io_t *__restrict__ bc,
-            const io_t *__restrict__ ac, const double *__restrict__ gin, io_t *__restrict__ gx,
-            io_t *__restrict__ gb, io_t *__restrict__ ga, io_t *__restrict__ gxi,
-            io_t *__restrict__ gyi, double *__restrict__ part)
+__device__ __forceinline__ void bwd_apply_item(
+    const Dims &d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
+    const io_t *__restrict__ xi, const io_t *__restrict__ y, const io_t *__restrict__ yi,
+    const io_t *__restrict__ bc, const io_t *__restrict__ ac, const double *__restrict__ gin,
+    io_t *__restrict__ gx, io_t *__restrict__ gb, io_t *__restrict__ ga, io_t *__restrict__ gxi,
+    io_t *__restrict__ gyi, double *__restrict__ part, int64_t b, int64_t c)
 {
     constexpr int m = W - 1;
-    const int64_t total = d.B * d.C;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total)
-        return;
-    int64_t b, c, jj;
-    decode(d, idx, d.C, b, c, jj);
     const int64_t t0 = c * d.L;
     const int N = d.N, M = d.M;
     acc_t la[W + 1], lb[W];
@@ -352,6 +356,24 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
                 gxi[b * M + i] = (io_t)rs[(i + 2) & m];
         }
     }
+}
+
+template <int W, bool TV, bool FIR, bool GA, bool GB, bool AV, typename io_t, typename acc_t>
+__global__ void __launch_bounds__(kThreads)
+k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
+            const io_t *__restrict__ xi, const io_t *__restrict__ y,
+            const io_t *__restrict__ yi, const io_t *__restrict__ bc,
+            const io_t *__restrict__ ac, const double *__restrict__ gin, io_t *__restrict__ gx,
+            io_t *__restrict__ gb, io_t *__restrict__ ga, io_t *__restrict__ gxi,
+            io_t *__restrict__ gyi, double *__restrict__ part)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= d.B * d.C)
+        return;
+    int64_t b, c, jj;
+    decode(d, idx, d.C, b, c, jj);
+    bwd_apply_item<W, TV, FIR, GA, GB, AV, io_t, acc_t>(d, gy, x, xi, y, yi, bc, ac, gin, gx, gb,
+                                                        ga, gxi, gyi, part, b, c);
 }
 
 // ---------------------------------------------------------------- drivers

@@ -1,0 +1,263 @@
+// batched.h -- batched ragged filtering: many independent all-pole filters of
+// different lengths and orders (per-sample coefficients, M = 0) in one pass.
+//
+// Segments are grouped by register bucket W (the orders N <= W share one
+// kernel instantiation).  Every launch walks a device-side item list -- the
+// (segment, chunk[, lane]) work of one bucket -- with a grid-stride loop over
+// an occupancy-sized grid, so one launch per phase and bucket covers every
+// filter whatever its length.  The per-item arithmetic is the same device
+// code as the dense path (summary.h, carry.h, apply.h) applied to a
+// one-channel [B, T] problem at the segment's offsets.
+#pragma once
+
+#include "apply.h"
+#include "carry.h"
+#include "summary.h"
+
+namespace filt_detail {
+
+// Device-side description of one segment (offsets in elements / doubles).
+struct SegDesc {
+    int64_t x_off, T, a_off, ic_off;
+    int64_t L, C, G, NB;
+    int64_t summ_off, states_off, agg_off, bstart_off;
+    int32_t N, a_vec;
+};
+
+// One unit of work: a chunk of a segment (and, for the summaries, one of the
+// lanes that share that chunk's solves).
+struct Item {
+    int32_t seg, chunk, lane, pad;
+};
+
+__device__ __forceinline__ Dims seg_dims(const SegDesc &s)
+{
+    Dims d{};
+    d.B = 1;
+    d.T = s.T;
+    d.M = 0;
+    d.N = s.N;
+    d.tv = 1;
+    d.layout = FILT_LAYOUT_BT;
+    d.has_b = 0;
+    d.L = s.L;
+    d.C = s.C;
+    d.G = s.G;
+    d.NB = s.NB;
+    d.a_vec = s.a_vec;
+    d.ga_vec = s.a_vec;
+    return d;
+}
+
+__device__ __forceinline__ CarryArgs seg_carry(const SegDesc &s, double *ws, int bwd)
+{
+    CarryArgs a{};
+    a.summ = ws + s.summ_off;
+    a.phi = nullptr;
+    a.SS = (int64_t)s.N * s.N + s.N;
+    a.D = s.N;
+    a.R = 0;
+    a.bwd = bwd;
+    a.agg = ws + s.agg_off;
+    a.bstart = ws + s.bstart_off;
+    a.states = ws + s.states_off;
+    return a;
+}
+
+#define FILT_GRID_STRIDE(g, n)                                                                     \
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < (n);                      \
+         g += (int64_t)gridDim.x * blockDim.x)
+
+// Forward summaries: items (seg, chunk, lane) for chunks 0..C-2.
+template <int W, bool AV>
+__global__ void __launch_bounds__(kThreads)
+kb_fwd_summary(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+               const float *__restrict__ x, const float *__restrict__ a, double *__restrict__ ws)
+{
+    constexpr int S = SummarySlots<W>::value;
+    FILT_GRID_STRIDE(g, n)
+    {
+        const Item it = items[g];
+        const SegDesc sd = segs[it.seg];
+        const Dims d = seg_dims(sd);
+        const float *ap = a + sd.a_off;
+        fwd_summary_item<W, S, true, false, true, AV, float>(d, x + sd.x_off, nullptr, ap, ap, 0,
+                                                             sd.N + 1, ws + sd.summ_off, nullptr,
+                                                             0, it.chunk, it.lane);
+    }
+}
+
+// Backward summaries: items (seg, chunk, lane); the chunk summarised is
+// chunk + 1 (chunks 1..C-1 pass a state to an earlier chunk).
+template <int W, bool AV>
+__global__ void __launch_bounds__(kThreads)
+kb_bwd_summary(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+               const float *__restrict__ gy, const float *__restrict__ a, double *__restrict__ ws)
+{
+    constexpr int S = SummarySlots<W>::value;
+    FILT_GRID_STRIDE(g, n)
+    {
+        const Item it = items[g];
+        const SegDesc sd = segs[it.seg];
+        const Dims d = seg_dims(sd);
+        const float *ap = a + sd.a_off;
+        bwd_summary_item<W, S, true, false, true, AV, float>(d, gy + sd.x_off, ap, ap, 0,
+                                                             sd.N + 1, ws + sd.summ_off, nullptr,
+                                                             0, it.chunk + 1, it.lane);
+    }
+}
+
+// Forward apply: items (seg, chunk) for every chunk.
+template <int W, bool AV>
+__global__ void __launch_bounds__(kThreads)
+kb_fwd_apply(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+             const float *__restrict__ x, const float *__restrict__ a,
+             const float *__restrict__ yi, const double *__restrict__ ws, float *__restrict__ y)
+{
+    FILT_GRID_STRIDE(g, n)
+    {
+        const Item it = items[g];
+        const SegDesc sd = segs[it.seg];
+        const Dims d = seg_dims(sd);
+        const float *ap = a + sd.a_off;
+        fwd_apply_item<W, true, false, AV, float, double>(
+            d, x + sd.x_off, nullptr, ap, ap, yi != nullptr ? yi + sd.ic_off : nullptr,
+            ws + sd.states_off, y + sd.x_off, 0, it.chunk);
+    }
+}
+
+// Backward apply: items (seg, chunk); writes gx, the per-sample ga rows (GA)
+// and, from chunk 0, gyi.
+template <int W, bool AV, bool GA>
+__global__ void __launch_bounds__(kThreads)
+kb_bwd_apply(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+             const float *__restrict__ gy, const float *__restrict__ y,
+             const float *__restrict__ a, const float *__restrict__ yi,
+             const double *__restrict__ ws, float *__restrict__ gx, float *__restrict__ ga,
+             float *__restrict__ gyi)
+{
+    FILT_GRID_STRIDE(g, n)
+    {
+        const Item it = items[g];
+        const SegDesc sd = segs[it.seg];
+        const Dims d = seg_dims(sd);
+        const float *ap = a + sd.a_off;
+        bwd_apply_item<W, true, false, GA, false, AV, float, double>(
+            d, gy + sd.x_off, nullptr, nullptr, y + sd.x_off,
+            yi != nullptr ? yi + sd.ic_off : nullptr, ap, ap, ws + sd.states_off,
+            gx != nullptr ? gx + sd.x_off : nullptr, nullptr, GA ? ga + sd.a_off : nullptr, nullptr,
+            gyi != nullptr ? gyi + sd.ic_off : nullptr, nullptr, 0, it.chunk);
+    }
+}
+
+// Launch geometry of a grid-stride kernel over n items.
+inline void persistent_grid(int64_t n, unsigned &blocks, unsigned &threads)
+{
+    threads = block_for(n);
+    const int64_t want = (n + threads - 1) / threads;
+    const int64_t cap = kCUs * (threads == 64 ? 16 : 4);
+    blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
+}
+
+// One bucket's launches (defined per bucket in generated units).
+struct BucketArgs {
+    const SegDesc *segs;
+    const Item *sum_items;
+    int64_t sum_n;
+    const Item *app_items;
+    int64_t app_n;
+    int av;
+};
+
+template <int W>
+filt_status batched_fwd_summary(const BucketArgs &b, const float *x, const float *a, double *ws,
+                                hipStream_t st)
+{
+    if (b.sum_n == 0)
+        return FILT_OK;
+    unsigned g, t;
+    persistent_grid(b.sum_n, g, t);
+    if (b.av)
+        FILT_LAUNCH("batched_fwd_summary", (kb_fwd_summary<W, true>), dim3(g), dim3(t), 0, st,
+                    b.segs, b.sum_items, b.sum_n, x, a, ws);
+    else
+        FILT_LAUNCH("batched_fwd_summary", (kb_fwd_summary<W, false>), dim3(g), dim3(t), 0, st,
+                    b.segs, b.sum_items, b.sum_n, x, a, ws);
+    return check_launch("batched forward summary");
+}
+
+template <int W>
+filt_status batched_bwd_summary(const BucketArgs &b, const float *gy, const float *a, double *ws,
+                                hipStream_t st)
+{
+    if (b.sum_n == 0)
+        return FILT_OK;
+    unsigned g, t;
+    persistent_grid(b.sum_n, g, t);
+    if (b.av)
+        FILT_LAUNCH("batched_bwd_summary", (kb_bwd_summary<W, true>), dim3(g), dim3(t), 0, st,
+                    b.segs, b.sum_items, b.sum_n, gy, a, ws);
+    else
+        FILT_LAUNCH("batched_bwd_summary", (kb_bwd_summary<W, false>), dim3(g), dim3(t), 0, st,
+                    b.segs, b.sum_items, b.sum_n, gy, a, ws);
+    return check_launch("batched backward summary");
+}
+
+template <int W>
+filt_status batched_fwd_apply(const BucketArgs &b, const float *x, const float *a,
+                              const float *yi, const double *ws, float *y, hipStream_t st)
+{
+    if (b.app_n == 0)
+        return FILT_OK;
+    unsigned g, t;
+    persistent_grid(b.app_n, g, t);
+    if (b.av)
+        FILT_LAUNCH("batched_fwd_apply", (kb_fwd_apply<W, true>), dim3(g), dim3(t), 0, st, b.segs,
+                    b.app_items, b.app_n, x, a, yi, ws, y);
+    else
+        FILT_LAUNCH("batched_fwd_apply", (kb_fwd_apply<W, false>), dim3(g), dim3(t), 0, st,
+                    b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
+    return check_launch("batched forward apply");
+}
+
+template <int W>
+filt_status batched_bwd_apply(const BucketArgs &b, const float *gy, const float *y,
+                              const float *a, const float *yi, const double *ws, float *gx,
+                              float *ga, float *gyi, hipStream_t st)
+{
+    if (b.app_n == 0)
+        return FILT_OK;
+    unsigned g, t;
+    persistent_grid(b.app_n, g, t);
+#define FILT_KB_BWD(AVV, GAV)                                                                      \
+    FILT_LAUNCH("batched_bwd_apply", (kb_bwd_apply<W, AVV, GAV>), dim3(g), dim3(t), 0, st, b.segs, \
+                b.app_items, b.app_n, gy, y, a, yi, ws, gx, ga, gyi)
+    if (b.av) {
+        if (ga != nullptr)
+            FILT_KB_BWD(true, true);
+        else
+            FILT_KB_BWD(true, false);
+    } else {
+        if (ga != nullptr)
+            FILT_KB_BWD(false, true);
+        else
+            FILT_KB_BWD(false, false);
+    }
+#undef FILT_KB_BWD
+    return check_launch("batched backward apply");
+}
+
+#define FILT_DECLARE_BATCHED(W, EXT)                                                               \
+    EXT template filt_status batched_fwd_summary<W>(const BucketArgs &, const float *,             \
+                                                    const float *, double *, hipStream_t);         \
+    EXT template filt_status batched_bwd_summary<W>(const BucketArgs &, const float *,             \
+                                                    const float *, double *, hipStream_t);         \
+    EXT template filt_status batched_fwd_apply<W>(const BucketArgs &, const float *,               \
+                                                  const float *, const float *, const double *,    \
+                                                  float *, hipStream_t);                           \
+    EXT template filt_status batched_bwd_apply<W>(const BucketArgs &, const float *,               \
+                                                  const float *, const float *, const float *,     \
+                                                  const double *, float *, float *, float *,       \
+                                                  hipStream_t);
+
+}  // namespace filt_detail

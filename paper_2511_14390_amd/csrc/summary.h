@@ -106,22 +106,15 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t t0, const Curs
 //   phi[b*N*N + i*N + j]                = Phi[i][j]   (time-invariant)
 //   summ[(b*C + c)*(N*N + N) + N*N + i] = s_c[i]
 template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t>
-__global__ void __launch_bounds__(kThreads)
-k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
-              const io_t *__restrict__ bc, const io_t *__restrict__ ac, int64_t c_first,
-              int64_t ncs, int j_first, int nj, double *__restrict__ summ,
-              double *__restrict__ phi)
+__device__ __forceinline__ void fwd_summary_item(const Dims &d, const io_t *__restrict__ x,
+                                                 const io_t *__restrict__ xi,
+                                                 const io_t *__restrict__ bc,
+                                                 const io_t *__restrict__ ac, int j_first, int nj,
+                                                 double *__restrict__ summ,
+                                                 double *__restrict__ phi, int64_t b, int64_t c,
+                                                 int r)
 {
     constexpr int m = W - 1;
-    const int nl = (nj + S - 1) / S;
-    const int64_t total = d.B * ncs * nl;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total)
-        return;
-    int64_t b, cc;
-    int r;
-    decode_lanes(d, idx, ncs, nl, b, cc, r);
-    const int64_t c = c_first + cc;
     const int64_t t0 = c * d.L;
     const int N = d.N;
 
@@ -169,6 +162,24 @@ k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
                     o[(int64_t)i * N + j] = h[q][(-(i + 1)) & m];
         }
     }
+}
+
+template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t>
+__global__ void __launch_bounds__(kThreads)
+k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
+              const io_t *__restrict__ bc, const io_t *__restrict__ ac, int64_t c_first,
+              int64_t ncs, int j_first, int nj, double *__restrict__ summ,
+              double *__restrict__ phi)
+{
+    const int nl = (nj + S - 1) / S;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= d.B * ncs * nl)
+        return;
+    int64_t b, cc;
+    int r;
+    decode_lanes(d, idx, ncs, nl, b, cc, r);
+    fwd_summary_item<W, S, TV, FIR, XIN, AV>(d, x, xi, bc, ac, j_first, nj, summ, phi, b,
+                                             c_first + cc, r);
 }
 
 // ---------------------------------------------------------------- backward
@@ -256,21 +267,14 @@ __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t t0, const Curs
 // Before the first (highest) time and after the last, s_k sits in slot
 // (k + 1) mod W.
 template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t>
-__global__ void __launch_bounds__(kThreads)
-k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
-              const io_t *__restrict__ ac, int64_t c_first, int64_t ncs, int j_first, int nj,
-              double *__restrict__ summ, double *__restrict__ phi)
+__device__ __forceinline__ void bwd_summary_item(const Dims &d, const io_t *__restrict__ gy,
+                                                 const io_t *__restrict__ bc,
+                                                 const io_t *__restrict__ ac, int j_first, int nj,
+                                                 double *__restrict__ summ,
+                                                 double *__restrict__ phi, int64_t b, int64_t c,
+                                                 int r)
 {
     constexpr int m = W - 1;
-    const int nl = (nj + S - 1) / S;
-    const int64_t total = d.B * ncs * nl;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total)
-        return;
-    int64_t b, cc;
-    int r;
-    decode_lanes(d, idx, ncs, nl, b, cc, r);
-    const int64_t c = c_first + cc;
     const int64_t t0 = c * d.L;
     const int N = d.N, M = d.M;
     double la[W + 1], lb[W];
@@ -318,6 +322,23 @@ k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
             }
         }
     }
+}
+
+template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t>
+__global__ void __launch_bounds__(kThreads)
+k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
+              const io_t *__restrict__ ac, int64_t c_first, int64_t ncs, int j_first, int nj,
+              double *__restrict__ summ, double *__restrict__ phi)
+{
+    const int nl = (nj + S - 1) / S;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= d.B * ncs * nl)
+        return;
+    int64_t b, cc;
+    int r;
+    decode_lanes(d, idx, ncs, nl, b, cc, r);
+    bwd_summary_item<W, S, TV, FIR, GIN, AV>(d, gy, bc, ac, j_first, nj, summ, phi, b,
+                                             c_first + cc, r);
 }
 
 // ---------------------------------------------------------------- launch

@@ -219,3 +219,114 @@ def profile_read(max_entries: int = 64):
         nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
         out[nm] = (int(counts[i]), float(ms[i]))
     return out
+
+
+# ------------------------------------------------------------------ batched
+
+
+class FiltSegment(ctypes.Structure):
+    _fields_ = [("x_off", ctypes.c_int64), ("T", ctypes.c_int64), ("a_off", ctypes.c_int64),
+                ("ic_off", ctypes.c_int64), ("N", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def _plan_lib():
+    L = lib()
+    if not getattr(L, "_plan_ready", False):
+        P, VP = ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)
+        L.filt_plan_create.argtypes = [ctypes.POINTER(FiltSegment), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), VP]
+        L.filt_plan_create.restype = ctypes.c_int
+        L.filt_plan_destroy.argtypes = [P]
+        L.filt_plan_destroy.restype = None
+        L.filt_plan_forward.argtypes = [P] * 5 + [P]
+        L.filt_plan_forward.restype = ctypes.c_int
+        L.filt_plan_backward.argtypes = [P] * 8 + [P]
+        L.filt_plan_backward.restype = ctypes.c_int
+        L.filt_plan_tune.argtypes = [P] * 9 + [P]
+        L.filt_plan_tune.restype = ctypes.c_int
+        L.filt_plan_capture.argtypes = [P] * 9 + [P]
+        L.filt_plan_capture.restype = ctypes.c_int
+        L.filt_plan_replay.argtypes = [P, P]
+        L.filt_plan_replay.restype = ctypes.c_int
+        L.filt_plan_get_chunks.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+        L.filt_plan_get_chunks.restype = ctypes.c_int
+        L._plan_ready = True
+    return L
+
+
+class BatchedFilter:
+    """Many independent all-pole filters with per-sample coefficients, packed
+    into flat tensors (see filt_segment in include/filt.h): segment i covers
+    x[x_off[i] : x_off[i] + T[i]], its rows a[a_off[i] : a_off[i] + T[i]*N[i]]
+    ([T_i, N_i] row-major) and yi[ic_off[i] : ic_off[i] + N[i]]."""
+
+    def __init__(self, T, N, x_off, a_off, ic_off, chunks=None):
+        L = _plan_lib()
+        n = len(T)
+        segs = (FiltSegment * max(n, 1))()
+        for i in range(n):
+            segs[i] = FiltSegment(int(x_off[i]), int(T[i]), int(a_off[i]), int(ic_off[i]),
+                                  int(N[i]), 0)
+        ch = None
+        if chunks is not None:
+            ch = (ctypes.c_int32 * 5)(*[int(c) for c in chunks])
+        h = ctypes.c_void_p(0)
+        _check(L.filt_plan_create(segs, n, ch, ctypes.byref(h)))
+        self._h = h
+        self.nseg = n
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _plan_lib().filt_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def chunks(self):
+        out = (ctypes.c_int32 * 5)()
+        _check(_plan_lib().filt_plan_get_chunks(self._h, out))
+        return list(out)
+
+    def forward(self, x, a, yi=None, out=None, stream=None):
+        y = out if out is not None else torch.empty_like(x)
+        _check(_plan_lib().filt_plan_forward(self._h, _ptr(x), _ptr(a), _ptr(yi), _ptr(y),
+                                             _stream(x.device, stream)))
+        return y
+
+    def backward(self, gy, y, a, yi=None, want=("x", "a", "yi"), out=None, stream=None):
+        o = out or {}
+        gx = o.get("x", torch.empty_like(gy)) if "x" in want else None
+        ga = o.get("a", torch.zeros_like(a)) if "a" in want else None
+        gyi = (o.get("yi", torch.zeros_like(yi)) if ("yi" in want and yi is not None) else None)
+        _check(_plan_lib().filt_plan_backward(self._h, _ptr(gy), _ptr(y), _ptr(a), _ptr(yi),
+                                              _ptr(gx), _ptr(ga), _ptr(gyi),
+                                              _stream(gy.device, stream)))
+        return {k: v for k, v in (("x", gx), ("a", ga), ("yi", gyi)) if v is not None}
+
+    def tune(self, x, a, yi, gy, stream=None):
+        y = torch.empty_like(x)
+        gx = torch.empty_like(x)
+        ga = torch.zeros_like(a)
+        gyi = torch.zeros_like(yi) if yi is not None else None
+        _check(_plan_lib().filt_plan_tune(self._h, _ptr(x), _ptr(a), _ptr(yi), _ptr(gy),
+                                          _ptr(y), _ptr(gx), _ptr(ga), _ptr(gyi),
+                                          _stream(x.device, stream)))
+        return self.chunks
+
+    def capture(self, x, a, yi, gy, y, gx, ga, gyi, stream=None):
+        """Capture forward + backward on these tensors into a HIP graph."""
+        s = stream if stream is not None else torch.cuda.Stream(x.device)
+        torch.cuda.current_stream(x.device).synchronize()
+        _check(_plan_lib().filt_plan_capture(self._h, _ptr(x), _ptr(a), _ptr(yi), _ptr(gy),
+                                             _ptr(y), _ptr(gx), _ptr(ga), _ptr(gyi),
+                                             ctypes.c_void_p(s.cuda_stream)))
+        s.synchronize()
+
+    def replay(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(_plan_lib().filt_plan_replay(self._h, ctypes.c_void_p(s.cuda_stream)))

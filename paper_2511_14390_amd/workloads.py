@@ -201,7 +201,7 @@ class Segments:
     a_off: np.ndarray        # [S] int64 offsets into the packed per-sample a
     ic_off: np.ndarray       # [S] int64 offsets into yi
     x: np.ndarray            # [sum T] f32
-    a: np.ndarray            # [sum T*N] f32, per segment [T_i, N_i] row-major
+    a: np.ndarray            # packed f32, per segment [T_i, N_i] row-major at a_off
     yi: np.ndarray           # [sum N] f32
     gy: np.ndarray           # [sum T] f32
     meta: dict = field(default_factory=dict)
@@ -222,11 +222,13 @@ def config5(nseg=512, Tmin=1000, Tmax=200000, orders=(1, 2, 4, 8, 16), hop=128, 
     T = rng.integers(Tmin, Tmax + 1, nseg).astype(np.int64)
     N = rng.choice(np.asarray(orders), nseg).astype(np.int32)
     x_off = np.concatenate([[0], np.cumsum(T)[:-1]]).astype(np.int64)
-    a_off = np.concatenate([[0], np.cumsum(T * N)[:-1]]).astype(np.int64)
+    # coefficient blocks start on 16-byte boundaries (multiples of 4 floats)
+    a_len = (T * N + 3) // 4 * 4
+    a_off = np.concatenate([[0], np.cumsum(a_len)[:-1]]).astype(np.int64)
     ic_off = np.concatenate([[0], np.cumsum(N)[:-1]]).astype(np.int64)
     x = np.empty(int(T.sum()), dtype=F32)
     gy = np.empty(int(T.sum()), dtype=F32)
-    a = np.empty(int((T * N).sum()), dtype=F32)
+    a = np.zeros(int(a_len.sum()), dtype=F32)
     yi = np.empty(int(N.sum()), dtype=F32)
     for i in range(nseg):
         t, n = int(T[i]), int(N[i])

@@ -151,3 +151,16 @@ def test_python_binding_refuses_cpu_tensors():
     a = torch.zeros(2, 2)
     with pytest.raises(ValueError):
         F.filt_forward(x, a)
+
+
+def test_plan_create_rejects_bad_segments_on_host(L):
+    F._plan_lib()
+    h = ctypes.c_void_p(0)
+    bad_order = (F.FiltSegment * 1)(F.FiltSegment(0, 100, 0, 0, 17, 0))
+    assert L.filt_plan_create(bad_order, 1, None, ctypes.byref(h)) == F.FILT_EUNSUPPORTED
+    bad_len = (F.FiltSegment * 1)(F.FiltSegment(0, -1, 0, 0, 2, 0))
+    assert L.filt_plan_create(bad_len, 1, None, ctypes.byref(h)) == F.FILT_EINVAL
+    bad_chunk = (ctypes.c_int32 * 5)(48, 64, 64, 64, 64)
+    ok = (F.FiltSegment * 1)(F.FiltSegment(0, 100, 0, 0, 2, 0))
+    assert L.filt_plan_create(ok, 1, bad_chunk, ctypes.byref(h)) == F.FILT_EINVAL
+    assert L.filt_plan_create(ok, 1, None, None) == F.FILT_EINVAL
