@@ -165,9 +165,13 @@ filt_status plan_layout(filt_plan *p)
         const int S = W == 1 ? 2 : 3;  // SummarySlots
         p->sum_off[b] = (int64_t)items.size();
         for (int i = 0; i < nseg; ++i) {
-            if (bucket_of(std::max(p->segs[i].N, 1)) != b || p->segs[i].N == 0)
+            if (bucket_of(std::max(p->segs[i].N, 1)) != b)
                 continue;
+            // full-width rows only if every segment of the bucket has them
+            // (an order-0 segment has none)
             p->bucket_av[b] = p->bucket_av[b] && sd[i].a_vec;
+            if (p->segs[i].N == 0)
+                continue;
             const int nl = (sd[i].N + 1 + S - 1) / S;
             for (int64_t c = 0; c + 1 < sd[i].C; ++c)
                 for (int r = 0; r < nl; ++r)
