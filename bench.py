@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--f32-state", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (a known-size kernel for "
+                         "calibrating hardware byte counters)")
     return ap.parse_args()
 
 
@@ -178,6 +181,13 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     F.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
