@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="steps of the per-filter launch loop timed for comparison")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--layout", choices=["TB", "BT"], default=None,
+                    help="signal layout (default: the workload's own)")
     ap.add_argument("--f32-state", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -51,6 +53,19 @@ def make_problem(name):
 
     return {"ltv-allpole-n16": W.config2, "lti-allpole-n2": W.config1,
             "lti-df-m4n4": W.config3, "lti-allpole-n4-long": W.config4}[name]()
+
+
+def to_layout(p, layout):
+    """The same problem with signals (and per-sample coefficients) transposed
+    between [B, T] and [T, B]."""
+    import numpy as np
+
+    from paper_2511_14390_amd import workloads as W
+
+    sw = lambda v: None if v is None else np.ascontiguousarray(np.swapaxes(v, 0, 1))
+    a = sw(p.a) if p.a.ndim == 3 else p.a
+    b = (sw(p.b) if p.b.ndim == 3 else p.b) if p.b is not None else None
+    return W.Problem(p.name, layout, sw(p.x), a, b, p.xi, p.yi, sw(p.gy), dict(p.meta))
 
 
 def kernel_bytes(p, name):
@@ -163,6 +178,8 @@ def main():
 
     dev = torch.device("cuda:0")
     p = make_problem(args.workload)
+    if args.layout is not None and args.layout != p.layout:
+        p = to_layout(p, args.layout)
     t = lambda v, rg=False: None if v is None else torch.from_numpy(v).to(dev).requires_grad_(rg)
     x = t(p.x, True)
     a = t(p.a, True)
