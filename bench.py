@@ -178,8 +178,11 @@ def main():
 
     dev = torch.device("cuda:0")
     p = make_problem(args.workload)
-    if args.layout is not None and args.layout != p.layout:
-        p = to_layout(p, args.layout)
+    # the per-sample workload runs channel-interleaved ([T, B]): one wavefront
+    # then reads 64 channels' coefficient rows of one time step as one block
+    layout = args.layout or ("TB" if args.workload == "ltv-allpole-n16" else p.layout)
+    if layout != p.layout:
+        p = to_layout(p, layout)
     t = lambda v, rg=False: None if v is None else torch.from_numpy(v).to(dev).requires_grad_(rg)
     x = t(p.x, True)
     a = t(p.a, True)

@@ -75,14 +75,20 @@ inline int pow2_at_least(int v)
 int64_t auto_chunk(const filt_problem *p)
 {
     const int64_t B = p->B, T = p->T;
-    // aim for about 32K (channel, chunk) lanes in the apply phase
-    const int64_t target = 32768;
+    // Enough (channel, chunk) chains to keep every SIMD busy in the apply
+    // phase.  Per-sample filters pay N + 1 solves per sample in the summary
+    // whatever the chunk length, plus an N x N FP64 transition per chunk, so
+    // they take fewer, longer chunks; time-invariant filters summarise with one
+    // solve per sample and favour many short chunks.
+    const int64_t target = p->time_varying ? 32768 : 262144;
     int64_t per = (target + B - 1) / std::max<int64_t>(B, 1);
     int64_t L = (T + per - 1) / std::max<int64_t>(per, 1);
     if (p->time_varying) {
-        // every chunk stores an N x N FP64 transition: keep its 8 N^2 / L bytes
-        // per sample well below the 4 (N + M + 1) bytes of coefficients read
+        // keep the 8 (N^2 + N) / L transition bytes per sample well below
+        // the 4 (N + M + 1) bytes of coefficients
         L = std::max<int64_t>(L, 12 * (int64_t)p->N);
+    } else {
+        L = std::max<int64_t>(L, 128);
     }
     L = ((L + 31) / 32) * 32;
     return std::max<int64_t>(32, std::min<int64_t>(L, 1 << 16));

@@ -37,27 +37,35 @@ k_fir_states(Dims d, const double *__restrict__ summ, double *__restrict__ state
     states[(b * d.C + c) * M + q] = summ[(b * d.C + c + 1) * M + q];
 }
 
-// Sum the per-chunk partials of time-invariant ga / gb over chunks (FP64,
-// fixed order).
+// Sum the per-chunk partials of time-invariant ga / gb over chunks: one
+// workgroup per (channel, tap), strided partial sums then a fixed-shape tree
+// in LDS (FP64, deterministic order).
 template <typename io_t>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(256)
 k_reduce_lti(Dims d, const double *__restrict__ part, io_t *__restrict__ ga,
              io_t *__restrict__ gb)
 {
+    __shared__ double red[256];
     const int K = d.N + d.M + 1;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= d.B * K)
-        return;
-    const int64_t b = idx / K;
-    const int k = (int)(idx % K);
+    const int64_t b = blockIdx.x / K;
+    const int k = (int)(blockIdx.x % K);
     double acc = 0.0;
-    for (int64_t c = 0; c < d.C; ++c)
+    for (int64_t c = threadIdx.x; c < d.C; c += blockDim.x)
         acc += part[(b * d.C + c) * K + k];
-    if (k < d.N) {
-        if (ga != nullptr)
-            ga[b * d.N + k] = (io_t)acc;
-    } else if (gb != nullptr) {
-        gb[b * (d.M + 1) + (k - d.N)] = (io_t)acc;
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (k < d.N) {
+            if (ga != nullptr)
+                ga[b * d.N + k] = (io_t)red[0];
+        } else if (gb != nullptr) {
+            gb[b * (d.M + 1) + (k - d.N)] = (io_t)red[0];
+        }
     }
 }
 
@@ -91,13 +99,14 @@ filt_status fir_states_run(const Dims &d, const double *summ, double *states, hi
 filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb, bool f64,
                            hipStream_t st)
 {
-    const int64_t n = d.B * (d.N + d.M + 1);
+    const unsigned n = (unsigned)(d.B * (d.N + d.M + 1));
+    const unsigned t = d.C >= 256 ? 256u : 64u;
     if (f64)
-        FILT_LAUNCH("reduce_lti", (k_reduce_lti<double>), dim3(blocks_for(n)), dim3(block_for(n)), 0, st,
-                    d, part, (double *)ga, (double *)gb);
+        FILT_LAUNCH("reduce_lti", (k_reduce_lti<double>), dim3(n), dim3(t), 0, st, d, part,
+                    (double *)ga, (double *)gb);
     else
-        FILT_LAUNCH("reduce_lti", (k_reduce_lti<float>), dim3(blocks_for(n)), dim3(block_for(n)), 0, st,
-                    d, part, (float *)ga, (float *)gb);
+        FILT_LAUNCH("reduce_lti", (k_reduce_lti<float>), dim3(n), dim3(t), 0, st, d, part,
+                    (float *)ga, (float *)gb);
     return check_launch("reduce");
 }
 
