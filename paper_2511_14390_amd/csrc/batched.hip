@@ -40,25 +40,40 @@ kb_carry_agg(const SegDesc *__restrict__ segs, const Item *__restrict__ items, d
 {
     const Item it = items[blockIdx.x];
     const SegDesc sd = segs[it.seg];
-    carry_agg_body(seg_dims(sd), seg_carry(sd, ws, bwd), 0, it.chunk);
+    const Dims d = seg_dims(sd);
+    const CarryArgs a = seg_carry(sd, ws, bwd);
+    extern __shared__ double carry_stage[];
+#define CALL(DB) carry_agg_body<DB, true>(d, a, 0, it.chunk, carry_stage)
+    FILT_CARRY_DB(a.D, CALL);
+#undef CALL
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 kb_carry_blocks(const SegDesc *__restrict__ segs, const Item *__restrict__ items, double *ws,
                 int bwd, const float *__restrict__ yi)
 {
     const Item it = items[blockIdx.x];
     const SegDesc sd = segs[it.seg];
     const float *init = (!bwd && yi != nullptr) ? yi + sd.ic_off : nullptr;
-    carry_blocks_body(seg_dims(sd), seg_carry(sd, ws, bwd), init, 0, 0);
+    const Dims d = seg_dims(sd);
+    const CarryArgs a = seg_carry(sd, ws, bwd);
+    extern __shared__ double carry_stage[];
+#define CALL(DB) carry_blocks_body<DB>(d, a, init, 0, 0, carry_stage)
+    FILT_CARRY_DB(a.D, CALL);
+#undef CALL
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 kb_carry_fill(const SegDesc *__restrict__ segs, const Item *__restrict__ items, double *ws, int bwd)
 {
     const Item it = items[blockIdx.x];
     const SegDesc sd = segs[it.seg];
-    carry_fill_body(seg_dims(sd), seg_carry(sd, ws, bwd), 0, it.chunk);
+    const Dims d = seg_dims(sd);
+    const CarryArgs a = seg_carry(sd, ws, bwd);
+    extern __shared__ double carry_stage[];
+#define CALL(DB) carry_fill_body<DB, true>(d, a, 0, it.chunk, carry_stage)
+    FILT_CARRY_DB(a.D, CALL);
+#undef CALL
 }
 
 template <typename T>
@@ -94,6 +109,9 @@ struct filt_plan {
     size_t ws_doubles = 0;
     int64_t sum_off[kBuckets], sum_n[kBuckets], app_off[kBuckets], app_n[kBuckets];
     int64_t cblk_off = 0, cblk_n = 0, cseg_off = 0, cseg_n = 0;
+    // dynamic LDS (doubles) of the carry launches: the largest staged run
+    int64_t agg_lds = 0, blk_lds = 0, fill_lds = 0;
+    int max_order = 0;
     // captured forward + backward
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -188,10 +206,19 @@ filt_status plan_layout(filt_plan *p)
         p->app_n[b] = (int64_t)items.size() - p->app_off[b];
     }
     p->cblk_off = (int64_t)items.size();
+    p->agg_lds = p->blk_lds = p->fill_lds = 0;
+    p->max_order = 0;
     for (int i = 0; i < nseg; ++i)
-        if (sd[i].C > 1 && sd[i].N > 0)
+        if (sd[i].C > 1 && sd[i].N > 0) {
+            const int n = sd[i].N;
+            const CarryRec cr = carry_rec(1, n, 0, (int64_t)n * n + n);
+            p->agg_lds = std::max<int64_t>(p->agg_lds, (int64_t)stage_steps(cr.agg_len, sd[i].G) * cr.agg_len);
+            p->blk_lds = std::max<int64_t>(p->blk_lds, (int64_t)stage_steps(cr.blk_len, sd[i].NB) * cr.blk_len);
+            p->fill_lds = std::max<int64_t>(p->fill_lds, (int64_t)stage_steps(cr.fill_len, sd[i].G) * cr.fill_len);
+            p->max_order = std::max(p->max_order, n);
             for (int64_t k = 0; k < sd[i].NB; ++k)
                 items.push_back(Item{i, (int32_t)k, 0, 0});
+        }
     p->cblk_n = (int64_t)items.size() - p->cblk_off;
     p->cseg_off = (int64_t)items.size();
     for (int i = 0; i < nseg; ++i)
@@ -235,12 +262,16 @@ filt_status carry_launch(const filt_plan *p, int bwd, const float *yi, hipStream
         return FILT_OK;
     const Item *blk = p->d_items + p->cblk_off;
     const Item *seg = p->d_items + p->cseg_off;
-    FILT_LAUNCH("batched_carry_agg", kb_carry_agg, dim3((unsigned)p->cblk_n), dim3(320), 0, st,
-                p->d_segs, blk, p->d_ws, bwd);
-    FILT_LAUNCH("batched_carry_blocks", kb_carry_blocks, dim3((unsigned)p->cseg_n), dim3(64), 0,
-                st, p->d_segs, seg, p->d_ws, bwd, yi);
-    FILT_LAUNCH("batched_carry_fill", kb_carry_fill, dim3((unsigned)p->cblk_n), dim3(64), 0, st,
-                p->d_segs, blk, p->d_ws, bwd);
+    const int n = p->max_order;
+    const unsigned agg_threads = (unsigned)(((n * (n + 1) + 63) / 64) * 64);
+    FILT_LAUNCH("batched_carry_agg", kb_carry_agg, dim3((unsigned)p->cblk_n), dim3(agg_threads),
+                p->agg_lds * sizeof(double), st, p->d_segs, blk, p->d_ws, bwd);
+    FILT_LAUNCH("batched_carry_blocks", kb_carry_blocks, dim3((unsigned)p->cseg_n),
+                dim3(carry_threads(p->blk_lds, n)), p->blk_lds * sizeof(double), st, p->d_segs,
+                seg, p->d_ws, bwd, yi);
+    FILT_LAUNCH("batched_carry_fill", kb_carry_fill, dim3((unsigned)p->cblk_n),
+                dim3(carry_threads(p->fill_lds, n)), p->fill_lds * sizeof(double), st, p->d_segs,
+                blk, p->d_ws, bwd);
     return check_launch("batched carry");
 }
 

@@ -7,18 +7,33 @@ namespace {
 
 __global__ void __launch_bounds__(320) k_carry_agg(Dims d, CarryArgs a)
 {
-    carry_agg_body(d, a, blockIdx.x / d.NB, blockIdx.x % d.NB);
+    extern __shared__ double carry_stage[];
+    const int64_t b = blockIdx.x / d.NB, blk = blockIdx.x % d.NB;
+#define CALL(DB)                                                                                   \
+    (d.tv ? carry_agg_body<DB, true>(d, a, b, blk, carry_stage)                                    \
+          : carry_agg_body<DB, false>(d, a, b, blk, carry_stage))
+    FILT_CARRY_DB(a.D, CALL);
+#undef CALL
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 k_carry_blocks(Dims d, CarryArgs a, const void *init, int init_f64)
 {
-    carry_blocks_body(d, a, init, init_f64, blockIdx.x);
+    extern __shared__ double carry_stage[];
+#define CALL(DB) carry_blocks_body<DB>(d, a, init, init_f64, blockIdx.x, carry_stage)
+    FILT_CARRY_DB(a.D, CALL);
+#undef CALL
 }
 
-__global__ void __launch_bounds__(64) k_carry_fill(Dims d, CarryArgs a)
+__global__ void __launch_bounds__(256) k_carry_fill(Dims d, CarryArgs a)
 {
-    carry_fill_body(d, a, blockIdx.x / d.NB, blockIdx.x % d.NB);
+    extern __shared__ double carry_stage[];
+    const int64_t b = blockIdx.x / d.NB, blk = blockIdx.x % d.NB;
+#define CALL(DB)                                                                                   \
+    (d.tv ? carry_fill_body<DB, true>(d, a, b, blk, carry_stage)                                   \
+          : carry_fill_body<DB, false>(d, a, b, blk, carry_stage))
+    FILT_CARRY_DB(a.D, CALL);
+#undef CALL
 }
 
 // Pure FIR backward (N == 0): the FIR adjoint state entering chunk c is the
@@ -78,12 +93,18 @@ filt_status carry_run(const Dims &d, const CarryArgs &a, const void *init, bool 
         return FILT_OK;
     if (a.D < 1 || a.D > kMaxD || a.D + a.R > 64)
         return fail(FILT_EUNSUPPORTED, "carry order %d (+%d)", a.D, a.R);
+    const CarryRec cr = carry_rec(d.tv, a.D, a.R, a.SS);
+    const int64_t agg_lds = (int64_t)stage_steps(cr.agg_len, d.G) * cr.agg_len;
+    const int64_t blk_lds = (int64_t)stage_steps(cr.blk_len, d.NB) * cr.blk_len;
+    const int64_t fill_lds = (int64_t)stage_steps(cr.fill_len, d.G) * cr.fill_len;
     const int agg_threads = ((a.D * (a.D + 1) + 63) / 64) * 64;
-    FILT_LAUNCH("carry_agg", k_carry_agg, dim3((unsigned)(d.B * d.NB)), dim3(agg_threads), 0, st,
-                d, a);
-    FILT_LAUNCH("carry_blocks", k_carry_blocks, dim3((unsigned)d.B), dim3(64), 0, st, d, a, init,
+    FILT_LAUNCH("carry_agg", k_carry_agg, dim3((unsigned)(d.B * d.NB)), dim3(agg_threads),
+                agg_lds * sizeof(double), st, d, a);
+    FILT_LAUNCH("carry_blocks", k_carry_blocks, dim3((unsigned)d.B),
+                dim3(carry_threads(blk_lds, a.D)), blk_lds * sizeof(double), st, d, a, init,
                 (int)init_f64);
-    FILT_LAUNCH("carry_fill", k_carry_fill, dim3((unsigned)(d.B * d.NB)), dim3(64), 0, st, d, a);
+    FILT_LAUNCH("carry_fill", k_carry_fill, dim3((unsigned)(d.B * d.NB)),
+                dim3(carry_threads(fill_lds, a.D + a.R)), fill_lds * sizeof(double), st, d, a);
     return check_launch("carry");
 }
 
