@@ -60,6 +60,13 @@ typedef enum { FILT_LAYOUT_TB = 0, FILT_LAYOUT_BT = 1 } filt_layout;
  * poles cluster near the unit circle.  FILT_F32_STATE runs the per-sample
  * output pass in FP32 instead (the chunk transitions and the carry stay FP64). */
 #define FILT_F32_STATE 0x2
+/* Time-invariant problems in the [B][T] layout (FP32 entry points) run the
+ * chunked scan with each chunk's zero-state response computed as a
+ * lower-triangular Toeplitz matrix product on the FP32 matrix cores (chunks
+ * of 64 samples; chunk must be 0 or 64) and the chunk carry in FP64; their
+ * error is that of FP32 arithmetic over 64-term sums (about 1e-6 relative).
+ * FILT_RECURRENCE makes them use the per-lane recurrence (FP64 state) instead. */
+#define FILT_RECURRENCE 0x4
 
 typedef struct {
     int64_t B;            /* channels (>= 0); B == 0 or T == 0 is a no-op */
@@ -68,7 +75,7 @@ typedef struct {
     int32_t N;            /* feedback order: a_1..a_N, 0 <= N <= 16 */
     int32_t time_varying; /* 0: coefficients per channel; 1: per sample */
     int32_t layout;       /* filt_layout of x, y, gy, gx (and per-sample coefficients) */
-    int32_t flags;        /* FILT_F32_STATE or 0 */
+    int32_t flags;        /* FILT_F32_STATE | FILT_RECURRENCE, or 0 */
     int32_t chunk;        /* time-chunk length for the parallel scan; 0 = automatic,
                              else a multiple of 32 */
 } filt_problem;

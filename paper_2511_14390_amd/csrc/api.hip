@@ -113,7 +113,7 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
     if (p->chunk < 0 || (p->chunk % 32) != 0)
         return fail(FILT_EINVAL, "chunk must be 0 or a positive multiple of 32 (got %d)",
                     p->chunk);
-    if (p->flags & ~FILT_F32_STATE)
+    if (p->flags & ~(FILT_F32_STATE | FILT_RECURRENCE))
         return fail(FILT_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->B == 0 || p->T == 0)
         return FILT_OK;
@@ -130,9 +130,18 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
     return FILT_OK;
 }
 
-Dims make_dims(const filt_problem *p, int has_b)
+// Time-invariant [B, T] problems with FP32 data take the matrix-core path
+// unless the caller asks for the per-lane recurrence or another chunk length.
+bool tz_eligible(const filt_problem *p, bool f32_io)
+{
+    return f32_io && !p->time_varying && p->layout == FILT_LAYOUT_BT && p->N >= 1 &&
+           !(p->flags & FILT_RECURRENCE) && (p->chunk == 0 || p->chunk == kTzL);
+}
+
+Dims make_dims(const filt_problem *p, int has_b, bool f32_io)
 {
     Dims d{};
+    d.tz = tz_eligible(p, f32_io);
     d.B = p->B;
     d.T = p->T;
     d.M = p->M;
@@ -140,7 +149,7 @@ Dims make_dims(const filt_problem *p, int has_b)
     d.tv = p->time_varying;
     d.layout = p->layout;
     d.has_b = has_b;
-    d.L = p->chunk > 0 ? p->chunk : auto_chunk(p);
+    d.L = d.tz ? kTzL : (p->chunk > 0 ? p->chunk : auto_chunk(p));
     d.C = (d.T + d.L - 1) / d.L;
     const int64_t steps = std::max<int64_t>(d.C - 1, 1);
     int64_t G = 1;
@@ -197,7 +206,7 @@ filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, 
         return FILT_OK;
     if (y == nullptr)
         return fail(FILT_EINVAL, "y is NULL");
-    Dims d = make_dims(p, bc != nullptr);
+    Dims d = make_dims(p, bc != nullptr, sizeof(io_t) == 4);
     {
         const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
         const size_t vec = W >= 4 ? 16 : (size_t)W * sizeof(*ac);
@@ -213,6 +222,10 @@ filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, 
     hipStream_t st = (hipStream_t)stream;
     // without b the kernels read b_0 = 1 but still need a valid address
     const io_t *bvalid = bc != nullptr ? bc : (ac != nullptr ? ac : x);
+    if constexpr (sizeof(io_t) == 4) {
+        if (d.tz)
+            return tz_forward(d, x, bvalid, ac, xi, yi, y, w, wsa, st);
+    }
     const bool f64 = sizeof(io_t) == 8 || !(p->flags & FILT_F32_STATE);
     if (f64)
         return forward_dispatch<io_t, double>(d, W, x, bvalid, ac, xi, yi, y, wsa, st);
@@ -239,7 +252,7 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
         return fail(FILT_EINVAL, "gb requested but x is NULL");
     if (ga != nullptr && (y == nullptr || p->N == 0))
         return fail(FILT_EINVAL, "ga requested but y is NULL or N == 0");
-    Dims d = make_dims(p, bc != nullptr);
+    Dims d = make_dims(p, bc != nullptr, sizeof(io_t) == 4);
     {
         const int W = pow2_at_least(std::max(std::max(p->N, p->M + 1), 1));
         const size_t vec = W >= 4 ? 16 : (size_t)W * sizeof(*ac);
@@ -257,6 +270,10 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
     hipStream_t st = (hipStream_t)stream;
     // without b the kernels read b_0 = 1 but still need a valid address
     const io_t *bvalid = bc != nullptr ? bc : (ac != nullptr ? ac : gy);
+    if constexpr (sizeof(io_t) == 4) {
+        if (d.tz)
+            return tz_backward(d, gy, x, y, bvalid, ac, xi, yi, gx, gb, ga, gxi, gyi, w, wsa, st);
+    }
     const bool f64 = sizeof(io_t) == 8 || !(p->flags & FILT_F32_STATE);
     if (f64)
         return backward_dispatch<io_t, double>(d, W, gy, x, y, bvalid, ac, xi, yi, gx, gb, ga, gxi,
@@ -284,7 +301,8 @@ filt_status filt_workspace_bytes(const filt_problem *p, size_t *bytes)
         *bytes = 0;
         return FILT_OK;
     }
-    *bytes = ws_plan(make_dims(p, 1)).total;
+    // either data type: the matrix-core path serves FP32 data only
+    *bytes = std::max(ws_plan(make_dims(p, 1, true)).total, ws_plan(make_dims(p, 1, false)).total);
     return FILT_OK;
 }
 
@@ -292,6 +310,8 @@ int64_t filt_auto_chunk(const filt_problem *p)
 {
     if (p == nullptr || p->B <= 0 || p->T <= 0)
         return 0;
+    if (tz_eligible(p, true))
+        return kTzL;
     return p->chunk > 0 ? p->chunk : auto_chunk(p);
 }
 

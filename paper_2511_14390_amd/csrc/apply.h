@@ -415,6 +415,7 @@ filt_status forward_w(const Dims &d, const io_t *x, const io_t *bc, const io_t *
         a.summ = summ;
         a.phi = phi;
         a.SS = (int64_t)N * N + N;
+        a.soff = (int64_t)N * N;
         a.D = N;
         a.R = 0;
         a.bwd = 0;
@@ -482,6 +483,7 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
             a.summ = summ;
             a.phi = phi;
             a.SS = (int64_t)(N + 1) * (N + M);
+            a.soff = (int64_t)N * N;
             a.D = N;
             a.R = M;
             a.bwd = 1;

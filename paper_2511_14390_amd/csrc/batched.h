@@ -55,6 +55,7 @@ __device__ __forceinline__ CarryArgs seg_carry(const SegDesc &s, double *ws, int
     a.summ = ws + s.summ_off;
     a.phi = nullptr;
     a.SS = (int64_t)s.N * s.N + s.N;
+    a.soff = (int64_t)s.N * s.N;
     a.D = s.N;
     a.R = 0;
     a.bwd = bwd;

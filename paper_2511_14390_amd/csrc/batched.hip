@@ -211,7 +211,7 @@ filt_status plan_layout(filt_plan *p)
     for (int i = 0; i < nseg; ++i)
         if (sd[i].C > 1 && sd[i].N > 0) {
             const int n = sd[i].N;
-            const CarryRec cr = carry_rec(1, n, 0, (int64_t)n * n + n);
+            const CarryRec cr = carry_rec(1, n, (int64_t)n * n + n, (int64_t)n * n);
             p->agg_lds = std::max<int64_t>(p->agg_lds, (int64_t)stage_steps(cr.agg_len, sd[i].G) * cr.agg_len);
             p->blk_lds = std::max<int64_t>(p->blk_lds, (int64_t)stage_steps(cr.blk_len, sd[i].NB) * cr.blk_len);
             p->fill_lds = std::max<int64_t>(p->fill_lds, (int64_t)stage_steps(cr.fill_len, sd[i].G) * cr.fill_len);

@@ -37,25 +37,24 @@ __host__ __device__ inline int stage_steps(int rec, int64_t steps)
 }
 
 // Record layout of the chunk summaries as the carry reads them: per chunk
-// (stride SS) Phi [D x D], s [D] and, for the backward with M > 0, R [M x D]
-// and r0 [M].  Time-invariant filters keep Phi and R once per channel, so only
-// the vectors from offset D*D on are staged.
+// (stride SS) Phi [D x D] (per-sample filters), the vector s at offset soff
+// and, for the backward with M > 0, R [M x D] and r0 [M] after it.
+// Time-invariant filters keep Phi (and R) once per channel, so only the part
+// from s on is staged.
 struct CarryRec {
     int agg_off, agg_len;    // what the block aggregation reads
     int fill_off, fill_len;  // what the in-block fill reads
     int blk_len;             // one block aggregate [P | q]
 };
 
-__host__ __device__ inline CarryRec carry_rec(int tv, int D, int R, int64_t SS)
+__host__ __device__ inline CarryRec carry_rec(int tv, int D, int64_t SS, int64_t soff)
 {
     CarryRec r;
-    const int DD = D * D;
-    r.agg_off = tv ? 0 : DD;
-    r.agg_len = tv ? DD + D : D;
-    r.fill_off = tv ? 0 : DD;
+    r.agg_off = tv ? 0 : (int)soff;
+    r.agg_len = tv ? (int)soff + D : D;
+    r.fill_off = r.agg_off;
     r.fill_len = (int)SS - r.fill_off;
-    (void)R;
-    r.blk_len = DD + D;
+    r.blk_len = D * D + D;
     return r;
 }
 
@@ -110,7 +109,7 @@ __device__ __forceinline__ void carry_agg_body(const Dims &d, const CarryArgs &a
     __shared__ double Pm[2][kMaxD][kMaxD + 1];
     const int D = a.D;
     const int DD = D * D;
-    const CarryRec cr = carry_rec(TV, D, a.R, a.SS);
+    const CarryRec cr = carry_rec(TV, D, a.SS, a.soff);
     const int e = threadIdx.x;
     const bool act = e < D * (D + 1);
     const int i = act ? e / (D + 1) : 0;
@@ -123,8 +122,8 @@ __device__ __forceinline__ void carry_agg_body(const Dims &d, const CarryArgs &a
     const int64_t i1 = min(i0 + d.G, d.C - 1);
     const int K = stage_steps(cr.agg_len, d.G);
     const double *sb = a.summ + b * d.C * a.SS;
-    // within a record: row i of Phi at i*D (per-sample), s[i] at DD + i
-    const int s_at = (TV ? DD : 0) + i;
+    // within a record: row i of Phi at i*D (per-sample), s[i] after the offset
+    const int s_at = (int)a.soff + i - cr.agg_off;
     int cur = 0;
     for (int64_t t0 = i0; t0 < i1; t0 += K) {
         const int k = (int)min<int64_t>(K, i1 - t0);
@@ -225,15 +224,16 @@ __device__ __forceinline__ void carry_fill_body(const Dims &d, const CarryArgs &
     const int R = a.R;
     const int SD = D + R;
     const int DD = D * D;
-    const CarryRec cr = carry_rec(TV, D, R, a.SS);
+    const CarryRec cr = carry_rec(TV, D, a.SS, a.soff);
     const int i = threadIdx.x;
     const bool act = i < SD;
     if (i < D)
         v[0][i] = a.bstart[(b * d.NB + blk) * D + i];
     // thread i < D: row i of Phi and s[i]; thread D + q: row q of R and r0[q]
     // (offsets within a staged record)
-    const int row_at = i < D ? i * D : DD + D + (i - D) * D;
-    const int s_at = (i < D ? DD + i : DD + D + R * D + (i - D)) - cr.fill_off;
+    const int so = (int)a.soff;
+    const int row_at = i < D ? i * D : so + D + (i - D) * D;
+    const int s_at = (i < D ? so + i : so + D + R * D + (i - D)) - cr.fill_off;
     double fixed[DB];
     {
         const double *pb = a.phi + b * (DD + (int64_t)R * D);

@@ -66,6 +66,7 @@ struct Dims {
     int64_t G, NB;  // carry: steps per block and number of blocks
     int a_vec;      // a rows are exactly W wide and vector-aligned (full-row loads)
     int ga_vec;     // same for the per-sample ga rows written by the backward
+    int tz;         // time-invariant [B, T] problem on the matrix-core path (toeplitz.hip)
 };
 
 __device__ __forceinline__ int64_t sig_at(const Dims &d, int64_t b, int64_t t)
@@ -271,6 +272,7 @@ struct CarryArgs {
     const double *summ;   // per-chunk summaries
     const double *phi;    // per-channel time-invariant Phi (and R), or null
     int64_t SS;           // stride of one chunk summary (doubles)
+    int64_t soff;         // offset of the vector s within a chunk summary
     int D;                // state size N
     int R;                // extra outputs (M for backward, 0 for forward)
     int bwd;
@@ -300,9 +302,33 @@ inline unsigned blocks_for(int64_t n)
     return (unsigned)((n + bs - 1) / bs);
 }
 
-// Workspace carve-up (all FP64), 256-byte aligned regions.
+// Time-invariant [B, T] problems on the matrix cores (toeplitz.hip): chunks
+// of kTzL samples, 64 chunks per workgroup tile.
+constexpr int kTzL = 64;
+
+__host__ __device__ inline int round4(int v) { return (v + 3) & ~3; }
+
+struct TzGeom {
+    int KH, KS, KPF;   // forward GEMM depth: input-history rows, state rows, total
+    int KW, KWp, KPB;  // backward: adjoint window max(N, M), padded, total depth
+};
+
+__host__ __device__ inline TzGeom tz_geom(int N, int M)
+{
+    TzGeom g;
+    g.KH = round4(M);
+    g.KS = round4(N);
+    g.KPF = g.KH + kTzL + g.KS;
+    g.KW = N > M ? N : M;
+    g.KWp = round4(g.KW);
+    g.KPB = kTzL + g.KWp;
+    return g;
+}
+
+// Workspace carve-up, 256-byte aligned regions (FP64 unless noted).
 struct WsPlan {
     size_t summ, phi, agg, bstart, states, part, total;
+    size_t tz_af, tz_ayb, tz_agx, tz_phib;  // matrix-core path (FP32 matrices)
 };
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -310,6 +336,32 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 inline WsPlan ws_plan(const Dims &d)
 {
     const int64_t N = d.N, M = d.M;
+    if (d.tz) {
+        const TzGeom g = tz_geom(d.N, d.M);
+        const int64_t KW = g.KW;
+        const int64_t nwg = (d.C + 63) / 64;
+        WsPlan w{};
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t o = off;
+            off = align256(off + bytes);
+            return o;
+        };
+        w.tz_af = take((size_t)(d.B * g.KPF * kTzL) * sizeof(float));
+        w.tz_ayb = take((size_t)(d.B * g.KPB * kTzL) * sizeof(float));
+        w.tz_agx = take((size_t)(d.B * g.KPB * kTzL) * sizeof(float));
+        w.phi = take((size_t)(d.B * N * N) * sizeof(double));
+        w.tz_phib = take((size_t)(d.B * KW * KW) * sizeof(double));
+        w.summ = take((size_t)(d.B * d.C * KW) * sizeof(double));
+        w.states = take((size_t)(d.B * d.C * KW) * sizeof(double));
+        // block (or 256-step tile) sums and start states of the carry
+        const int64_t nb = std::max<int64_t>(d.NB, (d.C + 254) / 256);
+        w.agg = take((size_t)(d.B * nb * (KW * KW + KW)) * sizeof(double));
+        w.bstart = take((size_t)(d.B * nb * KW) * sizeof(double));
+        w.part = take((size_t)(d.B * nwg * (N + M + 1)) * sizeof(double));
+        w.total = off + 256;
+        return w;
+    }
     const int64_t SSf = N * N + N;
     const int64_t SSb = (N + 1) * (N + M);
     WsPlan w{};
@@ -321,8 +373,10 @@ inline WsPlan ws_plan(const Dims &d)
     };
     w.summ = take((size_t)(d.B * d.C * std::max(SSf, SSb)));
     w.phi = take((size_t)(d.B * (N * N + M * N)));
-    w.agg = take((size_t)(d.B * d.NB * (N * N + N)));
-    w.bstart = take((size_t)(d.B * d.NB * std::max<int64_t>(N, 1)));
+    // block (or 256-step tile) sums and start states of the carry
+    const int64_t nb = std::max<int64_t>(d.NB, (d.C + 254) / 256);
+    w.agg = take((size_t)(d.B * nb * (N * N + N)));
+    w.bstart = take((size_t)(d.B * nb * std::max<int64_t>(N, 1)));
     w.states = take((size_t)(d.B * d.C * (N + M)));
     w.part = take((size_t)(d.B * d.C * (N + M + 1)));
     w.total = off + 256;
@@ -335,6 +389,20 @@ filt_status carry_run(const Dims &d, const CarryArgs &a, const void *init, bool 
 filt_status fir_states_run(const Dims &d, const double *summ, double *states, hipStream_t st);
 filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb, bool f64,
                            hipStream_t st);
+
+// toeplitz.hip
+struct TzPlan {
+    int KW, KPF, KPB;
+    int64_t nwg;  // workgroup tiles per channel
+};
+TzPlan tz_plan(const Dims &d);
+filt_status tz_forward(const Dims &d, const float *x, const float *bc, const float *ac,
+                       const float *xi, const float *yi, float *y, const WsPlan &w, char *ws,
+                       hipStream_t st);
+filt_status tz_backward(const Dims &d, const float *gy, const float *x, const float *y,
+                        const float *bc, const float *ac, const float *xi, const float *yi,
+                        float *gx, float *gb, float *ga, float *gxi, float *gyi, const WsPlan &w,
+                        char *ws, hipStream_t st);
 
 // Solves per lane in the per-sample chunk summaries: the lanes of one chunk
 // share every coefficient row among their solves.

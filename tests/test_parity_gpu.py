@@ -25,12 +25,13 @@ def _dev(v, dev, dtype=torch.float32):
 
 
 def run_gpu(p, dev, chunk=0, f32_state=False, dtype=torch.float32,
-            want=("x", "a", "b", "xi", "yi")):
+            want=("x", "a", "b", "xi", "yi"), recurrence=False):
     t = lambda v: _dev(v, dev, dtype)
     x, a, b, xi, yi, gy = map(t, (p.x, p.a, p.b, p.xi, p.yi, p.gy))
-    y = F.filt_forward(x, a, b, xi, yi, layout=p.layout, chunk=chunk, f32_state=f32_state)
+    y = F.filt_forward(x, a, b, xi, yi, layout=p.layout, chunk=chunk, f32_state=f32_state,
+                       recurrence=recurrence)
     g = F.filt_backward(gy, x, y, a, b, xi, yi, layout=p.layout, chunk=chunk,
-                        f32_state=f32_state, want=want)
+                        f32_state=f32_state, recurrence=recurrence, want=want)
     torch.cuda.synchronize()
     return y.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}
 
@@ -91,11 +92,12 @@ def _case(M, N, tv, layout, T):
 
 @pytest.mark.parametrize("M,N,tv,layout,T,chunk", CASES)
 def test_random_problems_several_chunks_ragged_tail(gpu_device, M, N, tv, layout, T, chunk):
-    # default FP64 state with FP32 I/O: only the final FP32 rounding differs
-    # from the oracle, so any algorithmic slip (wrong carry, index or boundary)
-    # shows up well above this tolerance
+    # FP64 state with FP32 I/O (the per-lane recurrence, also for time-invariant
+    # [B, T] problems): only the final FP32 rounding differs from the oracle, so
+    # any algorithmic slip (wrong carry, index or boundary) shows up well above
+    # this tolerance
     p = _case(M, N, tv, layout, T)
-    yg, gg = run_gpu(p, gpu_device, chunk=chunk)
+    yg, gg = run_gpu(p, gpu_device, chunk=chunk, recurrence=True)
     yo, go = run_oracle(p)
     compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6, label=f"chunk={chunk}")
 
@@ -133,6 +135,19 @@ def test_chunk_length_invariance(gpu_device):
         assert chan_rel_err(y, ref_y, "BT") <= 1e-5
         for k in g:
             assert chan_rel_err(g[k], ref_g[k], "BT") <= 1e-4, k
+
+
+@pytest.mark.parametrize("M,N,layout,T,chunk", [(3, 4, "TB", 120000, 32), (0, 9, "BT", 50000, 32),
+                                                (2, 16, "BT", 40000, 64)])
+def test_time_invariant_carry_over_many_tiles(gpu_device, M, N, layout, T, chunk):
+    # more than 256 chunk steps: the log-depth time-invariant carry sums
+    # 256-step tiles, scans the tiles and refills them (with the FIR adjoint
+    # state for M > 0), on the FP64-state recurrence path
+    p = W.random_problem(3100 + N, B=3, T=T, M=M, N=N, time_varying=False, layout=layout,
+                         rho_max=0.95)
+    yg, gg = run_gpu(p, gpu_device, chunk=chunk, recurrence=True)
+    yo, go = run_oracle(p)
+    compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6, label=f"lti-tiles chunk={chunk}")
 
 
 def test_config1_full(gpu_device):
