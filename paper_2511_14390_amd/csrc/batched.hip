@@ -35,17 +35,12 @@ int bucket_of(int N)
 
 // Carry kernels over the segment table: one workgroup per (segment, block)
 // item, or per segment for the pass over blocks.
-__global__ void __launch_bounds__(320)
+__global__ void __launch_bounds__(64)
 kb_carry_agg(const SegDesc *__restrict__ segs, const Item *__restrict__ items, double *ws, int bwd)
 {
     const Item it = items[blockIdx.x];
     const SegDesc sd = segs[it.seg];
-    const Dims d = seg_dims(sd);
-    const CarryArgs a = seg_carry(sd, ws, bwd);
-    extern __shared__ double carry_stage[];
-#define CALL(DB) carry_agg_body<DB, true>(d, a, 0, it.chunk, carry_stage)
-    FILT_CARRY_DB(a.D, CALL);
-#undef CALL
+    carry_agg_body(seg_dims(sd), seg_carry(sd, ws, bwd), 0, it.chunk);
 }
 
 __global__ void __launch_bounds__(256)
@@ -71,7 +66,7 @@ kb_carry_fill(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
     const Dims d = seg_dims(sd);
     const CarryArgs a = seg_carry(sd, ws, bwd);
     extern __shared__ double carry_stage[];
-#define CALL(DB) carry_fill_body<DB, true>(d, a, 0, it.chunk, carry_stage)
+#define CALL(DB) carry_fill_body<DB>(d, a, 0, it.chunk, carry_stage)
     FILT_CARRY_DB(a.D, CALL);
 #undef CALL
 }
@@ -110,7 +105,7 @@ struct filt_plan {
     int64_t sum_off[kBuckets], sum_n[kBuckets], app_off[kBuckets], app_n[kBuckets];
     int64_t cblk_off = 0, cblk_n = 0, cseg_off = 0, cseg_n = 0;
     // dynamic LDS (doubles) of the carry launches: the largest staged run
-    int64_t agg_lds = 0, blk_lds = 0, fill_lds = 0;
+    int64_t blk_lds = 0, fill_lds = 0;
     int max_order = 0;
     // captured forward + backward
     hipGraph_t graph = nullptr;
@@ -206,13 +201,12 @@ filt_status plan_layout(filt_plan *p)
         p->app_n[b] = (int64_t)items.size() - p->app_off[b];
     }
     p->cblk_off = (int64_t)items.size();
-    p->agg_lds = p->blk_lds = p->fill_lds = 0;
+    p->blk_lds = p->fill_lds = 0;
     p->max_order = 0;
     for (int i = 0; i < nseg; ++i)
         if (sd[i].C > 1 && sd[i].N > 0) {
             const int n = sd[i].N;
-            const CarryRec cr = carry_rec(1, n, (int64_t)n * n + n, (int64_t)n * n);
-            p->agg_lds = std::max<int64_t>(p->agg_lds, (int64_t)stage_steps(cr.agg_len, sd[i].G) * cr.agg_len);
+            const CarryRec cr = carry_rec(n, (int64_t)n * n + n);
             p->blk_lds = std::max<int64_t>(p->blk_lds, (int64_t)stage_steps(cr.blk_len, sd[i].NB) * cr.blk_len);
             p->fill_lds = std::max<int64_t>(p->fill_lds, (int64_t)stage_steps(cr.fill_len, sd[i].G) * cr.fill_len);
             p->max_order = std::max(p->max_order, n);
@@ -263,9 +257,8 @@ filt_status carry_launch(const filt_plan *p, int bwd, const float *yi, hipStream
     const Item *blk = p->d_items + p->cblk_off;
     const Item *seg = p->d_items + p->cseg_off;
     const int n = p->max_order;
-    const unsigned agg_threads = (unsigned)(((n * (n + 1) + 63) / 64) * 64);
-    FILT_LAUNCH("batched_carry_agg", kb_carry_agg, dim3((unsigned)p->cblk_n), dim3(agg_threads),
-                p->agg_lds * sizeof(double), st, p->d_segs, blk, p->d_ws, bwd);
+    FILT_LAUNCH("batched_carry_agg", kb_carry_agg, dim3((unsigned)p->cblk_n), dim3(64), 0, st,
+                p->d_segs, blk, p->d_ws, bwd);
     FILT_LAUNCH("batched_carry_blocks", kb_carry_blocks, dim3((unsigned)p->cseg_n),
                 dim3(carry_threads(p->blk_lds, n)), p->blk_lds * sizeof(double), st, p->d_segs,
                 seg, p->d_ws, bwd, yi);

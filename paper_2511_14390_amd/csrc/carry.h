@@ -1,21 +1,22 @@
-// carry.h -- device bodies of the carry scan (phase 2), shared by the
-// dense kernels in carry.hip and the batched kernels in batched.hip.
+// carry.h -- device bodies of the carry scan (phase 2) for per-sample
+// coefficients, shared by the dense kernels in carry.hip and the batched
+// kernels in batched.hip (time-invariant filters use the log-depth scan in
+// carry.hip).
 //
 // Chunk summaries (Phi_c, s_c) combine with the operator of Sec. 3.2,
 // (Phi, s) then (Phi', s') = (Phi' Phi, Phi' s + s').  The scan is blocked:
 //   (1) carry_agg    every block of G consecutive steps is reduced to one
-//                    affine map (one workgroup per block, the running
-//                    D x (D+1) matrix in LDS, one thread per entry);
+//                    affine map (one wavefront per block, the running
+//                    [P | q] in MFMA registers);
 //   (2) carry_blocks one pass per channel over the blocks gives the state at
 //                    every block start (one workgroup per channel);
 //   (3) carry_fill   every block replays its steps from that state and writes
 //                    the state entering each chunk (one workgroup per block).
-// Each step is a short dependent chain, so a workgroup first copies the
-// records of a run of steps from HBM into LDS with every thread loading
-// (many loads in flight, one memory latency per run) and then walks the steps
-// out of LDS.  For a time-invariant filter Phi (and R) are the same for every
-// chunk and stay in registers; only the vectors are staged.
-// All arithmetic is FP64.  D = the filter order N (<= 16).
+// Steps (2) and (3) are chains of matrix-vector products: a workgroup first
+// copies the records of a run of steps from HBM into LDS with every thread
+// loading (many loads in flight, one memory latency per run) and then walks
+// the steps out of LDS.  All arithmetic is FP64.  D = the filter order N
+// (<= 16).
 #pragma once
 
 #include "common.h"
@@ -24,8 +25,9 @@ namespace filt_detail {
 
 constexpr int kMaxD = 16;
 
-// LDS budget of one staged run of step records, in doubles (32 KiB).
-constexpr int kStageDoubles = 4096;
+// LDS budget of one staged run of step records, in doubles (36 KiB: 16
+// steps of an order-16 summary).
+constexpr int kStageDoubles = 4608;
 
 // Steps per staged run for records of `rec` doubles, out of `steps`.
 __host__ __device__ inline int stage_steps(int rec, int64_t steps)
@@ -37,23 +39,17 @@ __host__ __device__ inline int stage_steps(int rec, int64_t steps)
 }
 
 // Record layout of the chunk summaries as the carry reads them: per chunk
-// (stride SS) Phi [D x D] (per-sample filters), the vector s at offset soff
-// and, for the backward with M > 0, R [M x D] and r0 [M] after it.
-// Time-invariant filters keep Phi (and R) once per channel, so only the part
-// from s on is staged.
+// (stride SS) Phi [D x D], the vector s at offset soff and, for the backward
+// with M > 0, R [M x D] and r0 [M] after it.  The fill stages whole records.
 struct CarryRec {
-    int agg_off, agg_len;    // what the block aggregation reads
-    int fill_off, fill_len;  // what the in-block fill reads
-    int blk_len;             // one block aggregate [P | q]
+    int fill_len;  // doubles of one chunk record
+    int blk_len;   // one block aggregate [P | q]
 };
 
-__host__ __device__ inline CarryRec carry_rec(int tv, int D, int64_t SS, int64_t soff)
+__host__ __device__ inline CarryRec carry_rec(int D, int64_t SS)
 {
     CarryRec r;
-    r.agg_off = tv ? 0 : (int)soff;
-    r.agg_len = tv ? (int)soff + D : D;
-    r.fill_off = r.agg_off;
-    r.fill_len = (int)SS - r.fill_off;
+    r.fill_len = (int)SS;
     r.blk_len = D * D + D;
     return r;
 }
@@ -89,72 +85,90 @@ __device__ __forceinline__ void stage_records(const double *__restrict__ base, i
     }
 }
 
-// Row `row` (D entries, zero padded to DB) of a constant matrix, in registers.
-template <int DB>
-__device__ __forceinline__ void const_row(const double *row, int D, double (&r)[DB])
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ doublex4 mfma_f64(double a, double b, doublex4 c)
 {
-#pragma unroll
-    for (int k = 0; k < DB; ++k)
-        r[k] = (row != nullptr && k < D) ? row[k] : 0.0;
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// (1) Block aggregates.  Workgroup (b, blk); thread e = i*(D+1) + j holds
-// entry (i, j) of [P | q]: column j < D of the block's matrix, column D its
-// vector.  agg[(b*NB + blk)*(D*D + D) + i*D + j] = P[i][j], [... + D*D + i] = q[i].
-// stage: dynamic LDS of stage_steps(agg_len, G) * agg_len doubles.
-template <int DB, bool TV>
+// (1) Block aggregates of per-sample transitions, on the FP64 matrix cores.
+// One wavefront per (b, blk).  The running [P | q] is held as two 16 x 16
+// tiles (zero-padded past D; q in column 0 of the second) in the output
+// layout of the FP64 16x16x4 MFMA: lane l has rows 4 r + l / 16 (r < 4) of
+// column l % 16.  A step multiplies both by Phi_c with four 16x16x4 products
+// each; product s takes k = 4 s + l / 16, so its B operand is register r = s
+// of the same lane and the chain never leaves registers.  The operands of the
+// next steps are fetched kCarryPrefetch steps ahead.
+// agg[(b*NB + blk)*(D*D + D) + i*D + j] = P[i][j], [... + D*D + i] = q[i].
+constexpr int kCarryPrefetch = 4;
+
+struct CarryOps {
+    double f[4];  // Phi_c[l % 16][4 s + l / 16]
+    double s[4];  // s_c[4 r + l / 16] in column 0, else 0
+};
+
 __device__ __forceinline__ void carry_agg_body(const Dims &d, const CarryArgs &a, int64_t b,
-                                               int64_t blk, double *stage)
+                                               int64_t blk)
 {
-    __shared__ double Pm[2][kMaxD][kMaxD + 1];
+    constexpr int PD = kCarryPrefetch;
     const int D = a.D;
-    const int DD = D * D;
-    const CarryRec cr = carry_rec(TV, D, a.SS, a.soff);
-    const int e = threadIdx.x;
-    const bool act = e < D * (D + 1);
-    const int i = act ? e / (D + 1) : 0;
-    const int j = act ? e % (D + 1) : 0;
-    if (act)
-        Pm[0][i][j] = (j == i) ? 1.0 : 0.0;
-    double fixed[DB];
-    const_row<DB>(TV ? nullptr : a.phi + b * (DD + (int64_t)a.R * D) + i * D, D, fixed);
+    const int l = threadIdx.x & 63;
+    const int j = l & 15, g = l >> 4;
+    doublex4 P, q;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        P[r] = (4 * r + g == j && j < D) ? 1.0 : 0.0;
+        q[r] = 0.0;
+    }
     const int64_t i0 = blk * d.G;
     const int64_t i1 = min(i0 + d.G, d.C - 1);
-    const int K = stage_steps(cr.agg_len, d.G);
-    const double *sb = a.summ + b * d.C * a.SS;
-    // within a record: row i of Phi at i*D (per-sample), s[i] after the offset
-    const int s_at = (int)a.soff + i - cr.agg_off;
-    int cur = 0;
-    for (int64_t t0 = i0; t0 < i1; t0 += K) {
-        const int k = (int)min<int64_t>(K, i1 - t0);
-        const int64_t c_lo = a.bwd ? d.C - t0 - k : t0;
-        __syncthreads();
-        stage_records(sb, a.SS, c_lo, k, cr.agg_off, cr.agg_len, stage);
-        __syncthreads();
-        for (int q = 0; q < k; ++q) {
-            if (act) {
-                const double *rec = stage + (a.bwd ? k - 1 - q : q) * cr.agg_len;
-                double acc0 = (j == D) ? rec[s_at] : 0.0;
-                double acc1 = 0.0;
+    auto fetch = [&](int64_t st, CarryOps &o) {
+        const int64_t c = a.bwd ? d.C - 1 - st : st;
+        const double *base = a.summ + (b * d.C + c) * a.SS;
 #pragma unroll
-                for (int k2 = 0; k2 < DB; k2 += 2) {
-                    if (k2 < D)
-                        acc0 += (TV ? rec[i * D + k2] : fixed[k2]) * Pm[cur][k2][j];
-                    if (k2 + 1 < D)
-                        acc1 += (TV ? rec[i * D + k2 + 1] : fixed[k2 + 1]) * Pm[cur][k2 + 1][j];
-                }
-                Pm[cur ^ 1][i][j] = acc0 + acc1;
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * t + g;
+            o.f[t] = (j < D && k < D) ? base[j * D + k] : 0.0;
+            o.s[t] = (j == 0 && k < D) ? base[a.soff + k] : 0.0;
+        }
+    };
+    CarryOps buf[PD];
+#pragma unroll
+    for (int t = 0; t < PD; ++t)
+        if (i0 + t < i1)
+            fetch(i0 + t, buf[t]);
+    for (int64_t base = i0; base < i1; base += PD) {
+#pragma unroll
+        for (int t = 0; t < PD; ++t) {
+            const int64_t st = base + t;
+            if (st < i1) {
+                const CarryOps o = buf[t];
+                if (st + PD < i1)
+                    fetch(st + PD, buf[t]);
+                doublex4 Pn = {0.0, 0.0, 0.0, 0.0};
+                doublex4 qn = {o.s[0], o.s[1], o.s[2], o.s[3]};
+                Pn = mfma_f64(o.f[0], P[0], Pn);
+                qn = mfma_f64(o.f[0], q[0], qn);
+                Pn = mfma_f64(o.f[1], P[1], Pn);
+                qn = mfma_f64(o.f[1], q[1], qn);
+                Pn = mfma_f64(o.f[2], P[2], Pn);
+                qn = mfma_f64(o.f[2], q[2], qn);
+                Pn = mfma_f64(o.f[3], P[3], Pn);
+                qn = mfma_f64(o.f[3], q[3], qn);
+                P = Pn;
+                q = qn;
             }
-            cur ^= 1;
-            __syncthreads();
         }
     }
-    if (act) {
-        double *o = a.agg + (b * d.NB + blk) * (int64_t)(DD + D);
-        if (j < D)
-            o[i * D + j] = Pm[cur][i][j];
-        else
-            o[DD + i] = Pm[cur][i][D];
+    double *o = a.agg + (b * d.NB + blk) * (int64_t)(D * D + D);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + g;
+        if (i < D && j < D)
+            o[i * D + j] = P[r];
+        if (i < D && j == 0)
+            o[D * D + i] = q[r];
     }
 }
 
@@ -215,7 +229,7 @@ __device__ __forceinline__ void carry_blocks_body(const Dims &d, const CarryArgs
 // the chunk the step crosses, S the state entering that chunk).  Writes
 // states[(b*C + cn)*(D + R)] for the chunk cn entered after each step.
 // stage: stage_steps(fill_len, G) * fill_len doubles.
-template <int DB, bool TV>
+template <int DB>
 __device__ __forceinline__ void carry_fill_body(const Dims &d, const CarryArgs &a, int64_t b,
                                                 int64_t blk, double *stage)
 {
@@ -224,7 +238,7 @@ __device__ __forceinline__ void carry_fill_body(const Dims &d, const CarryArgs &
     const int R = a.R;
     const int SD = D + R;
     const int DD = D * D;
-    const CarryRec cr = carry_rec(TV, D, a.SS, a.soff);
+    const CarryRec cr = carry_rec(D, a.SS);
     const int i = threadIdx.x;
     const bool act = i < SD;
     if (i < D)
@@ -233,13 +247,7 @@ __device__ __forceinline__ void carry_fill_body(const Dims &d, const CarryArgs &
     // (offsets within a staged record)
     const int so = (int)a.soff;
     const int row_at = i < D ? i * D : so + D + (i - D) * D;
-    const int s_at = (i < D ? so + i : so + D + R * D + (i - D)) - cr.fill_off;
-    double fixed[DB];
-    {
-        const double *pb = a.phi + b * (DD + (int64_t)R * D);
-        const double *row = i < D ? pb + i * D : pb + DD + (i - D) * D;
-        const_row<DB>((!TV && act) ? row : nullptr, D, fixed);
-    }
+    const int s_at = i < D ? so + i : so + D + R * D + (i - D);
     const int64_t i0 = blk * d.G;
     const int64_t i1 = min(i0 + d.G, d.C - 1);
     const int K = stage_steps(cr.fill_len, d.G);
@@ -250,7 +258,7 @@ __device__ __forceinline__ void carry_fill_body(const Dims &d, const CarryArgs &
         const int k = (int)min<int64_t>(K, i1 - t0);
         const int64_t c_lo = a.bwd ? d.C - t0 - k : t0;
         __syncthreads();
-        stage_records(sb, a.SS, c_lo, k, cr.fill_off, cr.fill_len, stage);
+        stage_records(sb, a.SS, c_lo, k, 0, cr.fill_len, stage);
         __syncthreads();
         for (int q = 0; q < k; ++q) {
             if (act) {
@@ -260,9 +268,9 @@ __device__ __forceinline__ void carry_fill_body(const Dims &d, const CarryArgs &
 #pragma unroll
                 for (int k2 = 0; k2 < DB; k2 += 2) {
                     if (k2 < D)
-                        acc0 += (TV ? rec[row_at + k2] : fixed[k2]) * v[cur][k2];
+                        acc0 += rec[row_at + k2] * v[cur][k2];
                     if (k2 + 1 < D)
-                        acc1 += (TV ? rec[row_at + k2 + 1] : fixed[k2 + 1]) * v[cur][k2 + 1];
+                        acc1 += rec[row_at + k2 + 1] * v[cur][k2 + 1];
                 }
                 const double acc = acc0 + acc1;
                 const int64_t st = t0 + q;

@@ -5,15 +5,9 @@
 namespace filt_detail {
 namespace {
 
-__global__ void __launch_bounds__(320) k_carry_agg(Dims d, CarryArgs a)
+__global__ void __launch_bounds__(64) k_carry_agg(Dims d, CarryArgs a)
 {
-    extern __shared__ double carry_stage[];
-    const int64_t b = blockIdx.x / d.NB, blk = blockIdx.x % d.NB;
-#define CALL(DB)                                                                                   \
-    (d.tv ? carry_agg_body<DB, true>(d, a, b, blk, carry_stage)                                    \
-          : carry_agg_body<DB, false>(d, a, b, blk, carry_stage))
-    FILT_CARRY_DB(a.D, CALL);
-#undef CALL
+    carry_agg_body(d, a, blockIdx.x / d.NB, blockIdx.x % d.NB);
 }
 
 __global__ void __launch_bounds__(256)
@@ -29,9 +23,7 @@ __global__ void __launch_bounds__(256) k_carry_fill(Dims d, CarryArgs a)
 {
     extern __shared__ double carry_stage[];
     const int64_t b = blockIdx.x / d.NB, blk = blockIdx.x % d.NB;
-#define CALL(DB)                                                                                   \
-    (d.tv ? carry_fill_body<DB, true>(d, a, b, blk, carry_stage)                                   \
-          : carry_fill_body<DB, false>(d, a, b, blk, carry_stage))
+#define CALL(DB) carry_fill_body<DB>(d, a, b, blk, carry_stage)
     FILT_CARRY_DB(a.D, CALL);
 #undef CALL
 }
@@ -354,13 +346,10 @@ filt_status carry_run(const Dims &d, const CarryArgs &a, const void *init, bool 
         return fail(FILT_EUNSUPPORTED, "carry order %d (+%d)", a.D, a.R);
     if (!d.tv)
         return lti_carry_run(d, a, init, init_f64, st);
-    const CarryRec cr = carry_rec(d.tv, a.D, a.SS, a.soff);
-    const int64_t agg_lds = (int64_t)stage_steps(cr.agg_len, d.G) * cr.agg_len;
+    const CarryRec cr = carry_rec(a.D, a.SS);
     const int64_t blk_lds = (int64_t)stage_steps(cr.blk_len, d.NB) * cr.blk_len;
     const int64_t fill_lds = (int64_t)stage_steps(cr.fill_len, d.G) * cr.fill_len;
-    const int agg_threads = ((a.D * (a.D + 1) + 63) / 64) * 64;
-    FILT_LAUNCH("carry_agg", k_carry_agg, dim3((unsigned)(d.B * d.NB)), dim3(agg_threads),
-                agg_lds * sizeof(double), st, d, a);
+    FILT_LAUNCH("carry_agg", k_carry_agg, dim3((unsigned)(d.B * d.NB)), dim3(64), 0, st, d, a);
     FILT_LAUNCH("carry_blocks", k_carry_blocks, dim3((unsigned)d.B),
                 dim3(carry_threads(blk_lds, a.D)), blk_lds * sizeof(double), st, d, a, init,
                 (int)init_f64);
