@@ -1,16 +1,18 @@
 """Benchmark: forward + backward throughput of the direct-form filter on one GPU.
 
 Default workload: per-sample (time-varying) all-pole filter, order N = 16,
-B = 64 channels x T = 48000 samples, [B, T] layout, per-sample coefficients
-[64, 48000, 16] from frame-held (hop 240) reflection coefficients, zero
-initial state, FP32 I/O.  One step = forward plus the full backward
-(gradients of x and of the per-sample coefficients) through the
+B = 64 channels x T = 48000 samples, channel-interleaved [T, B] layout,
+per-sample coefficients [48000, 64, 16] from frame-held (hop 240) reflection
+coefficients, zero initial state, FP32 I/O.  One step = forward plus the full
+backward (gradients of x and of the per-sample coefficients) through the
 autograd.Function, with all inputs already resident in HBM.
 
 Prints one JSON line.  Also reports the dominant kernel's achieved HBM
 bandwidth (algorithmic bytes per launch / its average duration, timed with
-HIP events on the launch stream during the timed steps) and the FP64 CPU
-oracle timed on the host.
+HIP events on the launch stream during the timed steps), its HBM traffic as
+counted by rocprofv3 (from the committed counter summary, only while the
+kernel sources are unchanged since the count) and the FP64 CPU oracle timed
+on the host.
 """
 from __future__ import annotations
 
@@ -77,6 +79,12 @@ def kernel_bytes(p, name):
     coef = 4 * (K_a + K_b) if p.time_varying else 0
     fir = 4 if p.M > 0 else 0
     table = {
+        # time-invariant [B, T] problems on the matrix cores: the tile kernels
+        # move only signals (the per-channel matrices stay in L2)
+        "tz_fwd_apply": 4 + 4,
+        "tz_bwd_apply": 4 + 4 + 4 + (4 if (p.M > 0 and p.b is not None) else 0),
+        "tz_fwd_summary": 4,
+        "tz_bwd_summary": 4,
         # forward: read x (+ coefficients), write y
         "fwd_apply": 4 + 4 + coef,
         # backward: read gy, y (+ x for M > 0) and coefficients; write gx and
@@ -87,6 +95,40 @@ def kernel_bytes(p, name):
         "bwd_summary": 4 + coef,
     }
     return table.get(name)
+
+
+def source_digest():
+    """Digest of the library's kernel sources: a counted traffic figure is
+    used only for the sources it was counted on."""
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2511_14390_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(workload, layout, chunk, kernel):
+    """HBM bytes per launch of `kernel` from a `traffic-record:` line of the
+    counter summaries in profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled by
+    the same counter's reading for a 1 GiB copy), or None when no record
+    matches this workload, layout, chunk and the current sources."""
+    import glob
+
+    digest = source_digest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
+        for line in open(f):
+            if not line.startswith("traffic-record:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if (kv.get("workload") == workload and kv.get("layout") == layout
+                    and int(kv.get("chunk", -1)) == chunk and kv.get("kernel") == kernel
+                    and kv.get("sources") == digest):
+                return int(kv["read_bytes"]) + int(kv["write_bytes"])
+    return None
 
 
 def batched_main(args):
@@ -225,12 +267,14 @@ def main():
             for k, (c, ms) in prof.items()}
     dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"]) if kern else None
     roofline = None
+    chunk = F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk))
     if dom is not None and kernel_bytes(p, dom) is not None:
         per_launch = kernel_bytes(p, dom) * samples
         ach = per_launch / (kern[dom]["avg_us"] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": None, "bytes_per_launch": per_launch,
+                    "traffic": counted_traffic(args.workload, p.layout, chunk, dom),
+                    "bytes_per_launch": per_launch,
                     "avg_launch_us": round(kern[dom]["avg_us"], 2)}
 
     cpu = None
@@ -263,7 +307,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": p.name, "io": "f32", "B": p.B, "T": p.T, "M": p.M, "N": p.N,
                    "time_varying": bool(p.time_varying), "layout": p.layout,
-                   "chunk": F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk)),
+                   "chunk": chunk,
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
