@@ -150,7 +150,8 @@ __device__ __forceinline__ void bwd_apply_item(
     const io_t *__restrict__ xi, const io_t *__restrict__ y, const io_t *__restrict__ yi,
     const io_t *__restrict__ bc, const io_t *__restrict__ ac, const double *__restrict__ gin,
     io_t *__restrict__ gx, io_t *__restrict__ gb, io_t *__restrict__ ga, io_t *__restrict__ gxi,
-    io_t *__restrict__ gyi, double *__restrict__ part, int64_t b, int64_t c)
+    io_t *__restrict__ gyi, double *__restrict__ part, io_t *__restrict__ ybo, int64_t b,
+    int64_t c)
 {
     constexpr int m = W - 1;
     const int64_t t0 = c * d.L;
@@ -163,6 +164,8 @@ __device__ __forceinline__ void bwd_apply_item(
     const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     const int64_t sstride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
     io_t *gxrow = gx != nullptr ? gx + sig_at(d, b, t0) : nullptr;
+    // the adjoint itself, for a separate coefficient-gradient pass
+    io_t *ybrow = ybo != nullptr ? ybo + sig_at(d, b, t0) : nullptr;
     // per-sample gradient rows: row of time t at grow + (t - t0) * gstride
     const int64_t gstride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
     io_t *garow = (TV && GA) ? ga + row_at(d, b, t0, N) : nullptr;
@@ -200,25 +203,31 @@ __device__ __forceinline__ void bwd_apply_item(
 #pragma unroll
     for (int k = 0; k < W; ++k)
         sgb[k] = 0.0;
-    acc_t wx[W], wy[W];
+    // signal windows for the coefficient gradients: per-sample gradients are
+    // single products rounded to io_t, so the windows stay in io_t (half the
+    // registers of FP64 windows); the time-invariant sums accumulate in FP64
+    using win_t = std::conditional_t<TV, io_t, acc_t>;
+    win_t wx[W], wy[W];
     const int64_t thi = t0 + d.L - 1;
     constexpr bool want_gb = GB;
     constexpr bool want_ga = GA;
     constexpr bool COEF = GA || GB;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
-        wx[q] = acc_t(0);
-        wy[q] = acc_t(0);
+        wx[q] = win_t(0);
+        wy[q] = win_t(0);
     }
+    // chunks start on multiples of 32 >= W, so thi = t0 + L - 1 sits in
+    // window slot W - 1 and every slot index below is a compile-time constant
     if constexpr (want_gb) {
 #pragma unroll
         for (int k = 0; k < W - 1; ++k)
-            wx[(thi - k) & m] = ld_x<io_t, acc_t>(d, x, xi, b, thi - k);
+            wx[(m - k) & m] = ld_x<io_t, win_t>(d, x, xi, b, thi - k);
     }
     if constexpr (want_ga) {
 #pragma unroll
         for (int k = 1; k < W; ++k)
-            wy[(thi - k) & m] = ld_y<io_t, acc_t>(d, y, yi, b, thi - k);
+            wy[(m - k) & m] = ld_y<io_t, win_t>(d, y, yi, b, thi - k);
     }
     using PF = Prefetch<W, TV, FIR, io_t>;
     auto fetch = [&](int64_t t, PF &p) {
@@ -258,6 +267,8 @@ __device__ __forceinline__ void bwd_apply_item(
                     cb[k] = lb[k];
             }
             const acc_t yb = (acc_t)cur.s0 + ss[(1 - s) & m];
+            if (ybrow != nullptr && in)
+                ybrow[(t - t0) * sstride] = (io_t)yb;
             if (gxrow != nullptr && in) {
                 acc_t gxv = cb[0] * yb;
                 if constexpr (FIR)
@@ -280,14 +291,15 @@ __device__ __forceinline__ void bwd_apply_item(
                 if constexpr (want_gb) {
                     // x[t-(W-1)] = x[s-(W-1)] = xi[W-2-s] when it is before time 0
                     const io_t xv = (s < W - 1) ? xic[(W - 2 - s) < 0 ? 0 : (W - 2 - s)] : io_t(0);
-                    wx[(s + 1) & m] = (acc_t)((pre0 && s < W - 1) ? xv : cur.s1);
+                    wx[(s + 1) & m] = (win_t)((pre0 && s < W - 1) ? xv : cur.s1);
                     if constexpr (TV) {
                         if (in) {
                             io_t *o = gbrow + (t - t0) * gstride * (M + 1);
+                            const io_t ybo = (io_t)yb;
 #pragma unroll
                             for (int k = 0; k < W; ++k)
                                 if (k <= M)
-                                    o[k] = (io_t)(yb * wx[(s - k) & m]);
+                                    o[k] = ybo * wx[(s - k) & m];
                         }
                     } else {
 #pragma unroll
@@ -298,10 +310,11 @@ __device__ __forceinline__ void bwd_apply_item(
                 if constexpr (want_ga) {
                     // y[t-W] = y[s-W] = yi[W-1-s] when it is before time 0
                     const io_t yv = yic[(s < W) ? (W - 1 - s) : 0];
-                    wy[s & m] = (acc_t)((pre0 && s < W) ? yv : cur.s2);
+                    wy[s & m] = (win_t)((pre0 && s < W) ? yv : cur.s2);
                     if constexpr (TV) {
                         if (in) {
                             io_t *o = garow + (t - t0) * gstride * N;
+                            const io_t nyb = -(io_t)yb;
                             bool done = false;
                             if constexpr (AV && sizeof(io_t) == 4 && W % 4 == 0) {
                                 {
@@ -309,10 +322,10 @@ __device__ __forceinline__ void bwd_apply_item(
                                     for (int q = 0; q < W / 4; ++q) {
                                         if (4 * q < N) {
                                             float4 v;
-                                            v.x = (float)(-yb * wy[(s - 4 * q - 1) & m]);
-                                            v.y = (float)(-yb * wy[(s - 4 * q - 2) & m]);
-                                            v.z = (float)(-yb * wy[(s - 4 * q - 3) & m]);
-                                            v.w = (float)(-yb * wy[(s - 4 * q - 4) & m]);
+                                            v.x = nyb * wy[(s - 4 * q - 1) & m];
+                                            v.y = nyb * wy[(s - 4 * q - 2) & m];
+                                            v.z = nyb * wy[(s - 4 * q - 3) & m];
+                                            v.w = nyb * wy[(s - 4 * q - 4) & m];
                                             *reinterpret_cast<float4 *>(o + 4 * q) = v;
                                         }
                                     }
@@ -323,7 +336,7 @@ __device__ __forceinline__ void bwd_apply_item(
 #pragma unroll
                                 for (int k = 1; k <= W; ++k)
                                     if (k <= N)
-                                        o[k - 1] = (io_t)(-yb * wy[(s - k) & m]);
+                                        o[k - 1] = nyb * wy[(s - k) & m];
                             }
                         }
                     } else {
@@ -365,7 +378,7 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
             const io_t *__restrict__ yi, const io_t *__restrict__ bc,
             const io_t *__restrict__ ac, const double *__restrict__ gin, io_t *__restrict__ gx,
             io_t *__restrict__ gb, io_t *__restrict__ ga, io_t *__restrict__ gxi,
-            io_t *__restrict__ gyi, double *__restrict__ part)
+            io_t *__restrict__ gyi, double *__restrict__ part, io_t *__restrict__ ybo)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= d.B * d.C)
@@ -373,7 +386,7 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
     int64_t b, c, jj;
     decode(d, idx, d.C, b, c, jj);
     bwd_apply_item<W, TV, FIR, GA, GB, AV, io_t, acc_t>(d, gy, x, xi, y, yi, bc, ac, gin, gx, gb,
-                                                        ga, gxi, gyi, part, b, c);
+                                                        ga, gxi, gyi, part, ybo, b, c);
 }
 
 // ---------------------------------------------------------------- drivers
@@ -435,12 +448,12 @@ template <int W, bool FIR, typename io_t, typename acc_t>
 filt_status bwd_apply(const Dims &d, const io_t *gy, const io_t *x, const io_t *y,
                       const io_t *bc, const io_t *ac, const io_t *xi, const io_t *yi,
                       const double *states, io_t *gx, io_t *gb, io_t *ga, io_t *gxi, io_t *gyi,
-                      double *part, hipStream_t st)
+                      double *part, io_t *ybo, hipStream_t st)
 {
 #define FILT_BWD_APPLY(TVV, GAV, GBV, AVV)                                                         \
     FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, GAV, GBV, AVV, io_t, acc_t>),               \
                 dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, gy, x, xi, y, yi, bc, ac,     \
-                states, gx, gb, ga, gxi, gyi, part)
+                states, gx, gb, ga, gxi, gyi, part, ybo)
 #define FILT_BWD_APPLY_G(TVV, AVV)                                                                 \
     do {                                                                                           \
         if (ga != nullptr && gb != nullptr)                                                        \
@@ -497,13 +510,27 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
         if (s != FILT_OK)
             return s;
     }
+    // Order-16 per-sample problems: the fused adjoint with the coefficient
+    // products needs more registers than a wavefront has and spills to
+    // AGPRs on every step, so the apply writes the adjoint (FP32) and a
+    // fully parallel pass forms ga and gb from it.
+    const bool split = d.tv && W >= 16 && sizeof(io_t) == 4 && (ga != nullptr || gb != nullptr) &&
+                       tv_coef_grads_fits(d);
+    io_t *ybo = split ? (io_t *)(ws + w.yb) : nullptr;
+    io_t *ga_f = split ? nullptr : ga;
+    io_t *gb_f = split ? nullptr : gb;
     filt_status s = (M > 0) ? bwd_apply<W, true, io_t, acc_t>(d, gy, x, y, bc, ac, xi, yi, states,
-                                                              gx, gb, ga, gxi, gyi, part, st)
+                                                              gx, gb_f, ga_f, gxi, gyi, part, ybo,
+                                                              st)
                             : bwd_apply<W, false, io_t, acc_t>(d, gy, x, y, bc, ac, xi, yi,
-                                                               states, gx, gb, ga, gxi, gyi, part,
-                                                               st);
+                                                               states, gx, gb_f, ga_f, gxi, gyi,
+                                                               part, ybo, st);
     if (s != FILT_OK)
         return s;
+    if constexpr (sizeof(io_t) == 4) {
+        if (split)
+            return tv_coef_grads_run(d, ybo, x, xi, y, yi, ga, gb, st);
+    }
     if (!d.tv && (ga != nullptr || gb != nullptr))
         s = reduce_lti_run(d, part, ga, gb, sizeof(io_t) == 8, st);
     return s;

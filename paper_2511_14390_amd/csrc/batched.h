@@ -147,7 +147,7 @@ kb_bwd_apply(const SegDesc *__restrict__ segs, const Item *__restrict__ items, i
             d, gy + sd.x_off, nullptr, nullptr, y + sd.x_off,
             yi != nullptr ? yi + sd.ic_off : nullptr, ap, ap, ws + sd.states_off,
             gx != nullptr ? gx + sd.x_off : nullptr, nullptr, GA ? ga + sd.a_off : nullptr, nullptr,
-            gyi != nullptr ? gyi + sd.ic_off : nullptr, nullptr, 0, it.chunk);
+            gyi != nullptr ? gyi + sd.ic_off : nullptr, nullptr, nullptr, 0, it.chunk);
     }
 }
 

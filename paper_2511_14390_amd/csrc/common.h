@@ -32,6 +32,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "filt.h"
 
@@ -327,7 +328,7 @@ __host__ __device__ inline TzGeom tz_geom(int N, int M)
 
 // Workspace carve-up, 256-byte aligned regions (FP64 unless noted).
 struct WsPlan {
-    size_t summ, phi, agg, bstart, states, part, total;
+    size_t summ, phi, agg, bstart, states, part, yb, total;
     size_t tz_af, tz_ayb, tz_agx, tz_phib;  // matrix-core path (FP32 matrices)
 };
 
@@ -379,6 +380,8 @@ inline WsPlan ws_plan(const Dims &d)
     w.bstart = take((size_t)(d.B * nb * std::max<int64_t>(N, 1)));
     w.states = take((size_t)(d.B * d.C * (N + M)));
     w.part = take((size_t)(d.B * d.C * (N + M + 1)));
+    // per-sample problems: the adjoint for the coefficient-gradient pass
+    w.yb = take(d.tv ? (size_t)(d.B * d.T) : 0);
     w.total = off + 256;
     return w;
 }
@@ -389,6 +392,13 @@ filt_status carry_run(const Dims &d, const CarryArgs &a, const void *init, bool 
 filt_status fir_states_run(const Dims &d, const double *summ, double *states, hipStream_t st);
 filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb, bool f64,
                            hipStream_t st);
+
+// grads.hip: per-sample coefficient gradients from a stored adjoint,
+// ga_k[n] = -ybar[n] y[n-k] and gb_k[n] = ybar[n] x[n-k] (Eq. 8-9 per sample).
+filt_status tv_coef_grads_run(const Dims &d, const float *ybar, const float *x, const float *xi,
+                              const float *y, const float *yi, float *ga, float *gb,
+                              hipStream_t st);
+bool tv_coef_grads_fits(const Dims &d);  // 32-bit thread indexing
 
 // toeplitz.hip
 struct TzPlan {

@@ -1,0 +1,128 @@
+// grads.hip -- per-sample coefficient gradients from a stored adjoint.
+//
+// With per-sample coefficients the gradients are one product per tap and
+// sample (Sec. 3.1 Eqs. 8-9 without the sum over time):
+//   ga_k[n] = -ybar[n] y[n-k]  (k = 1..N),   gb_k[n] = ybar[n] x[n-k]  (k = 0..M),
+// with y[-j] = yi[j-1] and x[-j] = xi[j-1].
+#include "common.h"
+
+namespace filt_detail {
+namespace {
+
+constexpr int kGradThreads = 256;
+constexpr int kGradRunTB = 16;  // consecutive samples per thread group in [T, B]
+
+// Four neighbouring threads share a (channel, run of TT consecutive samples)
+// and each owns four consecutive taps, so every row store of a wavefront is
+// one contiguous 16-byte piece per thread.  A thread loads the TT + 3 signal
+// values its taps need once.  Taps k = k0 + j, j < K <= 17, of
+// out[e*K + j] = sign * ybar[e] * s[n - k] (s[-i] = hist[i-1] for i <= nh,
+// else 0).  [T, B] takes TT = 4 (neighbouring thread groups are neighbouring
+// channels, whose rows of one time are contiguous); [B, T] takes TT = 1
+// (neighbouring samples of one channel).
+// G = (K + 3) / 4 threads per row; the launch keeps B * runs * G below 2^31
+// so the index arithmetic is 32-bit.
+template <int TT, int G>
+__global__ void __launch_bounds__(kGradThreads)
+k_tv_coef_grads(Dims d, const float *__restrict__ ybar, const float *__restrict__ s,
+                const float *__restrict__ hist, int nh, int k0, int K, float sign,
+                float *__restrict__ out, int vec)
+{
+    const uint32_t runs = (uint32_t)((d.T + TT - 1) / TT);
+    const uint32_t g = blockIdx.x * kGradThreads + threadIdx.x;
+    const uint32_t r = g / G;
+    if (r >= (uint32_t)d.B * runs)
+        return;
+    const int q = (int)(g - r * G);
+    const bool tb = d.layout == FILT_LAYOUT_TB;
+    const uint32_t B32 = (uint32_t)d.B;
+    const int64_t b = tb ? r % B32 : r / runs;
+    const int64_t t0 = (int64_t)(tb ? r / B32 : r % runs) * TT;
+    const int64_t step = tb ? d.B : 1;
+    const int64_t e0 = tb ? t0 * d.B + b : b * d.T + t0;
+    const int kq = k0 + 4 * q;  // first tap of this thread
+    // w[v] = s[t0 - kq - 3 + v]
+    float w[TT + 3];
+#pragma unroll
+    for (int v = 0; v < TT + 3; ++v) {
+        const int64_t t = t0 - kq - 3 + v;
+        float x = 0.f;
+        if (t >= 0) {
+            if (t < d.T)
+                x = s[e0 + (t - t0) * step];
+        } else if (hist != nullptr && -t <= nh) {
+            x = hist[b * nh + (-t - 1)];
+        }
+        w[v] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < TT; ++u) {
+        if (t0 + u >= d.T)
+            break;
+        const int64_t e = e0 + u * step;
+        const float v = sign * ybar[e];
+        float rr[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+            rr[jj] = (4 * q + jj < K) ? v * w[u - jj + 3] : 0.f;
+        float *o = out + e * K + 4 * q;
+        if (vec) {
+            *reinterpret_cast<float4 *>(o) = make_float4(rr[0], rr[1], rr[2], rr[3]);
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                if (4 * q + jj < K)
+                    o[jj] = rr[jj];
+        }
+    }
+}
+
+}  // namespace
+
+bool tv_coef_grads_fits(const Dims &d)
+{
+    return d.B * d.T * 5 < ((int64_t)1 << 31);
+}
+
+filt_status tv_coef_grads_run(const Dims &d, const float *ybar, const float *x, const float *xi,
+                              const float *y, const float *yi, float *ga, float *gb,
+                              hipStream_t st)
+{
+    const int64_t n = d.B * d.T;
+    if (n == 0)
+        return FILT_OK;
+    auto launch = [&](const float *sig, const float *hist, int nh, int k0, int K, float sign,
+                      float *out) {
+        // whole float4 pieces: rows a multiple of 4 wide and 16-byte aligned
+        const int vec = (K % 4 == 0) && ((uintptr_t)out % 16 == 0);
+        const int G = (K + 3) / 4;
+        const bool tb = d.layout == FILT_LAYOUT_TB;
+        const int64_t threads = d.B * (tb ? (d.T + kGradRunTB - 1) / kGradRunTB : d.T) * G;
+        const dim3 grid((unsigned)((threads + kGradThreads - 1) / kGradThreads));
+#define GRAD_LAUNCH(TT, GG)                                                                        \
+    FILT_LAUNCH("coef_grads", (k_tv_coef_grads<TT, GG>), grid, dim3(kGradThreads), 0, st, d, ybar, \
+                sig, hist, nh, k0, K, sign, out, vec)
+#define GRAD_G(TT)                                                                                 \
+    switch (G) {                                                                                   \
+    case 1: GRAD_LAUNCH(TT, 1); break;                                                             \
+    case 2: GRAD_LAUNCH(TT, 2); break;                                                             \
+    case 3: GRAD_LAUNCH(TT, 3); break;                                                             \
+    case 4: GRAD_LAUNCH(TT, 4); break;                                                             \
+    default: GRAD_LAUNCH(TT, 5); break;                                                            \
+    }
+        if (tb) {
+            GRAD_G(kGradRunTB)
+        } else {
+            GRAD_G(1)
+        }
+#undef GRAD_G
+#undef GRAD_LAUNCH
+    };
+    if (ga != nullptr && d.N > 0)
+        launch(y, yi, d.N, 1, d.N, -1.f, ga);
+    if (gb != nullptr)
+        launch(x, xi, d.M, 0, d.M + 1, 1.f, gb);
+    return check_launch("coefficient gradients");
+}
+
+}  // namespace filt_detail
