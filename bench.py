@@ -146,8 +146,13 @@ def batched_main(args):
     t = lambda v: torch.from_numpy(v).to(dev)
     x, a, yi, gy = t(s.x), t(s.a), t(s.yi), t(s.gy)
     samples = int(s.T.sum())
-    plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off)
-    chunks = plan.tune(x, a, yi, gy)
+    if args.chunk > 0:
+        # fixed chunk length for every order bucket (no tuning)
+        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off, chunks=[args.chunk] * 5)
+        chunks = plan.chunks
+    else:
+        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off)
+        chunks = plan.tune(x, a, yi, gy)
     y = torch.empty_like(x)
     gx = torch.empty_like(x)
     ga = torch.zeros_like(a)

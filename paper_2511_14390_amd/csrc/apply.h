@@ -11,6 +11,7 @@
 #pragma once
 
 #include "common.h"
+#include "stream.h"
 
 namespace filt_detail {
 
@@ -439,6 +440,10 @@ filt_status forward_w(const Dims &d, const io_t *x, const io_t *bc, const io_t *
         if (s != FILT_OK)
             return s;
     }
+    if constexpr (sizeof(io_t) == 4 && sizeof(acc_t) == 8 && W <= 16) {
+        if (stream_eligible(d))
+            return stream_forward_run<W>(d, x, ac, yi, states, y, st);
+    }
     if (d.M > 0)
         return fwd_apply<W, true, io_t, acc_t>(d, x, bc, ac, xi, yi, states, y, st);
     return fwd_apply<W, false, io_t, acc_t>(d, x, bc, ac, xi, yi, states, y, st);
@@ -509,6 +514,17 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
         }
         if (s != FILT_OK)
             return s;
+    }
+    if constexpr (sizeof(io_t) == 4 && sizeof(acc_t) == 8 && W <= 16) {
+        // [B, T] all-pole: staged apply writes ybar (gx itself when wanted,
+        // since gx = ybar for b = [1]); ga comes from the coalesced pass
+        if (stream_eligible(d) && (ga == nullptr || tv_coef_grads_fits(d))) {
+            io_t *yb = gx != nullptr ? gx : (io_t *)(ws + w.yb);
+            filt_status s = stream_backward_run<W>(d, gy, ac, states, yb, gyi, st);
+            if (s != FILT_OK || ga == nullptr)
+                return s;
+            return tv_coef_grads_run(d, yb, x, xi, y, yi, ga, nullptr, st);
+        }
     }
     // Order-16 per-sample problems: the fused adjoint with the coefficient
     // products needs more registers than a wavefront has and spills to

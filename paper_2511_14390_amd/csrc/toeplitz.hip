@@ -115,40 +115,51 @@ k_tz_prep(Dims d, const float *__restrict__ bc, const float *__restrict__ ac, in
     }
     if (!fwd) {
         // Pyb[i][w]: ybar[t0 + i] for a unit ybar[t1 + w] beyond the chunk.
-        // That value drives the adjoint at position i' through the term
-        // -a_{64 + w - i'}, which then spreads backwards by h_A.
+        // That value drives the adjoint at position i' = 64 + w - k through
+        // the term -a_k, which then spreads backwards by h_A.
         for (int e = tid; e < kTzL * g.KW; e += kTzThreads) {
             const int i = e / g.KW, w = e % g.KW;
             double v = 0.0;
-            for (int ip = i; ip < kTzL; ++ip) {
-                const int k = kTzL + w - ip;
-                if (k >= 1 && k <= N)
+            for (int k = w + 1; k <= N; ++k) {
+                const int ip = kTzL + w - k;
+                if (ip >= i)
                     v -= ca[k] * hA[ip - i];
             }
             pyb[i][w] = v;
         }
     }
     __syncthreads();
+    // each thread keeps one output row i (the element loops step by a
+    // multiple of 64) and the response values it needs in registers
+    const int ri = tid & (kTzL - 1);
+    double hr[kMaxD + 1];
+#pragma unroll
+    for (int n = 0; n <= kMaxD; ++n)
+        hr[n] = ri - n >= 0 ? hA[ri - n >= 0 ? ri - n : 0] : 0.0;
     if (fwd) {
         float *A = Af + b * (int64_t)g.KPF * kTzL;
         for (int e = tid; e < g.KPF * kTzL; e += kTzThreads) {
-            const int k = e / kTzL, i = e % kTzL;
+            const int k = e / kTzL;  // uniform across a wavefront
             double v = 0.0;
             if (k < g.KH) {
                 // unit x[t0 - m] enters through b_{n+m} at n = 0..M-m
                 const int m = g.KH - k;
                 if (m <= M)
-                    for (int n = 0; n <= M - m && n <= i; ++n)
-                        v += cb[n + m] * hA[i - n];
+#pragma unroll
+                    for (int n = 0; n <= kMaxD; ++n)
+                        if (n <= M - m)
+                            v += cb[n + m <= kMaxD ? n + m : kMaxD] * hr[n];
             } else if (k < g.KH + kTzL) {
                 const int j = k - g.KH;
-                v = i >= j ? h[i - j] : 0.0;
+                v = ri >= j ? h[ri - j] : 0.0;
             } else {
                 // unit y[t0 - m] enters through -a_{n+m} at n = 0..N-m
                 const int m = k - g.KH - kTzL + 1;
                 if (m <= N)
-                    for (int n = 0; n <= N - m && n <= i; ++n)
-                        v -= ca[n + m] * hA[i - n];
+#pragma unroll
+                    for (int n = 0; n <= kMaxD; ++n)
+                        if (n <= N - m)
+                            v -= ca[n + m <= kMaxD ? n + m : kMaxD] * hr[n];
             }
             A[e] = (float)v;
         }
@@ -196,27 +207,62 @@ k_tz_prep(Dims d, const float *__restrict__ bc, const float *__restrict__ ac, in
 
 // Stage the windows of the tile's chunks: window col holds, at k in
 // [0, KH + 64), the signal at t = t0(col) - KH + k; zero at t >= T; for t < 0
-// hist[-t - 1] when -t <= nh (hist may be null).
+// hist[-t - 1] when -t <= nh (hist may be null).  Runs of four samples move
+// as one float4 when the signal is 16-byte aligned there (vec).
+__device__ __forceinline__ float tz_sample(const float *__restrict__ s, int64_t T,
+                                           const float *__restrict__ hist, int nh, int64_t t)
+{
+    if (t >= 0)
+        return t < T ? s[t] : 0.f;
+    return (hist != nullptr && -t <= nh) ? hist[-t - 1] : 0.f;
+}
+
 __device__ __forceinline__ void tz_stage_signal(const float *__restrict__ s, int64_t T,
                                                 const float *__restrict__ hist, int nh,
-                                                int64_t c0, int KH, int lp, float *win)
+                                                int64_t c0, int KH, int lp, float *win, int vec)
 {
-    const int n = KH + kTzL * kTzCols;
+    const int n4 = (KH + kTzL * kTzCols) / 4;  // KH is a multiple of 4
     const int64_t base = c0 * kTzL - KH;
-    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    for (int p4 = threadIdx.x; p4 < n4; p4 += blockDim.x) {
+        const int p = 4 * p4;
         const int64_t t = base + p;
-        float v = 0.f;
-        if (t >= 0) {
-            if (t < T)
-                v = s[t];
-        } else if (hist != nullptr && -t <= nh) {
-            v = hist[-t - 1];
+        float4 v;
+        if (vec && t >= 0 && t + 3 < T) {
+            v = *reinterpret_cast<const float4 *>(s + t);
+        } else {
+            v.x = tz_sample(s, T, hist, nh, t);
+            v.y = tz_sample(s, T, hist, nh, t + 1);
+            v.z = tz_sample(s, T, hist, nh, t + 2);
+            v.w = tz_sample(s, T, hist, nh, t + 3);
         }
         const int ca = p >> 6, ka = p & 63;
         if (ca < kTzCols)
-            win[ca * lp + ka] = v;
+            *reinterpret_cast<float4 *>(win + ca * lp + ka) = v;
         if (ka < KH && ca >= 1)
-            win[(ca - 1) * lp + ka + kTzL] = v;
+            *reinterpret_cast<float4 *>(win + (ca - 1) * lp + ka + kTzL) = v;
+    }
+}
+
+// Stage the signal s[t], t in [c0*64 - 16, (c0 + 64)*64), as a flat array
+// (lin[16 + n] = s[c0*64 + n]), history from hist.
+__device__ __forceinline__ void tz_stage_linear(const float *__restrict__ s, int64_t T,
+                                                const float *__restrict__ hist, int nh,
+                                                int64_t c0, float *lin, int vec)
+{
+    const int n4 = (16 + kTzL * kTzCols) / 4;
+    const int64_t base = c0 * kTzL - 16;
+    for (int p4 = threadIdx.x; p4 < n4; p4 += blockDim.x) {
+        const int64_t t = base + 4 * p4;
+        float4 v;
+        if (vec && t >= 0 && t + 3 < T) {
+            v = *reinterpret_cast<const float4 *>(s + t);
+        } else {
+            v.x = tz_sample(s, T, hist, nh, t);
+            v.y = tz_sample(s, T, hist, nh, t + 1);
+            v.z = tz_sample(s, T, hist, nh, t + 2);
+            v.w = tz_sample(s, T, hist, nh, t + 3);
+        }
+        *reinterpret_cast<float4 *>(lin + 4 * p4) = v;
     }
 }
 
@@ -267,7 +313,7 @@ __global__ void __launch_bounds__(kTzThreads)
 k_tz_fwd(Dims d, int mode, const float *__restrict__ x, const float *__restrict__ xi,
          const float *__restrict__ yi, const float *__restrict__ Af,
          const double *__restrict__ states, double *__restrict__ summ, float *__restrict__ y,
-         int vec)
+         int vec, int vin)
 {
     extern __shared__ float tz_lds[];
     const int N = d.N, M = d.M;
@@ -281,7 +327,8 @@ k_tz_fwd(Dims d, int mode, const float *__restrict__ x, const float *__restrict_
     const int tid = threadIdx.x;
     const float *A = Af + b * (int64_t)g.KPF * kTzL;
     tz_stage_matrix(A, 0, mode ? g.KPF : g.KH + kTzL, As);
-    tz_stage_signal(x + b * d.T, d.T, xi != nullptr ? xi + b * M : nullptr, M, c0, g.KH, lp, win);
+    tz_stage_signal(x + b * d.T, d.T, xi != nullptr ? xi + b * M : nullptr, M, c0, g.KH, lp, win,
+                    vin);
     if (mode) {
         for (int e = tid; e < kTzCols * g.KS; e += kTzThreads) {
             const int col = e / g.KS, q = e % g.KS;
@@ -368,7 +415,7 @@ k_tz_bwd(Dims d, int mode, const float *__restrict__ gy, const float *__restrict
          const float *__restrict__ xi, const float *__restrict__ y, const float *__restrict__ yi,
          const float *__restrict__ bc, const float *__restrict__ ac, const float *__restrict__ Ayb,
          const float *__restrict__ Agx, const double *__restrict__ states,
-         double *__restrict__ summ, TzBwdOut o, int vec)
+         double *__restrict__ summ, TzBwdOut o, int vec, int vin)
 {
     extern __shared__ float tz_lds[];
     __shared__ double red[4][2 * kMaxD + 2];
@@ -389,7 +436,7 @@ k_tz_bwd(Dims d, int mode, const float *__restrict__ gy, const float *__restrict
         tz_stage_matrix(Ayb + b * (int64_t)g.KPB * kTzL, 0, mode ? g.KPB : kTzL, Ys);
     if (want_x)
         tz_stage_matrix(Agx + b * (int64_t)g.KPB * kTzL, 0, g.KPB, Xs);
-    tz_stage_signal(gy + b * d.T, d.T, nullptr, 0, c0, 0, lp, win);
+    tz_stage_signal(gy + b * d.T, d.T, nullptr, 0, c0, 0, lp, win, vin);
     if (mode) {
         for (int e = tid; e < kTzCols * g.KWp; e += kTzThreads) {
             const int col = e / g.KWp, q = e % g.KWp;
@@ -458,9 +505,10 @@ k_tz_bwd(Dims d, int mode, const float *__restrict__ gy, const float *__restrict
     if (want_x)
         tz_store_tile(outx, o.gx + b * d.T, d.T, d.C, c0, vec);
     if (o.want_ab) {
-        // thread: chunk col = tid / 4, samples i0 .. i0 + 15 of it
-        const int pc = tid >> 2, i0 = (tid & 3) * 16;
-        const int64_t t = (c0 + pc) * kTzL + i0;
+        // the signals are staged flat in LDS (the Agx region is free now):
+        // lin[16 + n] = y[c0*64 + n]; thread tid takes samples n = tid + 256 u
+        // of the tile, so neighbouring lanes read neighbouring words
+        float *lin = Xs;
         float ga_acc[kMaxD], gb_acc[kMaxD + 1];
 #pragma unroll
         for (int k = 0; k < kMaxD; ++k)
@@ -468,57 +516,32 @@ k_tz_bwd(Dims d, int mode, const float *__restrict__ gy, const float *__restrict
 #pragma unroll
         for (int k = 0; k <= kMaxD; ++k)
             gb_acc[k] = 0.f;
-        float yb[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            yb[u] = outy[pc * 68 + i0 + u];
-        // sw[q] = signal at t - 16 + q (history from the initial conditions)
-        float sw[32];
         if (o.want_ga) {
-            const float *ych = y + b * d.T;
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const int64_t tt = t - 16 + q;
-                float v = 0.f;
-                if (q >= 16 - N) {
-                    if (tt >= 0) {
-                        if (tt < d.T)
-                            v = ych[tt];
-                    } else if (yi != nullptr && -tt <= N) {
-                        v = yi[b * N + (-tt - 1)];
-                    }
-                }
-                sw[q] = v;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
+            tz_stage_linear(y + b * d.T, d.T, yi != nullptr ? yi + b * N : nullptr, N, c0, lin,
+                            vin);
+            __syncthreads();
+            for (int u = 0; u < kTzL * kTzCols / kTzThreads; ++u) {
+                const int n = tid + kTzThreads * u;
+                const float v = outy[(n >> 6) * 68 + (n & 63)];
 #pragma unroll
                 for (int k = 1; k <= kMaxD; ++k)
                     if (k <= N)
-                        ga_acc[k - 1] -= yb[u] * sw[16 + u - k];
+                        ga_acc[k - 1] -= v * lin[16 + n - k];
+            }
+            __syncthreads();
         }
         if (o.want_gb) {
-            const float *xch = x + b * d.T;
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const int64_t tt = t - 16 + q;
-                float v = 0.f;
-                if (q >= 16 - M) {
-                    if (tt >= 0) {
-                        if (tt < d.T)
-                            v = xch[tt];
-                    } else if (xi != nullptr && -tt <= M) {
-                        v = xi[b * M + (-tt - 1)];
-                    }
-                }
-                sw[q] = v;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u)
+            tz_stage_linear(x + b * d.T, d.T, xi != nullptr ? xi + b * M : nullptr, M, c0, lin,
+                            vin);
+            __syncthreads();
+            for (int u = 0; u < kTzL * kTzCols / kTzThreads; ++u) {
+                const int n = tid + kTzThreads * u;
+                const float v = outy[(n >> 6) * 68 + (n & 63)];
 #pragma unroll
                 for (int k = 0; k <= kMaxD; ++k)
                     if (k <= M)
-                        gb_acc[k] += yb[u] * sw[16 + u - k];
+                        gb_acc[k] += v * lin[16 + n - k];
+            }
         }
         // workgroup sums in FP64: wavefront butterfly, then across waves
         const int K = N + M + 1;
@@ -601,12 +624,13 @@ filt_status tz_forward(const Dims &d, const float *x, const float *bc, const flo
     double *states = (double *)(ws + w.states);
     const unsigned grid = (unsigned)(d.B * tp.nwg);
     const int vec = (d.T % 4 == 0) && ((uintptr_t)y % 16 == 0);
+    const int vin = (d.T % 4 == 0) && ((uintptr_t)x % 16 == 0);
     FILT_LAUNCH("tz_prep", k_tz_prep, dim3((unsigned)d.B), dim3(kTzThreads), 0, st, d, bc, ac, 1,
                 Af, (float *)nullptr, (float *)nullptr, phif, (double *)nullptr);
     if (d.C > 1) {
         FILT_LAUNCH("tz_fwd_summary", k_tz_fwd, dim3(grid), dim3(kTzThreads), tz_fwd_lds(d), st,
                     d, 0, x, xi, yi, (const float *)Af, (const double *)states, summ,
-                    (float *)nullptr, vec);
+                    (float *)nullptr, vec, vin);
         CarryArgs a{};
         a.summ = summ;
         a.phi = phif;
@@ -623,7 +647,8 @@ filt_status tz_forward(const Dims &d, const float *x, const float *bc, const flo
             return s;
     }
     FILT_LAUNCH("tz_fwd_apply", k_tz_fwd, dim3(grid), dim3(kTzThreads), tz_fwd_lds(d), st, d, 1,
-                x, xi, yi, (const float *)Af, (const double *)states, (double *)nullptr, y, vec);
+                x, xi, yi, (const float *)Af, (const double *)states, (double *)nullptr, y, vec,
+                vin);
     return check_launch("time-invariant forward");
 }
 
@@ -641,6 +666,8 @@ filt_status tz_backward(const Dims &d, const float *gy, const float *x, const fl
     double *part = (double *)(ws + w.part);
     const unsigned grid = (unsigned)(d.B * tp.nwg);
     const int vec = (d.T % 4 == 0) && (gx == nullptr || (uintptr_t)gx % 16 == 0);
+    auto al = [](const float *p) { return p == nullptr || (uintptr_t)p % 16 == 0; };
+    const int vin = (d.T % 4 == 0) && al(gy) && al(y) && al(x);
     FILT_LAUNCH("tz_prep", k_tz_prep, dim3((unsigned)d.B), dim3(kTzThreads), 0, st, d, bc, ac, 0,
                 (float *)nullptr, Ayb, Agx, (double *)nullptr, phib);
     TzBwdOut o{};
@@ -654,7 +681,7 @@ filt_status tz_backward(const Dims &d, const float *gy, const float *x, const fl
     if (d.C > 1) {
         FILT_LAUNCH("tz_bwd_summary", k_tz_bwd, dim3(grid), dim3(kTzThreads), tz_bwd_lds(d), st,
                     d, 0, gy, x, xi, y, yi, bc, ac, (const float *)Ayb, (const float *)Agx,
-                    (const double *)states, summ, o, vec);
+                    (const double *)states, summ, o, vec, vin);
         CarryArgs a{};
         a.summ = summ;
         a.phi = phib;
@@ -672,7 +699,7 @@ filt_status tz_backward(const Dims &d, const float *gy, const float *x, const fl
     }
     FILT_LAUNCH("tz_bwd_apply", k_tz_bwd, dim3(grid), dim3(kTzThreads), tz_bwd_lds(d), st, d, 1,
                 gy, x, xi, y, yi, bc, ac, (const float *)Ayb, (const float *)Agx,
-                (const double *)states, (double *)nullptr, o, vec);
+                (const double *)states, (double *)nullptr, o, vec, vin);
     filt_status s = check_launch("time-invariant backward");
     if (s != FILT_OK || !o.want_ab)
         return s;
