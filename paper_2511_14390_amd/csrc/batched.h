@@ -12,6 +12,7 @@
 
 #include "apply.h"
 #include "carry.h"
+#include "stream.h"
 #include "summary.h"
 
 namespace filt_detail {
@@ -151,6 +152,128 @@ kb_bwd_apply(const SegDesc *__restrict__ segs, const Item *__restrict__ items, i
     }
 }
 
+// Staged applies (stream.h) over the items (seg, chunk) of one bucket, one
+// wavefront per 64 items; Lc is the bucket's chunk length.
+template <int W, bool VEC>
+__global__ void __launch_bounds__(64)
+kb_stream_fwd(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+              int64_t Lc, const float *__restrict__ x, const float *__restrict__ a,
+              const float *__restrict__ yi, const double *__restrict__ ws, float *__restrict__ y)
+{
+    __shared__ StreamLds<W> L;
+    const int i = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 64 + i;
+    const bool act = g < n;
+    SegDesc sd{};
+    int64_t c = 0;
+    if (act) {
+        const Item it = items[g];
+        sd = segs[it.seg];
+        c = it.chunk;
+    }
+    const int64_t t0 = c * Lc;
+    L.osig[i] = act ? sd.x_off + t0 : 0;
+    L.oout[i] = L.osig[i];
+    L.ocoef[i] = act ? sd.a_off + t0 * sd.N : 0;
+    L.ln[i] = act ? min(Lc, sd.T - t0) : 0;
+    L.lN[i] = act ? sd.N : 0;
+    double h0[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+        double v = 0.0;
+        if (act && q < sd.N)
+            v = c == 0 ? (yi != nullptr ? (double)yi[sd.ic_off + q] : 0.0)
+                       : ws[sd.states_off + c * sd.N + q];
+        h0[q] = v;
+    }
+    __syncthreads();
+    stream_forward<W, VEC>(L, StreamPtrs{x, a, y}, Lc, h0);
+}
+
+// Writes ybar into gx (equal for b = [1]) and, from chunk 0, gyi.
+template <int W, bool VEC>
+__global__ void __launch_bounds__(64)
+kb_stream_bwd(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+              int64_t Lc, const float *__restrict__ gy, const float *__restrict__ a,
+              const double *__restrict__ ws, float *__restrict__ gx, float *__restrict__ gyi)
+{
+    __shared__ StreamLds<W> L;
+    const int i = threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 64 + i;
+    const bool act = g < n;
+    SegDesc sd{};
+    int64_t c = 0;
+    if (act) {
+        const Item it = items[g];
+        sd = segs[it.seg];
+        c = it.chunk;
+    }
+    const int64_t t0 = c * Lc;
+    L.osig[i] = act ? sd.x_off + t0 : 0;
+    L.oout[i] = L.osig[i];
+    L.ocoef[i] = act ? sd.a_off + t0 * sd.N : 0;
+    L.ln[i] = act ? min(Lc, sd.T - t0) : 0;
+    L.lN[i] = act ? sd.N : 0;
+    double s0[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q)
+        s0[q] = (act && q < sd.N && c + 1 < sd.C) ? ws[sd.states_off + c * sd.N + q] : 0.0;
+    __syncthreads();
+    stream_backward<W, VEC>(L, StreamPtrs{gy, a, gx}, Lc, s0);
+    if (act && c == 0 && gyi != nullptr)
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+            if (q < sd.N)
+                gyi[sd.ic_off + q] = (float)s0[q];
+}
+
+// Per-sample ga from the stored adjoint, one workgroup per item:
+// ga_k[t] = -ybar[t] y[t-k], y[-j] = yi[j-1] (Eq. 8 per sample).  One copy
+// per order bucket (W) so each bucket's unit owns its kernel.
+template <int W>
+__global__ void __launch_bounds__(256)
+kb_coef_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t Lc,
+              const float *__restrict__ ybar, const float *__restrict__ y,
+              const float *__restrict__ yi, float *__restrict__ ga)
+{
+    const Item it = items[blockIdx.x];
+    const SegDesc sd = segs[it.seg];
+    const int N = sd.N;
+    if (N == 0)
+        return;
+    const int64_t t0 = (int64_t)it.chunk * Lc;
+    const int64_t n = min(Lc, sd.T - t0);
+    const int G = (N + 3) / 4;
+    const bool vec = (N % 4) == 0;  // a_off is a multiple of 4 floats
+    for (int64_t u = threadIdx.x; u < n * G; u += blockDim.x) {
+        const int64_t t = t0 + u / G;
+        const int q = (int)(u % G);
+        const float v = -ybar[sd.x_off + t];
+        float r[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int k = 4 * q + jj + 1;
+            float yv = 0.f;
+            if (k <= N) {
+                if (t - k >= 0)
+                    yv = y[sd.x_off + t - k];
+                else if (yi != nullptr)
+                    yv = yi[sd.ic_off + (k - t - 1)];
+            }
+            r[jj] = v * yv;
+        }
+        float *o = ga + sd.a_off + t * N + 4 * q;
+        if (vec) {
+            *reinterpret_cast<float4 *>(o) = make_float4(r[0], r[1], r[2], r[3]);
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                if (4 * q + jj < N)
+                    o[jj] = r[jj];
+        }
+    }
+}
+
 // Launch geometry of a grid-stride kernel over n items.
 inline void persistent_grid(int64_t n, unsigned &blocks, unsigned &threads)
 {
@@ -246,6 +369,46 @@ filt_status batched_bwd_apply(const BucketArgs &b, const float *gy, const float 
     }
 #undef FILT_KB_BWD
     return check_launch("batched backward apply");
+}
+
+// Buckets whose rows are at most 8 taps take the staged applies.
+template <int W>
+constexpr bool kStreamBucket = W <= 8;
+
+template <int W>
+filt_status batched_stream_fwd(const BucketArgs &b, int64_t Lc, const float *x, const float *a,
+                               const float *yi, const double *ws, float *y, hipStream_t st)
+{
+    if (b.app_n == 0)
+        return FILT_OK;
+    const dim3 grid((unsigned)((b.app_n + 63) / 64));
+    if (b.av && W % 4 == 0)
+        FILT_LAUNCH("batched_stream_fwd", (kb_stream_fwd<W, (W % 4 == 0)>), grid, dim3(64), 0, st,
+                    b.segs, b.app_items, b.app_n, Lc, x, a, yi, ws, y);
+    else
+        FILT_LAUNCH("batched_stream_fwd", (kb_stream_fwd<W, false>), grid, dim3(64), 0, st, b.segs,
+                    b.app_items, b.app_n, Lc, x, a, yi, ws, y);
+    return check_launch("batched staged forward apply");
+}
+
+template <int W>
+filt_status batched_stream_bwd(const BucketArgs &b, int64_t Lc, const float *gy, const float *y,
+                               const float *a, const float *yi, const double *ws, float *gx,
+                               float *ga, float *gyi, hipStream_t st)
+{
+    if (b.app_n == 0)
+        return FILT_OK;
+    const dim3 grid((unsigned)((b.app_n + 63) / 64));
+    if (b.av && W % 4 == 0)
+        FILT_LAUNCH("batched_stream_bwd", (kb_stream_bwd<W, (W % 4 == 0)>), grid, dim3(64), 0, st,
+                    b.segs, b.app_items, b.app_n, Lc, gy, a, ws, gx, gyi);
+    else
+        FILT_LAUNCH("batched_stream_bwd", (kb_stream_bwd<W, false>), grid, dim3(64), 0, st, b.segs,
+                    b.app_items, b.app_n, Lc, gy, a, ws, gx, gyi);
+    if (ga != nullptr)
+        FILT_LAUNCH("batched_coef_grads", kb_coef_grads<W>, dim3((unsigned)b.app_n), dim3(256), 0, st,
+                    b.segs, b.app_items, Lc, gx, y, yi, ga);
+    return check_launch("batched staged backward apply");
 }
 
 #define FILT_DECLARE_BATCHED(W, EXT)                                                               \

@@ -280,7 +280,10 @@ filt_status run_forward(const filt_plan *p, const float *x, const float *a, cons
     if ((mask & 8u) && s == FILT_OK) s = CALL(8, 3);                                               \
     if ((mask & 16u) && s == FILT_OK) s = CALL(16, 4);
 #define FWD_SUM(W, B) batched_fwd_summary<W>(bucket_args(p, B, a), x, a, p->d_ws, st)
-#define FWD_APP(W, B) batched_fwd_apply<W>(bucket_args(p, B, a), x, a, yi, p->d_ws, y, st)
+#define FWD_APP(W, B)                                                                              \
+    (kStreamBucket<W> ? batched_stream_fwd<W>(bucket_args(p, B, a), p->chunk[B], x, a, yi, p->d_ws, \
+                                              y, st)                                               \
+                      : batched_fwd_apply<W>(bucket_args(p, B, a), x, a, yi, p->d_ws, y, st))
     FILT_BUCKETS(FWD_SUM)
     if (s == FILT_OK)
         s = carry_launch(p, 0, yi, st);
@@ -297,7 +300,10 @@ filt_status run_backward(const filt_plan *p, const float *gy, const float *y, co
     filt_status s = FILT_OK;
 #define BWD_SUM(W, B) batched_bwd_summary<W>(bucket_args(p, B, a), gy, a, p->d_ws, st)
 #define BWD_APP(W, B)                                                                              \
-    batched_bwd_apply<W>(bucket_args(p, B, a), gy, y, a, yi, p->d_ws, gx, ga, gyi, st)
+    ((kStreamBucket<W> && gx != nullptr)                                                           \
+         ? batched_stream_bwd<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx, ga,  \
+                                 gyi, st)                                                          \
+         : batched_bwd_apply<W>(bucket_args(p, B, a), gy, y, a, yi, p->d_ws, gx, ga, gyi, st))
     FILT_BUCKETS(BWD_SUM)
     if (s == FILT_OK)
         s = carry_launch(p, 1, nullptr, st);

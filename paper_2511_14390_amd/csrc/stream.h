@@ -42,6 +42,7 @@ struct StreamLds {
     // offsets so the accesses stay global-memory ones) and valid samples
     int64_t osig[64], ocoef[64], oout[64];
     int64_t ln[64];
+    int lN[64];  // row width (the order) of each lane's filter
 };
 
 // The arrays the lane offsets refer to.
@@ -90,8 +91,8 @@ __device__ __forceinline__ int64_t stream_clamp(int64_t t, int64_t n)
 // and are then replaced by 0), so the code is straight-line and the compiler
 // can wait for exactly the loads a commit needs.
 template <int W, bool VEC>
-__device__ __forceinline__ void stream_load(const StreamLds<W> &L, const StreamPtrs &P, int N,
-                                            int64_t lo, StreamRegs<W, VEC> &r)
+__device__ __forceinline__ void stream_load(const StreamLds<W> &L, const StreamPtrs &P, int64_t lo,
+                                            StreamRegs<W, VEC> &r)
 {
     constexpr int S = StreamSteps<W>::value;
     const int l = threadIdx.x;
@@ -118,13 +119,14 @@ __device__ __forceinline__ void stream_load(const StreamLds<W> &L, const StreamP
             const int i = g / (S * W), e = g % (S * W);
             const int s = e / W, k = e % W;
             const int64_t n = L.ln[i];
+            const int Ni = L.lN[i];
             const int64_t t = lo + s;
             const int64_t tc = stream_clamp(t, n);
-            const int kc = k < N ? k : 0;
-            r.c[j] = P.coef[L.ocoef[i] + tc * N + kc];
+            const int kc = k < Ni ? k : 0;
+            r.c[j] = P.coef[L.ocoef[i] + tc * Ni + kc];
             if (j % 32 == 0)
                 r.okc[j / 32] = 0;
-            r.okc[j / 32] |= ((k < N && t >= 0 && t < n) ? 1u : 0u) << (j % 32);
+            r.okc[j / 32] |= ((k < Ni && t >= 0 && t < n) ? 1u : 0u) << (j % 32);
         }
     }
 #pragma unroll
@@ -212,8 +214,8 @@ __device__ __forceinline__ void stream_row(const StreamLds<W> &L, int s, double 
 // Forward: y[t] = x[t] - sum_k a_k[t] y[t-k] over the lane's chunk, from the
 // entering state h0[i] = y[t0-1-i].  L is the chunk length (a multiple of 32).
 template <int W, bool VEC>
-__device__ __forceinline__ void stream_forward(StreamLds<W> &L, const StreamPtrs &P, int N,
-                                               int64_t Lc, const double (&h0)[W])
+__device__ __forceinline__ void stream_forward(StreamLds<W> &L, const StreamPtrs &P, int64_t Lc,
+                                               const double (&h0)[W])
 {
     constexpr int S = StreamSteps<W>::value;
     constexpr int m = W - 1;
@@ -227,11 +229,11 @@ __device__ __forceinline__ void stream_forward(StreamLds<W> &L, const StreamPtrs
     // (ring slot (k + 1) & 1 holds run k + 1)
     constexpr int UG = SU > 2 ? SU : 2;  // runs per unrolled group
     StreamRegs<W, VEC> r[2];
-    stream_load<W, VEC>(L, P, N, 0, r[0]);
+    stream_load<W, VEC>(L, P, 0, r[0]);
     stream_commit<W, VEC>(L, r[0]);
     stream_sync();
-    stream_load<W, VEC>(L, P, N, S, r[1]);
-    stream_load<W, VEC>(L, P, N, 2 * S, r[0]);
+    stream_load<W, VEC>(L, P, S, r[1]);
+    stream_load<W, VEC>(L, P, 2 * S, r[0]);
     for (int64_t g0 = 0; g0 < Lc; g0 += UG * S) {
 #pragma unroll
         for (int u = 0; u < UG; ++u) {
@@ -257,7 +259,7 @@ __device__ __forceinline__ void stream_forward(StreamLds<W> &L, const StreamPtrs
             stream_flush<W>(L, P, lo);
             stream_commit<W, VEC>(L, r[(u + 1) & 1]);
             stream_sync();
-            stream_load<W, VEC>(L, P, N, lo + 3 * S, r[(u + 1) & 1]);
+            stream_load<W, VEC>(L, P, lo + 3 * S, r[(u + 1) & 1]);
         }
     }
 }
@@ -267,8 +269,8 @@ __device__ __forceinline__ void stream_forward(StreamLds<W> &L, const StreamPtrs
 // the state left before the chunk's first sample in s0 (gyi for chunk 0).
 // Writes ybar (and gx = ybar).
 template <int W, bool VEC>
-__device__ __forceinline__ void stream_backward(StreamLds<W> &L, const StreamPtrs &P, int N,
-                                                int64_t Lc, double (&s0)[W])
+__device__ __forceinline__ void stream_backward(StreamLds<W> &L, const StreamPtrs &P, int64_t Lc,
+                                                double (&s0)[W])
 {
     constexpr int S = StreamSteps<W>::value;
     constexpr int m = W - 1;
@@ -282,11 +284,11 @@ __device__ __forceinline__ void stream_backward(StreamLds<W> &L, const StreamPtr
         ss[(q + 2) & m] = s0[q];
     constexpr int UG = SU > 2 ? SU : 2;
     StreamRegs<W, VEC> r[2];
-    stream_load<W, VEC>(L, P, N, Lc - S, r[0]);
+    stream_load<W, VEC>(L, P, Lc - S, r[0]);
     stream_commit<W, VEC>(L, r[0]);
     stream_sync();
-    stream_load<W, VEC>(L, P, N, Lc - 2 * S, r[1]);
-    stream_load<W, VEC>(L, P, N, Lc - 3 * S, r[0]);
+    stream_load<W, VEC>(L, P, Lc - 2 * S, r[1]);
+    stream_load<W, VEC>(L, P, Lc - 3 * S, r[0]);
     for (int64_t g0 = 0; g0 < Lc; g0 += UG * S) {
 #pragma unroll
         for (int u = 0; u < UG; ++u) {
@@ -309,7 +311,7 @@ __device__ __forceinline__ void stream_backward(StreamLds<W> &L, const StreamPtr
             stream_flush<W>(L, P, lo);
             stream_commit<W, VEC>(L, r[(u + 1) & 1]);
             stream_sync();
-            stream_load<W, VEC>(L, P, N, lo - 3 * S, r[(u + 1) & 1]);
+            stream_load<W, VEC>(L, P, lo - 3 * S, r[(u + 1) & 1]);
         }
     }
 #pragma unroll
@@ -338,6 +340,7 @@ k_stream_fwd(Dims d, const float *__restrict__ x, const float *__restrict__ a,
     L.ocoef[i] = (b * d.T + t0) * d.N;
     L.oout[i] = b * d.T + t0;
     L.ln[i] = act ? min(d.L, d.T - t0) : 0;
+    L.lN[i] = d.N;
     double h0[W];
 #pragma unroll
     for (int q = 0; q < W; ++q) {
@@ -348,7 +351,7 @@ k_stream_fwd(Dims d, const float *__restrict__ x, const float *__restrict__ a,
         h0[q] = v;
     }
     __syncthreads();
-    stream_forward<W, VEC>(L, StreamPtrs{x, a, y}, d.N, d.L, h0);
+    stream_forward<W, VEC>(L, StreamPtrs{x, a, y}, d.L, h0);
 }
 
 // Writes ybar to yb (gx itself when gx is wanted: for b = [1] they are equal)
@@ -368,12 +371,13 @@ k_stream_bwd(Dims d, const float *__restrict__ gy, const float *__restrict__ a,
     L.ocoef[i] = (b * d.T + t0) * d.N;
     L.oout[i] = b * d.T + t0;
     L.ln[i] = act ? min(d.L, d.T - t0) : 0;
+    L.lN[i] = d.N;
     double s0[W];
 #pragma unroll
     for (int q = 0; q < W; ++q)
         s0[q] = (act && q < d.N && c + 1 < d.C) ? states[(b * d.C + c) * d.N + q] : 0.0;
     __syncthreads();
-    stream_backward<W, VEC>(L, StreamPtrs{gy, a, yb}, d.N, d.L, s0);
+    stream_backward<W, VEC>(L, StreamPtrs{gy, a, yb}, d.L, s0);
     if (act && c == 0 && gyi != nullptr)
 #pragma unroll
         for (int q = 0; q < W; ++q)
@@ -381,10 +385,12 @@ k_stream_bwd(Dims d, const float *__restrict__ gy, const float *__restrict__ a,
                 gyi[b * d.N + q] = (float)s0[q];
 }
 
-// The staged path serves per-sample all-pole [B, T] problems with FP32 data.
+// The staged path serves per-sample all-pole [B, T] problems with FP32 data
+// and rows of up to 8 taps (order-16 rows already fill most of a cache line
+// per lane and step, and the direct path keeps more of them in flight).
 inline bool stream_eligible(const Dims &d)
 {
-    return d.tv && d.layout == FILT_LAYOUT_BT && !d.has_b && d.M == 0 && d.N > 0;
+    return d.tv && d.layout == FILT_LAYOUT_BT && !d.has_b && d.M == 0 && d.N > 0 && d.N <= 8;
 }
 
 template <int W>
