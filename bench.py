@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="steps of the per-filter launch loop timed for comparison")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--bucket-chunks", default="",
+                    help="batched-ragged: fixed chunk lengths for the five order buckets "
+                         "(comma separated) instead of tuning")
     ap.add_argument("--layout", choices=["TB", "BT"], default=None,
                     help="signal layout (default: the workload's own)")
     ap.add_argument("--f32-state", action="store_true")
@@ -146,9 +149,11 @@ def batched_main(args):
     t = lambda v: torch.from_numpy(v).to(dev)
     x, a, yi, gy = t(s.x), t(s.a), t(s.yi), t(s.gy)
     samples = int(s.T.sum())
-    if args.chunk > 0:
-        # fixed chunk length for every order bucket (no tuning)
-        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off, chunks=[args.chunk] * 5)
+    if args.chunk > 0 or args.bucket_chunks:
+        # fixed chunk lengths (no tuning)
+        fixed = ([int(v) for v in args.bucket_chunks.split(",")] if args.bucket_chunks
+                 else [args.chunk] * 5)
+        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off, chunks=fixed)
         chunks = plan.chunks
     else:
         plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off)
@@ -185,13 +190,15 @@ def batched_main(args):
             F.filt_backward(gy[xo:xo + tt][None], xs, ys, as_, None, None, yis, layout="BT",
                             want=("x", "a", "yi"))
 
-    plain_step()
-    torch.cuda.synchronize()
-    p0 = time.perf_counter()
-    for _ in range(args.plain_steps):
+    plain_ms = None
+    if args.plain_steps > 0:
         plain_step()
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            plain_step()
+        torch.cuda.synchronize()
+        plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
     coef = 4 * float((s.T * s.N).sum())
     algo = 4 * samples * 2 + coef + (4 * samples * 3 + 2 * coef)   # fwd + bwd bytes
     rec = {
@@ -203,8 +210,8 @@ def batched_main(args):
                    "samples": samples, "chunks_by_order_bucket": chunks,
                    "parallelism": "single GPU"},
         "whole_step_hbm_frac": round(algo / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
-        "plain_ms_per_step": round(plain_ms, 3),
-        "batched_speedup_vs_plain": round(plain_ms / ms, 2),
+        "plain_ms_per_step": round(plain_ms, 3) if plain_ms else None,
+        "batched_speedup_vs_plain": round(plain_ms / ms, 2) if plain_ms else None,
     }
     print(json.dumps(rec), flush=True)
 

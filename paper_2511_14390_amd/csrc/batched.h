@@ -411,6 +411,21 @@ filt_status batched_stream_bwd(const BucketArgs &b, int64_t Lc, const float *gy,
     return check_launch("batched staged backward apply");
 }
 
+// Order-16 bucket backward: the direct apply writes only gx (= ybar) and the
+// per-item pass forms ga (the fused products overflow the registers).
+template <int W>
+filt_status batched_bwd_split(const BucketArgs &b, int64_t Lc, const float *gy, const float *y,
+                              const float *a, const float *yi, const double *ws, float *gx,
+                              float *ga, float *gyi, hipStream_t st)
+{
+    filt_status s = batched_bwd_apply<W>(b, gy, y, a, yi, ws, gx, nullptr, gyi, st);
+    if (s != FILT_OK || ga == nullptr || b.app_n == 0)
+        return s;
+    FILT_LAUNCH("batched_coef_grads", kb_coef_grads<W>, dim3((unsigned)b.app_n), dim3(256), 0, st,
+                b.segs, b.app_items, Lc, gx, y, yi, ga);
+    return check_launch("batched coefficient gradients");
+}
+
 #define FILT_DECLARE_BATCHED(W, EXT)                                                               \
     EXT template filt_status batched_fwd_summary<W>(const BucketArgs &, const float *,             \
                                                     const float *, double *, hipStream_t);         \

@@ -300,10 +300,13 @@ filt_status run_backward(const filt_plan *p, const float *gy, const float *y, co
     filt_status s = FILT_OK;
 #define BWD_SUM(W, B) batched_bwd_summary<W>(bucket_args(p, B, a), gy, a, p->d_ws, st)
 #define BWD_APP(W, B)                                                                              \
-    ((kStreamBucket<W> && gx != nullptr)                                                           \
+    (gx == nullptr                                                                                 \
+         ? batched_bwd_apply<W>(bucket_args(p, B, a), gy, y, a, yi, p->d_ws, gx, ga, gyi, st)       \
+     : kStreamBucket<W>                                                                            \
          ? batched_stream_bwd<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx, ga,  \
                                  gyi, st)                                                          \
-         : batched_bwd_apply<W>(bucket_args(p, B, a), gy, y, a, yi, p->d_ws, gx, ga, gyi, st))
+         : batched_bwd_split<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx, ga,   \
+                                gyi, st))
     FILT_BUCKETS(BWD_SUM)
     if (s == FILT_OK)
         s = carry_launch(p, 1, nullptr, st);
