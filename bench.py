@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CUs x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 
 
 def parse():
@@ -81,6 +82,10 @@ def kernel_bytes(p, name):
     K_b = (p.M + 1) if p.b is not None else 0
     coef = 4 * (K_a + K_b) if p.time_varying else 0
     fir = 4 if p.M > 0 else 0
+    W = 1
+    while W < max(p.N, p.M + 1):
+        W *= 2
+    split = W >= 16
     table = {
         # time-invariant [B, T] problems on the matrix cores: the tile kernels
         # move only signals (the per-channel matrices stay in L2)
@@ -90,14 +95,33 @@ def kernel_bytes(p, name):
         "tz_bwd_summary": 4,
         # forward: read x (+ coefficients), write y
         "fwd_apply": 4 + 4 + coef,
+        "stream_fwd_apply": 4 + 4 + coef,
+        # backward adjoint pass that leaves the coefficient products to a
+        # separate pass: read gy and the row, write gx (= ybar)
+        "stream_bwd_apply": 4 + coef + 4,
+        # per-sample coefficient gradients: read ybar and y, write the rows
+        "coef_grads": 4 + 4 + coef,
         # backward: read gy, y (+ x for M > 0) and coefficients; write gx and
-        # the per-sample coefficient gradients
-        "bwd_apply": 4 + 4 + fir + 4 + 2 * coef,
+        # the per-sample coefficient gradients (register bucket 16 and up
+        # leaves the products to coef_grads: read gy, the row, write gx)
+        "bwd_apply": (4 + coef + 4 + fir) if (split and p.time_varying)
+                     else (4 + 4 + fir + 4 + 2 * coef),
         # chunk summaries read their phase's inputs once
         "fwd_summary": 4 + coef,
         "bwd_summary": 4 + coef,
     }
     return table.get(name)
+
+
+def kernel_flops(p, name, chunk):
+    """FP64 FLOPs per sample of the kernels bound by vector arithmetic: the
+    per-sample chunk summaries solve N homogeneous recursions and one driven
+    one of N FMAs each per sample, over every chunk but the one with no
+    successor (forward) / predecessor (backward)."""
+    if name not in ("fwd_summary", "bwd_summary") or not p.time_varying:
+        return None
+    C = -(-p.T // chunk)
+    return 2.0 * (p.N + 1) * (p.N + p.M) * (C - 1) / C
 
 
 def source_digest():
@@ -280,7 +304,17 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"]) if kern else None
     roofline = None
     chunk = F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk))
-    if dom is not None and kernel_bytes(p, dom) is not None:
+    if dom is not None and kernel_flops(p, dom, chunk) is not None:
+        # the dominant kernel is bound by FP64 vector arithmetic (SQ counters:
+        # VALU issue), so it is measured against the FP64 vector peak
+        flop = kernel_flops(p, dom, chunk) * samples
+        ach = flop / (kern[dom]["avg_us"] * 1e-6) / 1e12
+        roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2),
+                    "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP64_VALU_PEAK_TFLOPS, 4),
+                    "traffic": counted_traffic(args.workload, p.layout, chunk, dom),
+                    "flops_per_launch": flop, "avg_launch_us": round(kern[dom]["avg_us"], 2)}
+    elif dom is not None and kernel_bytes(p, dom) is not None:
         per_launch = kernel_bytes(p, dom) * samples
         ach = per_launch / (kern[dom]["avg_us"] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
