@@ -341,6 +341,439 @@ k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
                                              c_first + cc, r);
 }
 
+// ---------------------------------------------------------------- row solves
+//
+// Per-sample coefficients of order 9..16 (the W = 16 bucket): the N
+// homogeneous solves of a chunk (the columns of Phi_c) run on one 16-lane
+// DPP row, lane j solving column j.  Lane j also loads and converts the one
+// coefficient -a_{j+1}[t] of step t; the other lanes read it through a
+// row_newbcast broadcast folded into the FMA (v_fmac_f64 takes a DPP source
+// on CDNA3/4), so a lane converts one coefficient per step instead of a whole
+// row and every FP64 instruction of the step is an FMA.  The particular solve
+// (zero state, real input) has a coefficient row of its own per lane and runs
+// as in fwd_summary_item / bwd_summary_item, on lanes of the same launch.
+//
+// The broadcast source is written by a VALU instruction shortly before each
+// step's FMAs; DPP needs 2 wait states after such a write (5 after a VALU
+// write of EXEC), hence the s_nop 4 that opens each step.  All 16 lanes of a
+// row stay active for the whole chunk (lanes j >= N carry zero coefficients).
+
+// f(std::integral_constant<int, i>) for i = 0..n-1, in order.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int n, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_seq(f, std::make_integer_sequence<int, n>{});
+}
+
+#define FILT_ROW_FMAC(lane, acc, src, mul)                                                         \
+    "v_fmac_f64_dpp %" #acc ", %" #src ", %" #mul " row_newbcast:" #lane                          \
+    " row_mask:0xf bank_mask:0xf\n"
+
+// One forward step of a row: returns sum_k c_k * h[s - k] (k = 1..16) where
+// c_k sits in lane k - 1 of the row and h[s - k] = h[(s - k) & 15].
+template <int s>
+__device__ __forceinline__ double row_fwd_step(double c, const double (&h)[16])
+{
+    double acc = 0.0;
+    asm("s_nop 4\n"
+        FILT_ROW_FMAC(15, 0, 1, 2) FILT_ROW_FMAC(14, 0, 1, 3) FILT_ROW_FMAC(13, 0, 1, 4)
+        FILT_ROW_FMAC(12, 0, 1, 5) FILT_ROW_FMAC(11, 0, 1, 6) FILT_ROW_FMAC(10, 0, 1, 7)
+        FILT_ROW_FMAC(9, 0, 1, 8) FILT_ROW_FMAC(8, 0, 1, 9) FILT_ROW_FMAC(7, 0, 1, 10)
+        FILT_ROW_FMAC(6, 0, 1, 11) FILT_ROW_FMAC(5, 0, 1, 12) FILT_ROW_FMAC(4, 0, 1, 13)
+        FILT_ROW_FMAC(3, 0, 1, 14) FILT_ROW_FMAC(2, 0, 1, 15) FILT_ROW_FMAC(1, 0, 1, 16)
+        FILT_ROW_FMAC(0, 0, 1, 17)
+        : "+v"(acc)
+        : "v"(c), "v"(h[(s + 0) & 15]), "v"(h[(s + 1) & 15]), "v"(h[(s + 2) & 15]),
+          "v"(h[(s + 3) & 15]), "v"(h[(s + 4) & 15]), "v"(h[(s + 5) & 15]),
+          "v"(h[(s + 6) & 15]), "v"(h[(s + 7) & 15]), "v"(h[(s + 8) & 15]),
+          "v"(h[(s + 9) & 15]), "v"(h[(s + 10) & 15]), "v"(h[(s + 11) & 15]),
+          "v"(h[(s + 12) & 15]), "v"(h[(s + 13) & 15]), "v"(h[(s + 14) & 15]),
+          "v"(h[(s + 15) & 15]));
+    return acc;
+}
+
+// One adjoint step of a row (transposed form, as in bwd_solves with no
+// input): ybar = s_1; s_k <- s_{k+1} + c_k ybar (s_17 = 0), with s_k in
+// ss[(k - s) & 15] before the step and c_k in lane k - 1.
+template <int s>
+__device__ __forceinline__ void row_bwd_step(double c, double (&ss)[16])
+{
+    const double yb = ss[(1 - s) & 15];
+    double nw = 0.0;
+    asm("s_nop 4\n"
+        FILT_ROW_FMAC(15, 0, 16, 17) FILT_ROW_FMAC(0, 1, 16, 17) FILT_ROW_FMAC(1, 2, 16, 17)
+        FILT_ROW_FMAC(2, 3, 16, 17) FILT_ROW_FMAC(3, 4, 16, 17) FILT_ROW_FMAC(4, 5, 16, 17)
+        FILT_ROW_FMAC(5, 6, 16, 17) FILT_ROW_FMAC(6, 7, 16, 17) FILT_ROW_FMAC(7, 8, 16, 17)
+        FILT_ROW_FMAC(8, 9, 16, 17) FILT_ROW_FMAC(9, 10, 16, 17) FILT_ROW_FMAC(10, 11, 16, 17)
+        FILT_ROW_FMAC(11, 12, 16, 17) FILT_ROW_FMAC(12, 13, 16, 17)
+        FILT_ROW_FMAC(13, 14, 16, 17) FILT_ROW_FMAC(14, 15, 16, 17)
+        : "+v"(nw), "+v"(ss[(2 - s) & 15]), "+v"(ss[(3 - s) & 15]), "+v"(ss[(4 - s) & 15]),
+          "+v"(ss[(5 - s) & 15]), "+v"(ss[(6 - s) & 15]), "+v"(ss[(7 - s) & 15]),
+          "+v"(ss[(8 - s) & 15]), "+v"(ss[(9 - s) & 15]), "+v"(ss[(10 - s) & 15]),
+          "+v"(ss[(11 - s) & 15]), "+v"(ss[(12 - s) & 15]), "+v"(ss[(13 - s) & 15]),
+          "+v"(ss[(14 - s) & 15]), "+v"(ss[(15 - s) & 15]), "+v"(ss[(16 - s) & 15])
+        : "v"(c), "v"(yb));
+    ss[(1 - s) & 15] = nw;
+}
+
+#undef FILT_ROW_FMAC
+
+// Coefficient stream of one row lane: -a_{j+1}[t] for the chunk's steps in
+// increasing (forward) or decreasing (adjoint) time, 16 steps ahead of use.
+// Lanes j >= N read tap N - 1 and zero it.  Chunks with a successor (and, in
+// the adjoint, chunks 1..C-1) are whole, so every step read lies in the chunk
+// and the reads stop at its end.
+template <typename io_t, bool FULL>
+struct RowCoef {
+    const io_t *p;   // tap of this lane at the chunk's first step
+    int64_t stride;  // elements per time step
+    bool live;       // j < N
+
+    __device__ __forceinline__ double cvt(io_t raw) const
+    {
+        if constexpr (!FULL)
+            raw = live ? raw : io_t(0);
+        return -(double)raw;
+    }
+};
+
+template <typename io_t, bool FULL>
+__device__ __forceinline__ RowCoef<io_t, FULL> row_coef(const Dims &d, const io_t *ac, int64_t b,
+                                                        int64_t c, int j)
+{
+    RowCoef<io_t, FULL> r;
+    const int64_t t0 = c * d.L;
+    const int jj = j < d.N ? j : d.N - 1;
+    const bool tb = d.layout == FILT_LAYOUT_TB;
+    r.p = ac + (tb ? t0 * d.B + b : b * d.T + t0) * (int64_t)d.N + jj;
+    r.stride = (tb ? d.B : 1) * (int64_t)d.N;
+    r.live = j < d.N;
+    return r;
+}
+
+// Column j of Phi_c (unit state y(t0 - 1 - j) = 1, no input) on a row lane.
+template <bool FULL, typename io_t>
+__device__ __forceinline__ void fwd_row_item(const Dims &d, const io_t *__restrict__ ac,
+                                             double *__restrict__ summ, int64_t b, int64_t c,
+                                             int j)
+{
+    const RowCoef<io_t, FULL> rc = row_coef<io_t, FULL>(d, ac, b, c, j);
+    double h[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+        h[e] = (rc.live && e == ((-1 - j) & 15)) ? 1.0 : 0.0;
+    io_t buf[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        buf[s] = rc.p[s * rc.stride];
+    for (int rel = 0; rel < d.L; rel += 16) {
+        static_for<16>([&](auto I) {
+            constexpr int s = decltype(I)::value;
+            const double cf = rc.cvt(buf[s]);
+            // step rel + 16 + s; the last block re-reads the chunk's last row
+            // (unconditional loads keep the ring free of merges and waits)
+            buf[s] = rc.p[(int64_t)min(rel + 16 + s, (int)d.L - 1) * rc.stride];
+            h[s] = row_fwd_step<s>(cf, h);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+    // the chunk length is a multiple of 16: y(t_end - 1 - i) sits in h[15 - i]
+    if (rc.live) {
+        double *o = summ + (b * d.C + c) * ((int64_t)d.N * d.N + d.N) + j;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < d.N)
+                o[(int64_t)i * d.N] = h[15 - i];
+    }
+}
+
+// Column j of the adjoint chunk map (unit state s_{j+1} = 1, no input).
+template <bool FULL, typename io_t>
+__device__ __forceinline__ void bwd_row_item(const Dims &d, const io_t *__restrict__ ac,
+                                             double *__restrict__ summ, int64_t b, int64_t c,
+                                             int j)
+{
+    const RowCoef<io_t, FULL> rc = row_coef<io_t, FULL>(d, ac, b, c, j);
+    double *o = summ + (b * d.C + c) * ((int64_t)(d.N + 1) * d.N) + j;
+    if (c * d.L + d.L > d.T) {
+        // a last chunk cut short by the signal's end: no adjoint state enters
+        // it from above, so its map only ever multiplies zero; store zero
+        // rather than reading coefficients past T
+        if (rc.live)
+            for (int i = 0; i < d.N; ++i)
+                o[(int64_t)i * d.N] = 0.0;
+        return;
+    }
+    // s_k in ss[(k - s) & 15] before relative step s; the first step is
+    // s = L - 1 = 15 (mod 16)
+    double ss[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+        ss[e] = (rc.live && e == ((j + 2) & 15)) ? 1.0 : 0.0;
+    io_t buf[16];
+    const io_t *top = rc.p + (int64_t)(d.L - 16) * rc.stride;
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        buf[s] = top[s * rc.stride];
+    for (int rel = d.L - 16; rel >= 0; rel -= 16) {
+        static_for<16>([&](auto I) {
+            constexpr int s = 15 - decltype(I)::value;
+            const double cf = rc.cvt(buf[s]);
+            // step rel - 16 + s; the last block re-reads the chunk's first row
+            buf[s] = rc.p[(int64_t)max(rel - 16 + s, 0) * rc.stride];
+            row_bwd_step<s>(cf, ss);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+    }
+    // after the chunk's first step s_k sits in ss[(k + 1) & 15]
+    if (rc.live) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < d.N)
+                o[(int64_t)i * d.N] = ss[(i + 2) & 15];
+    }
+}
+
+// Particular solves on quads.  The zero-state solve driven by the input (the
+// s_c part of a summary) is one recursion per chunk; it runs on 4 adjacent
+// lanes, lane q owning taps k = 4q + 1 .. 4q + 4 (one 16-byte load of the
+// coefficient row per step).  Forward: lane q keeps w[i] = y[t - 4q - 1 - i],
+// forms its part of sum_k a_k[t] y[t - k], and a quad butterfly adds the four
+// parts (every lane ends with the same sum: FP64 addition is commutative);
+// the window then moves by one sample, lane q taking lane q - 1's oldest.
+// Adjoint (transposed form): lane q keeps st[i] = s_{4q+1+i}; ybar = g + s_1
+// comes from lane 0 and s_k <- s_{k+1} - a_k ybar shifts within the lane,
+// s_{4q+5} arriving from lane q + 1 (zero past the last lane).
+template <int CTRL>
+__device__ __forceinline__ double quad_dpp(double v)
+{
+    // every source lane of a quad_perm is live, so bound_ctrl only spares the
+    // move that would preload an "old" value
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, true);
+}
+constexpr int kQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kQuadFromPrev = 0x90;  // quad_perm [0,0,1,2]: lane q reads lane q - 1
+constexpr int kQuadFromNext = 0xF9;  // quad_perm [1,2,3,3]: lane q reads lane q + 1
+constexpr int kQuadLane0 = 0x00;     // quad_perm [0,0,0,0]
+
+constexpr int kQuadPrefetch = 4;  // steps in flight (chunk lengths are multiples of 32)
+
+template <typename io_t>
+struct QuadRaw {
+    io_t a[4];  // taps 4q .. 4q + 3 of the coefficient row (a_{4q+1} .. a_{4q+4})
+    io_t s, g;  // signal sample and its gain (b_0, or 1 without b)
+};
+
+// Taps 4q .. 4q + 3 of one coefficient row (N == 16 and 16-byte aligned rows
+// with AV; else element loads, clamped into the row and zeroed on use).
+template <bool AV, typename io_t>
+__device__ __forceinline__ void quad_taps(const io_t *row, int q, int N, io_t (&v)[4])
+{
+    if constexpr (AV && sizeof(io_t) == 4) {
+        const float4 f = *reinterpret_cast<const float4 *>(row + 4 * q);
+        v[0] = f.x;
+        v[1] = f.y;
+        v[2] = f.z;
+        v[3] = f.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] = row[min(4 * q + i, N - 1)];
+    }
+}
+
+// -a_{4q+1+i} as a double (zero for taps past N).
+template <bool AV, typename io_t>
+__device__ __forceinline__ double quad_coef(const io_t (&v)[4], int i, int q, int N)
+{
+    if constexpr (AV && sizeof(io_t) == 4)
+        return -(double)v[i];
+    else
+        return 4 * q + i < N ? -(double)v[i] : 0.0;
+}
+
+// s_c of chunk c (zero state, real input), forward.  The chunk is whole.
+// HASB: per-sample gains b_0[t] (an FIR part of order 0).
+template <bool AV, bool HASB, typename io_t>
+__device__ __forceinline__ void fwd_part_quad(const Dims &d, const io_t *__restrict__ x,
+                                              const io_t *__restrict__ bc,
+                                              const io_t *__restrict__ ac,
+                                              double *__restrict__ summ, int64_t b, int64_t c,
+                                              int q)
+{
+    constexpr int P = kQuadPrefetch;
+    const int N = d.N;
+    const bool tb = d.layout == FILT_LAYOUT_TB;
+    const int64_t e0 = tb ? c * d.L * d.B + b : b * d.T + c * d.L;
+    const int64_t es = tb ? d.B : 1;
+    const io_t *xp = x + e0;
+    const io_t *ap = ac + e0 * N;
+    const io_t *gp = HASB ? bc + e0 : nullptr;
+    const int64_t as = es * N;
+    auto fetch = [&](int rel, QuadRaw<io_t> &r) {
+        quad_taps<AV>(ap + rel * as, q, N, r.a);
+        r.s = xp[rel * es];
+        if constexpr (HASB)
+            r.g = gp[rel * es];
+    };
+    QuadRaw<io_t> buf[P];
+    static_for<P>([&](auto I) { fetch(decltype(I)::value, buf[decltype(I)::value]); });
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int rel = 0; rel < d.L; rel += P) {
+        static_for<P>([&](auto I) {
+            constexpr int s = decltype(I)::value;
+            const QuadRaw<io_t> r = buf[s];
+            fetch(min(rel + P + s, (int)d.L - 1), buf[s]);  // unconditional, clamped into the chunk
+            double p = 0.0;
+#pragma unroll
+            for (int i = 3; i >= 0; --i)
+                p = __builtin_fma(quad_coef<AV>(r.a, i, q, N), w[i], p);
+            double tot = p + quad_dpp<kQuadXor1>(p);
+            tot = tot + quad_dpp<kQuadXor2>(tot);
+            const double y = HASB ? __builtin_fma((double)r.g, (double)r.s, tot)
+                                  : (double)r.s + tot;
+            const double prev = quad_dpp<kQuadFromPrev>(w[3]);
+            w[3] = w[2];
+            w[2] = w[1];
+            w[1] = w[0];
+            w[0] = q == 0 ? y : prev;
+        });
+    }
+    // w[i] = y[t_end - 1 - (4q + i)] = s_c[4q + i]
+    double *o = summ + (b * d.C + c) * ((int64_t)N * N + N) + (int64_t)N * N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (4 * q + i < N)
+            o[4 * q + i] = w[i];
+}
+
+// Particular part of the adjoint map of chunk c (zero state at its top, the
+// real gy).  CLAMP: a last chunk cut short by the signal's end; its steps
+// past T read clamped rows and a zero gy, leaving the state zero.
+template <bool AV, bool CLAMP, typename io_t>
+__device__ __forceinline__ void bwd_part_quad(const Dims &d, const io_t *__restrict__ gy,
+                                              const io_t *__restrict__ ac,
+                                              double *__restrict__ summ, int64_t b, int64_t c,
+                                              int q)
+{
+    constexpr int P = kQuadPrefetch;
+    const int N = d.N;
+    const bool tb = d.layout == FILT_LAYOUT_TB;
+    const int64_t e0 = tb ? c * d.L * d.B + b : b * d.T + c * d.L;
+    const int64_t es = tb ? d.B : 1;
+    const int last = CLAMP ? (int)min<int64_t>(d.T - 1 - c * d.L, d.L - 1) : d.L - 1;
+    const io_t *gp = gy + e0;
+    const io_t *ap = ac + e0 * N;
+    const int64_t as = es * N;
+    auto fetch = [&](int rel, QuadRaw<io_t> &r) {
+        const int rc = CLAMP ? min(rel, last) : rel;
+        quad_taps<AV>(ap + rc * as, q, N, r.a);
+        const io_t g = gp[rc * es];
+        r.s = (!CLAMP || rel <= last) ? g : io_t(0);
+    };
+    QuadRaw<io_t> buf[P];
+    static_for<P>([&](auto I) {
+        fetch(d.L - P + decltype(I)::value, buf[decltype(I)::value]);
+    });
+    double st[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int rel = d.L - P; rel >= 0; rel -= P) {
+        static_for<P>([&](auto I) {
+            constexpr int s = P - 1 - decltype(I)::value;
+            const QuadRaw<io_t> r = buf[s];
+            fetch(max(rel - P + s, 0), buf[s]);  // unconditional, clamped into the chunk
+            const double yb = (double)r.s + quad_dpp<kQuadLane0>(st[0]);
+            const double nx = quad_dpp<kQuadFromNext>(st[0]);
+            st[0] = __builtin_fma(quad_coef<AV>(r.a, 0, q, N), yb, st[1]);
+            st[1] = __builtin_fma(quad_coef<AV>(r.a, 1, q, N), yb, st[2]);
+            st[2] = __builtin_fma(quad_coef<AV>(r.a, 2, q, N), yb, st[3]);
+            st[3] = __builtin_fma(quad_coef<AV>(r.a, 3, q, N), yb, q == 3 ? 0.0 : nx);
+        });
+    }
+    double *o = summ + (b * d.C + c) * ((int64_t)(N + 1) * N) + (int64_t)N * N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (4 * q + i < N)
+            o[4 * q + i] = st[i];
+}
+
+// Workgroups of kRowGroupThreads threads cover kRowGroupChunks consecutive
+// items (b, chunk): waves 0-3 hold one 16-lane row per item, wave 4 the
+// items' particular solves (a quad each; with an FIR part, one lane each).
+// The rows and the particular solves read the same coefficient rows; keeping
+// them in one workgroup, advancing through the chunk together, makes the
+// second read of each row a cache hit instead of a second pass over HBM.
+constexpr int kRowGroupChunks = 16;
+constexpr int kRowGroupThreads = 16 * kRowGroupChunks + 64;
+
+template <bool FIR, bool AV, bool FULL, typename io_t>
+__global__ void __launch_bounds__(kRowGroupThreads, 5)
+k_fwd_summary_rows(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
+                   const io_t *__restrict__ bc, const io_t *__restrict__ ac, int64_t ncs,
+                   double *__restrict__ summ)
+{
+    const int64_t n = d.B * ncs;
+    const int64_t first = (int64_t)blockIdx.x * kRowGroupChunks;
+    const int t = threadIdx.x;
+    int64_t b, cc;
+    int r;
+    if (t >= 16 * kRowGroupChunks) {
+        const int u = t - 16 * kRowGroupChunks;
+        if constexpr (FIR) {
+            if (u >= kRowGroupChunks || first + u >= n)
+                return;
+            decode_lanes(d, first + u, ncs, 1, b, cc, r);
+            fwd_summary_item<16, 1, true, FIR, true, AV>(d, x, xi, bc, ac, d.N, 1, summ, nullptr,
+                                                         b, cc, 0);
+        } else {
+            if (first + (u >> 2) >= n)  // whole quads only
+                return;
+            decode_lanes(d, first + (u >> 2), ncs, 1, b, cc, r);
+            if (d.has_b)
+                fwd_part_quad<AV, true>(d, x, bc, ac, summ, b, cc, u & 3);
+            else
+                fwd_part_quad<AV, false>(d, x, bc, ac, summ, b, cc, u & 3);
+        }
+        return;
+    }
+    if (first + (t >> 4) >= n)  // whole rows only
+        return;
+    decode_lanes(d, first + (t >> 4), ncs, 1, b, cc, r);
+    fwd_row_item<FULL>(d, ac, summ, b, cc, t & 15);
+}
+
+template <bool AV, bool FULL, typename io_t>
+__global__ void __launch_bounds__(kRowGroupThreads, 5)
+k_bwd_summary_rows(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ ac, int64_t ncs,
+                   double *__restrict__ summ)
+{
+    const int64_t n = d.B * ncs;
+    const int64_t first = (int64_t)blockIdx.x * kRowGroupChunks;
+    const int t = threadIdx.x;
+    int64_t b, cc;
+    int r;
+    if (t >= 16 * kRowGroupChunks) {
+        const int u = t - 16 * kRowGroupChunks;
+        if (first + (u >> 2) >= n)
+            return;
+        decode_lanes(d, first + (u >> 2), ncs, 1, b, cc, r);
+        if ((cc + 2) * d.L > d.T)
+            bwd_part_quad<AV, true>(d, gy, ac, summ, b, cc + 1, u & 3);
+        else
+            bwd_part_quad<AV, false>(d, gy, ac, summ, b, cc + 1, u & 3);
+        return;
+    }
+    if (first + (t >> 4) >= n)
+        return;
+    decode_lanes(d, first + (t >> 4), ncs, 1, b, cc, r);
+    bwd_row_item<FULL>(d, ac, summ, b, cc + 1, t & 15);
+}
+
 // ---------------------------------------------------------------- launch
 
 template <int W, bool FIR, typename io_t>
@@ -349,6 +782,24 @@ filt_status fwd_summary_fir(const Dims &d, const io_t *x, const io_t *xi, const 
 {
     const int N = d.N;
     const int64_t ncs = d.C - 1;  // chunks with a successor
+    if constexpr (W == 16) {
+        if (d.tv) {
+            const unsigned gr = (unsigned)((d.B * ncs + kRowGroupChunks - 1) / kRowGroupChunks);
+#define FILT_ROWS(AV, FULL)                                                                        \
+    FILT_LAUNCH("fwd_summary", (k_fwd_summary_rows<FIR, AV, FULL, io_t>), dim3(gr),               \
+                dim3(kRowGroupThreads), 0, st, d, x, xi, bc, ac, ncs, summ)
+            if (d.a_vec) {
+                if (N == 16)
+                    FILT_ROWS(true, true);
+                else
+                    FILT_ROWS(true, false);
+            } else {
+                FILT_ROWS(false, false);
+            }
+#undef FILT_ROWS
+            return check_launch("forward summary");
+        }
+    }
     if (d.tv) {
         constexpr int S = SummarySlots<W>::value;
         const int nl = (N + 1 + S - 1) / S;
@@ -386,6 +837,24 @@ filt_status bwd_summary_fir(const Dims &d, const io_t *gy, const io_t *bc, const
 {
     const int N = d.N;
     const int64_t ncs = d.C - 1;  // chunks 1..C-1 pass a state to an earlier chunk
+    if constexpr (W == 16 && !FIR) {
+        if (d.tv) {
+            const unsigned gr = (unsigned)((d.B * ncs + kRowGroupChunks - 1) / kRowGroupChunks);
+#define FILT_ROWS(AV, FULL)                                                                        \
+    FILT_LAUNCH("bwd_summary", (k_bwd_summary_rows<AV, FULL, io_t>), dim3(gr),                    \
+                dim3(kRowGroupThreads), 0, st, d, gy, ac, ncs, summ)
+            if (d.a_vec) {
+                if (N == 16)
+                    FILT_ROWS(true, true);
+                else
+                    FILT_ROWS(true, false);
+            } else {
+                FILT_ROWS(false, false);
+            }
+#undef FILT_ROWS
+            return check_launch("backward summary");
+        }
+    }
     if (d.tv) {
         constexpr int S = SummarySlots<W>::value;
         const int nl = (N + 1 + S - 1) / S;

@@ -74,6 +74,8 @@ CASES = [
     (0, 16, True, "BT", 2500, 128),
     (1, 16, True, "TB", 700, 64),
     (16, 16, True, "BT", 640, 64),
+    (0, 12, True, "TB", 1000, 96),
+    (2, 13, True, "BT", 845, 64),
     (16, 2, False, "TB", 500, 32),
     (5, 0, False, "BT", 400, 64),
     (3, 0, True, "TB", 300, 32),
