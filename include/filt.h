@@ -192,6 +192,11 @@ int64_t filt_auto_chunk(const filt_problem *p);
  * of max_entries * 64 chars, counts / total_ms host arrays of max_entries.
  * Returns the number of entries filled.  Not thread-safe. */
 filt_status filt_profile_enable(int on);
+/* Restrict the recording to launches of one kernel name (as reported by
+ * filt_profile_read), so that a timed loop carries two events per launch of
+ * that kernel only; NULL (or "") records every launch again.  name is a host
+ * string of at most 63 characters, copied; FILT_EINVAL if longer. */
+filt_status filt_profile_only(const char *name);
 int filt_profile_read(char *names, int32_t *counts, double *total_ms, int max_entries);
 
 /* Text of a status code, and the last error message of the calling thread. */

@@ -35,10 +35,13 @@ int g_prof_nev = 0;        // events created
 int g_prof_used = 0;       // events handed out
 ProfRec g_prof_rec[kProfEvents / 2];
 int g_prof_nrec = 0;
+char g_prof_only[64] = "";  // record only launches of this name (empty: all)
 
 int prof_begin(const char *name, hipStream_t st)
 {
     if (!g_prof_on || g_prof_used + 2 > g_prof_nev)
+        return -1;
+    if (g_prof_only[0] != 0 && strncmp(name, g_prof_only, sizeof g_prof_only) != 0)
         return -1;
     const int r = g_prof_nrec++;
     g_prof_rec[r].name = name;
@@ -379,6 +382,18 @@ filt_status filt_profile_enable(int on)
         g_prof_nrec = 0;
     }
     g_prof_on = on != 0;
+    return FILT_OK;
+}
+
+filt_status filt_profile_only(const char *name)
+{
+    if (name == nullptr) {
+        g_prof_only[0] = 0;
+        return FILT_OK;
+    }
+    if (strlen(name) >= sizeof g_prof_only)
+        return fail(FILT_EINVAL, "kernel name longer than %zu characters", sizeof g_prof_only - 1);
+    strcpy(g_prof_only, name);
     return FILT_OK;
 }
 

@@ -206,6 +206,14 @@ def profile_enable(on: bool):
     _check(L.filt_profile_enable(1 if on else 0))
 
 
+def profile_only(name):
+    """Record only launches of kernel `name` (None: every launch)."""
+    L = lib()
+    L.filt_profile_only.argtypes = [ctypes.c_char_p]
+    L.filt_profile_only.restype = ctypes.c_int
+    _check(L.filt_profile_only(None if name is None else name.encode()))
+
+
 def profile_read(max_entries: int = 64):
     """{kernel name: (launches, total ms)} of the recorded launches (synchronises)."""
     L = lib()
