@@ -283,6 +283,71 @@ inline void persistent_grid(int64_t n, unsigned &blocks, unsigned &threads)
     blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
 }
 
+// Order-16 bucket: summaries on DPP rows (summary.h).  Items are (seg,
+// chunk), kRowGroupChunks of them per workgroup: waves 0-3 one 16-lane row per
+// item, wave 4 the items' particular solves (a quad each).  Every segment of
+// the bucket has the same chunk length, so the rows of a wave run in step.
+// FULL: every segment has order 16 and 16-byte aligned rows.
+template <bool FULL>
+__global__ void __launch_bounds__(kRowGroupThreads, 5)
+kb_fwd_summary_rows(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+                    const float *__restrict__ x, const float *__restrict__ a,
+                    double *__restrict__ ws)
+{
+    const int t = threadIdx.x;
+    for (int64_t first = (int64_t)blockIdx.x * kRowGroupChunks; first < n;
+         first += (int64_t)gridDim.x * kRowGroupChunks) {
+        const int k = t >= 16 * kRowGroupChunks ? (t - 16 * kRowGroupChunks) >> 2 : t >> 4;
+        if (first + k >= n)  // whole rows and quads
+            continue;
+        const Item it = items[first + k];
+        const SegDesc sd = segs[it.seg];
+        const Dims d = seg_dims(sd);
+        if (t >= 16 * kRowGroupChunks)
+            fwd_part_quad<FULL, false>(d, x + sd.x_off, (const float *)nullptr, a + sd.a_off,
+                                       ws + sd.summ_off, 0, it.chunk, t & 3);
+        else
+            fwd_row_item<FULL>(d, a + sd.a_off, ws + sd.summ_off, 0, it.chunk, t & 15);
+    }
+}
+
+template <bool FULL>
+__global__ void __launch_bounds__(kRowGroupThreads, 5)
+kb_bwd_summary_rows(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+                    const float *__restrict__ gy, const float *__restrict__ a,
+                    double *__restrict__ ws)
+{
+    const int t = threadIdx.x;
+    for (int64_t first = (int64_t)blockIdx.x * kRowGroupChunks; first < n;
+         first += (int64_t)gridDim.x * kRowGroupChunks) {
+        const int k = t >= 16 * kRowGroupChunks ? (t - 16 * kRowGroupChunks) >> 2 : t >> 4;
+        if (first + k >= n)
+            continue;
+        const Item it = items[first + k];
+        const SegDesc sd = segs[it.seg];
+        const Dims d = seg_dims(sd);
+        const int64_t c = it.chunk + 1;  // chunks 1..C-1 pass a state to an earlier chunk
+        if (t >= 16 * kRowGroupChunks) {
+            if ((c + 1) * d.L > d.T)
+                bwd_part_quad<FULL, true>(d, gy + sd.x_off, a + sd.a_off, ws + sd.summ_off, 0, c,
+                                          t & 3);
+            else
+                bwd_part_quad<FULL, false>(d, gy + sd.x_off, a + sd.a_off, ws + sd.summ_off, 0, c,
+                                           t & 3);
+        } else {
+            bwd_row_item<FULL>(d, a + sd.a_off, ws + sd.summ_off, 0, c, t & 15);
+        }
+    }
+}
+
+// Workgroups for the row summaries: one per kRowGroupChunks items, at most
+// four per CU (five waves each, all resident).
+inline unsigned row_groups(int64_t n)
+{
+    const int64_t want = (n + kRowGroupChunks - 1) / kRowGroupChunks;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kCUs * 4));
+}
+
 // One bucket's launches (defined per bucket in generated units).
 struct BucketArgs {
     const SegDesc *segs;
@@ -299,6 +364,16 @@ filt_status batched_fwd_summary(const BucketArgs &b, const float *x, const float
 {
     if (b.sum_n == 0)
         return FILT_OK;
+    if constexpr (W == 16) {
+        if (b.av)
+            FILT_LAUNCH("batched_fwd_summary", kb_fwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
+                        dim3(kRowGroupThreads), 0, st, b.segs, b.sum_items, b.sum_n, x, a, ws);
+        else
+            FILT_LAUNCH("batched_fwd_summary", kb_fwd_summary_rows<false>,
+                        dim3(row_groups(b.sum_n)), dim3(kRowGroupThreads), 0, st, b.segs,
+                        b.sum_items, b.sum_n, x, a, ws);
+        return check_launch("batched forward summary");
+    }
     unsigned g, t;
     persistent_grid(b.sum_n, g, t);
     if (b.av)
@@ -316,6 +391,16 @@ filt_status batched_bwd_summary(const BucketArgs &b, const float *gy, const floa
 {
     if (b.sum_n == 0)
         return FILT_OK;
+    if constexpr (W == 16) {
+        if (b.av)
+            FILT_LAUNCH("batched_bwd_summary", kb_bwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
+                        dim3(kRowGroupThreads), 0, st, b.segs, b.sum_items, b.sum_n, gy, a, ws);
+        else
+            FILT_LAUNCH("batched_bwd_summary", kb_bwd_summary_rows<false>,
+                        dim3(row_groups(b.sum_n)), dim3(kRowGroupThreads), 0, st, b.segs,
+                        b.sum_items, b.sum_n, gy, a, ws);
+        return check_launch("batched backward summary");
+    }
     unsigned g, t;
     persistent_grid(b.sum_n, g, t);
     if (b.av)

@@ -185,7 +185,9 @@ filt_status plan_layout(filt_plan *p)
             p->bucket_av[b] = p->bucket_av[b] && sd[i].a_vec;
             if (p->segs[i].N == 0)
                 continue;
-            const int nl = (sd[i].N + 1 + S - 1) / S;
+            // order-16 bucket: one item per chunk (a DPP row and a quad);
+            // else nl lanes of S solves each
+            const int nl = W == 16 ? 1 : (sd[i].N + 1 + S - 1) / S;
             for (int64_t c = 0; c + 1 < sd[i].C; ++c)
                 for (int r = 0; r < nl; ++r)
                     items.push_back(Item{i, (int32_t)c, r, 0});
