@@ -294,20 +294,18 @@ kb_fwd_summary_rows(const SegDesc *__restrict__ segs, const Item *__restrict__ i
                     const float *__restrict__ x, const float *__restrict__ a,
                     double *__restrict__ ws)
 {
+    __shared__ float hand[2][kHandSteps][16][16];
     const int t = threadIdx.x;
+    const int k = t >= 16 * kRowGroupChunks ? (t - 16 * kRowGroupChunks) >> 2 : t >> 4;
+    // every thread of the workgroup takes the same passes (the group holds
+    // barriers); a lane past the end works on the last item and stores nothing
     for (int64_t first = (int64_t)blockIdx.x * kRowGroupChunks; first < n;
          first += (int64_t)gridDim.x * kRowGroupChunks) {
-        const int k = t >= 16 * kRowGroupChunks ? (t - 16 * kRowGroupChunks) >> 2 : t >> 4;
-        if (first + k >= n)  // whole rows and quads
-            continue;
-        const Item it = items[first + k];
+        const bool act = first + k < n;
+        const Item it = items[act ? first + k : n - 1];
         const SegDesc sd = segs[it.seg];
-        const Dims d = seg_dims(sd);
-        if (t >= 16 * kRowGroupChunks)
-            fwd_part_quad<FULL, false>(d, x + sd.x_off, (const float *)nullptr, a + sd.a_off,
-                                       ws + sd.summ_off, 0, it.chunk, t & 3);
-        else
-            fwd_row_item<FULL>(d, a + sd.a_off, ws + sd.summ_off, 0, it.chunk, t & 15);
+        fwd_rows_group<FULL, false>(seg_dims(sd), x + sd.x_off, (const float *)nullptr,
+                                    a + sd.a_off, ws + sd.summ_off, 0, it.chunk, act, hand);
     }
 }
 

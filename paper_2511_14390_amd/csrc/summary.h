@@ -562,6 +562,11 @@ constexpr int kQuadFromPrev = 0x90;  // quad_perm [0,0,1,2]: lane q reads lane q
 constexpr int kQuadFromNext = 0xF9;  // quad_perm [1,2,3,3]: lane q reads lane q + 1
 constexpr int kQuadLane0 = 0x00;     // quad_perm [0,0,0,0]
 
+// Workgroups of the row summaries: kRowGroupChunks items, waves 0-3 their
+// rows, wave 4 their particular solves.
+constexpr int kRowGroupChunks = 16;
+constexpr int kRowGroupThreads = 16 * kRowGroupChunks + 64;
+
 constexpr int kQuadPrefetch = 4;  // steps in flight (chunk lengths are multiples of 32)
 
 template <typename io_t>
@@ -598,59 +603,139 @@ __device__ __forceinline__ double quad_coef(const io_t (&v)[4], int i, int q, in
         return 4 * q + i < N ? -(double)v[i] : 0.0;
 }
 
-// s_c of chunk c (zero state, real input), forward.  The chunk is whole.
-// HASB: per-sample gains b_0[t] (an FIR part of order 0).
-template <bool AV, bool HASB, typename io_t>
-__device__ __forceinline__ void fwd_part_quad(const Dims &d, const io_t *__restrict__ x,
-                                              const io_t *__restrict__ bc,
-                                              const io_t *__restrict__ ac,
-                                              double *__restrict__ summ, int64_t b, int64_t c,
-                                              int q)
+// Forward summaries of one workgroup's items, reading the coefficient rows
+// once.  The row lanes park every raw coefficient they consume in LDS (hand:
+// two buffers of kHandSteps steps x 16 items x 16 taps) and the quad wave
+// takes its taps from there, kHandSteps steps behind the rows, instead of
+// loading the rows from HBM a second time.  Per 16-step block each wave
+// passes two barriers (rows: write buffer 0, barrier, write buffer 1,
+// barrier; quad: read buffer 1 of the block before, barrier, read buffer 0,
+// barrier), L / 16 + 1 blocks in all, so L must be the same for every item
+// of the workgroup.  The roles are wave-uniform; (b, c) is the item of this
+// lane's row (threads below 16 kRowGroupChunks) or quad, and a lane whose
+// item does not exist (act false) still runs every barrier, computing on a
+// valid chunk and storing nothing.  Every chunk summarised here is whole.
+constexpr int kHandSteps = 8;
+
+template <bool FULL, bool HASB, typename io_t>
+__device__ __forceinline__ void fwd_rows_group(const Dims &d, const io_t *__restrict__ x,
+                                               const io_t *__restrict__ bc,
+                                               const io_t *__restrict__ ac,
+                                               double *__restrict__ summ, int64_t b,
+                                               int64_t c, bool act,
+                                               io_t (*hand)[kHandSteps][16][16])
 {
-    constexpr int P = kQuadPrefetch;
+    using H0 = std::integral_constant<int, 0>;
+    using H1 = std::integral_constant<int, 1>;
+    const int t = threadIdx.x;
+    const int nblk = (int)(d.L / 16);
     const int N = d.N;
+    if (t < 16 * kRowGroupChunks) {
+        const int row = t >> 4, j = t & 15;
+        const RowCoef<io_t, FULL> rc = row_coef<io_t, FULL>(d, ac, b, c, j);
+        double h[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            h[e] = (rc.live && e == ((-1 - j) & 15)) ? 1.0 : 0.0;
+        io_t buf[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+            buf[s] = rc.p[s * rc.stride];
+        // steps 8 HH .. 8 HH + 7 of the block at rel; raw values to hand[HH]
+        auto half = [&](auto HH, int rel) {
+            static_for<kHandSteps>([&](auto I) {
+                constexpr int s = decltype(HH)::value * kHandSteps + decltype(I)::value;
+                hand[decltype(HH)::value][decltype(I)::value][row][j] = buf[s];
+                const double cf = rc.cvt(buf[s]);
+                buf[s] = rc.p[(int64_t)min(rel + 16 + s, (int)d.L - 1) * rc.stride];
+                h[s] = row_fwd_step<s>(cf, h);
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        };
+        for (int kb = 0; kb <= nblk; ++kb) {
+            if (kb < nblk)
+                half(H0{}, 16 * kb);
+            __syncthreads();
+            if (kb < nblk)
+                half(H1{}, 16 * kb);
+            __syncthreads();
+        }
+        if (act && rc.live) {
+            double *o = summ + (b * d.C + c) * ((int64_t)N * N + N) + j;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < N)
+                    o[(int64_t)i * N] = h[15 - i];
+        }
+        return;
+    }
+    const int u = t - 16 * kRowGroupChunks;
+    const int k = u >> 2, q = u & 3;
     const bool tb = d.layout == FILT_LAYOUT_TB;
     const int64_t e0 = tb ? c * d.L * d.B + b : b * d.T + c * d.L;
     const int64_t es = tb ? d.B : 1;
     const io_t *xp = x + e0;
-    const io_t *ap = ac + e0 * N;
-    const io_t *gp = HASB ? bc + e0 : nullptr;
-    const int64_t as = es * N;
-    auto fetch = [&](int rel, QuadRaw<io_t> &r) {
-        quad_taps<AV>(ap + rel * as, q, N, r.a);
-        r.s = xp[rel * es];
+    const io_t *gp = HASB ? bc + e0 : xp;  // order-0 FIR part: one tap per row
+    io_t xb[16], gb[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        xb[s] = xp[s * es];
         if constexpr (HASB)
-            r.g = gp[rel * es];
-    };
-    QuadRaw<io_t> buf[P];
-    static_for<P>([&](auto I) { fetch(decltype(I)::value, buf[decltype(I)::value]); });
-    double w[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int rel = 0; rel < d.L; rel += P) {
-        static_for<P>([&](auto I) {
-            constexpr int s = decltype(I)::value;
-            const QuadRaw<io_t> r = buf[s];
-            fetch(min(rel + P + s, (int)d.L - 1), buf[s]);  // unconditional, clamped into the chunk
+            gb[s] = gp[s * es];
+    }
+    double w[4] = {0.0, 0.0, 0.0, 0.0};  // w[i] = y[t - 4q - 1 - i]
+    // steps 8 HH .. 8 HH + 7 of the block at rel, taps from hand[HH]
+    auto qhalf = [&](auto HH, int rel) {
+        static_for<kHandSteps>([&](auto I) {
+            constexpr int s = decltype(HH)::value * kHandSteps + decltype(I)::value;
+            const io_t *hp = &hand[decltype(HH)::value][decltype(I)::value][k][4 * q];
+            io_t a4[4];
+            if constexpr (sizeof(io_t) == 4) {
+                const float4 f = *reinterpret_cast<const float4 *>(hp);
+                a4[0] = f.x;
+                a4[1] = f.y;
+                a4[2] = f.z;
+                a4[3] = f.w;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    a4[i] = hp[i];
+            }
+            const double xv = (double)xb[s];
+            const double gv = HASB ? (double)gb[s] : 1.0;
+            const int nx = min(rel + 16 + s, (int)d.L - 1);
+            xb[s] = xp[nx * es];
+            if constexpr (HASB)
+                gb[s] = gp[nx * es];
             double p = 0.0;
 #pragma unroll
             for (int i = 3; i >= 0; --i)
-                p = __builtin_fma(quad_coef<AV>(r.a, i, q, N), w[i], p);
+                p = __builtin_fma((FULL || 4 * q + i < N) ? -(double)a4[i] : 0.0, w[i], p);
             double tot = p + quad_dpp<kQuadXor1>(p);
             tot = tot + quad_dpp<kQuadXor2>(tot);
-            const double y = HASB ? __builtin_fma((double)r.g, (double)r.s, tot)
-                                  : (double)r.s + tot;
+            const double y = HASB ? __builtin_fma(gv, xv, tot) : xv + tot;
             const double prev = quad_dpp<kQuadFromPrev>(w[3]);
             w[3] = w[2];
             w[2] = w[1];
             w[1] = w[0];
             w[0] = q == 0 ? y : prev;
         });
+    };
+    for (int kb = 0; kb <= nblk; ++kb) {
+        if (kb > 0)
+            qhalf(H1{}, 16 * (kb - 1));
+        __syncthreads();
+        if (kb < nblk)
+            qhalf(H0{}, 16 * kb);
+        __syncthreads();
     }
-    // w[i] = y[t_end - 1 - (4q + i)] = s_c[4q + i]
-    double *o = summ + (b * d.C + c) * ((int64_t)N * N + N) + (int64_t)N * N;
+    if (act) {
+        double *o = summ + (b * d.C + c) * ((int64_t)N * N + N) + (int64_t)N * N;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (4 * q + i < N)
-            o[4 * q + i] = w[i];
+        for (int i = 0; i < 4; ++i)
+            if (4 * q + i < N)
+                o[4 * q + i] = w[i];
+    }
 }
 
 // Particular part of the adjoint map of chunk c (zero state at its top, the
@@ -704,12 +789,10 @@ __device__ __forceinline__ void bwd_part_quad(const Dims &d, const io_t *__restr
 
 // Workgroups of kRowGroupThreads threads cover kRowGroupChunks consecutive
 // items (b, chunk): waves 0-3 hold one 16-lane row per item, wave 4 the
-// items' particular solves (a quad each; with an FIR part, one lane each).
-// The rows and the particular solves read the same coefficient rows; keeping
-// them in one workgroup, advancing through the chunk together, makes the
-// second read of each row a cache hit instead of a second pass over HBM.
-constexpr int kRowGroupChunks = 16;
-constexpr int kRowGroupThreads = 16 * kRowGroupChunks + 64;
+// items' particular solves (a quad each, fed through LDS in the forward; with
+// an FIR part, one lane each).  In the adjoint the quads load the coefficient
+// rows themselves (a last chunk cut short needs clamped rows), and sharing
+// the workgroup with the rows keeps part of that second read in cache.
 
 template <bool FIR, bool AV, bool FULL, typename io_t>
 __global__ void __launch_bounds__(kRowGroupThreads, 5)
@@ -720,25 +803,32 @@ k_fwd_summary_rows(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ 
     const int64_t n = d.B * ncs;
     const int64_t first = (int64_t)blockIdx.x * kRowGroupChunks;
     const int t = threadIdx.x;
+    if constexpr (!FIR) {
+        __shared__ io_t hand[2][kHandSteps][16][16];
+        // this lane's item: its row's, or its quad's
+        const int k = t >= 16 * kRowGroupChunks ? (t - 16 * kRowGroupChunks) >> 2 : t >> 4;
+        const bool act = first + k < n;
+        int64_t b = 0, cc = 0;
+        int r;
+        if (act)
+            decode_lanes(d, first + k, ncs, 1, b, cc, r);
+        if (d.has_b)
+            fwd_rows_group<FULL, true>(d, x, bc, ac, summ, b, cc, act, hand);
+        else
+            fwd_rows_group<FULL, false>(d, x, bc, ac, summ, b, cc, act, hand);
+        return;
+    }
+    // with an FIR part: one lane per chunk for the particular solve, rows
+    // and particular lanes each reading the coefficient rows
     int64_t b, cc;
     int r;
     if (t >= 16 * kRowGroupChunks) {
         const int u = t - 16 * kRowGroupChunks;
-        if constexpr (FIR) {
-            if (u >= kRowGroupChunks || first + u >= n)
-                return;
-            decode_lanes(d, first + u, ncs, 1, b, cc, r);
-            fwd_summary_item<16, 1, true, FIR, true, AV>(d, x, xi, bc, ac, d.N, 1, summ, nullptr,
-                                                         b, cc, 0);
-        } else {
-            if (first + (u >> 2) >= n)  // whole quads only
-                return;
-            decode_lanes(d, first + (u >> 2), ncs, 1, b, cc, r);
-            if (d.has_b)
-                fwd_part_quad<AV, true>(d, x, bc, ac, summ, b, cc, u & 3);
-            else
-                fwd_part_quad<AV, false>(d, x, bc, ac, summ, b, cc, u & 3);
-        }
+        if (u >= kRowGroupChunks || first + u >= n)
+            return;
+        decode_lanes(d, first + u, ncs, 1, b, cc, r);
+        fwd_summary_item<16, 1, true, FIR, true, AV>(d, x, xi, bc, ac, d.N, 1, summ, nullptr, b,
+                                                     cc, 0);
         return;
     }
     if (first + (t >> 4) >= n)  // whole rows only
