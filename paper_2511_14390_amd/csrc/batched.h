@@ -263,13 +263,16 @@ kb_coef_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
             r[jj] = v * yv;
         }
         float *o = ga + sd.a_off + t * N + 4 * q;
+        // written once, not read again here: stream past the caches
         if (vec) {
-            *reinterpret_cast<float4 *>(o) = make_float4(r[0], r[1], r[2], r[3]);
+            using f4 = float __attribute__((ext_vector_type(4)));
+            const f4 v4 = {r[0], r[1], r[2], r[3]};
+            __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(o));
         } else {
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
                 if (4 * q + jj < N)
-                    o[jj] = r[jj];
+                    __builtin_nontemporal_store(r[jj], o + jj);
         }
     }
 }

@@ -66,13 +66,17 @@ k_tv_coef_grads(Dims d, const float *__restrict__ ybar, const float *__restrict_
         for (int jj = 0; jj < 4; ++jj)
             rr[jj] = (4 * q + jj < K) ? v * w[u - jj + 3] : 0.f;
         float *o = out + e * K + 4 * q;
+        // the gradient rows are written once and not read again here:
+        // non-temporal stores stream them past the caches
         if (vec) {
-            *reinterpret_cast<float4 *>(o) = make_float4(rr[0], rr[1], rr[2], rr[3]);
+            using f4 = float __attribute__((ext_vector_type(4)));
+            const f4 v4 = {rr[0], rr[1], rr[2], rr[3]};
+            __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(o));
         } else {
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
                 if (4 * q + jj < K)
-                    o[jj] = rr[jj];
+                    __builtin_nontemporal_store(rr[jj], o + jj);
         }
     }
 }
