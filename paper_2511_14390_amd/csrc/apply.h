@@ -392,6 +392,244 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
 
 // ---------------------------------------------------------------- drivers
 
+// ---------------------------------------------------------------- quad applies
+//
+// Per-sample coefficients of order 9..16 without an FIR part: each
+// (channel, chunk) chain runs on a lane quad, lane q owning taps
+// 4q+1 .. 4q+4 (the layout of the summaries' particular solves), with the
+// history window and the butterfly sum of the forward, and the shifted
+// adjoint state of the transposed backward.  Per lane a step costs four FMAs
+// and conversions instead of sixteen, and four times as many lanes carry the
+// chains: a wave on its own issues an FP64 instruction only every ~13
+// cycles, so the one-lane-per-chain applies were bound by that issue rate.
+// FP64 state; CLAMP: the chunk runs past T (rows clamped, nothing stored
+// past T).
+
+constexpr int kQuadApplyPrefetch = 16;
+
+template <bool AV, bool HASB, bool CLAMP, typename io_t>
+__device__ __forceinline__ void fwd_apply_quad(const Dims &d, const io_t *__restrict__ x,
+                                               const io_t *__restrict__ bc,
+                                               const io_t *__restrict__ ac,
+                                               const io_t *__restrict__ yi,
+                                               const double *__restrict__ hin,
+                                               io_t *__restrict__ y, int64_t b, int64_t c, int q)
+{
+    constexpr int P = kQuadApplyPrefetch;
+    const int N = d.N;
+    const int64_t t0 = c * d.L;
+    const int64_t e0 = sig_at(d, b, t0);
+    const int64_t es = d.layout == FILT_LAYOUT_TB ? d.B : 1;
+    const int64_t as = es * N;
+    const int last = CLAMP ? (int)min<int64_t>(d.T - 1 - t0, d.L - 1) : (int)d.L - 1;
+    const io_t *xp = x + e0;
+    const io_t *ap = ac + e0 * N;
+    const io_t *gp = HASB ? bc + e0 : xp;  // order-0 FIR part: one tap per row
+    io_t *yp = y + e0;
+    double w[4];  // w[i] = y[t - 4q - 1 - i], from the entering state
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = 4 * q + i;
+        double v = 0.0;
+        if (k < N) {
+            if (c == 0)
+                v = yi != nullptr ? (double)yi[b * N + k] : 0.0;
+            else
+                v = hin[(b * d.C + c) * N + k];
+        }
+        w[i] = v;
+    }
+    auto fetch = [&](int rel, QuadRaw<io_t> &r) {
+        const int rc = CLAMP ? min(rel, last) : rel;
+        quad_taps<AV>(ap + rc * as, q, N, r.a);
+        r.s = xp[rc * es];
+        if constexpr (HASB)
+            r.g = gp[rc * es];
+    };
+    QuadRaw<io_t> buf[P];
+    static_for<P>([&](auto I) { fetch(decltype(I)::value, buf[decltype(I)::value]); });
+    for (int rel = 0; rel < d.L; rel += P) {
+        static_for<P>([&](auto I) {
+            constexpr int s = decltype(I)::value;
+            const QuadRaw<io_t> r = buf[s];
+            fetch(min(rel + P + s, (int)d.L - 1), buf[s]);
+            double p = 0.0;
+#pragma unroll
+            for (int i = 3; i >= 0; --i)
+                p = __builtin_fma(quad_coef<AV>(r.a, i, q, N), w[i], p);
+            double tot = p + quad_dpp<kQuadXor1>(p);
+            tot = tot + quad_dpp<kQuadXor2>(tot);
+            const double v = HASB ? __builtin_fma((double)r.g, (double)r.s, tot)
+                                  : (double)r.s + tot;
+            if (q == 0 && (!CLAMP || rel + s <= last))
+                yp[(rel + s) * es] = (io_t)v;
+            const double prev = quad_dpp<kQuadFromPrev>(w[3]);
+            w[3] = w[2];
+            w[2] = w[1];
+            w[1] = w[0];
+            w[0] = q == 0 ? v : prev;
+        });
+    }
+}
+
+template <bool AV, bool HASB, typename io_t>
+__global__ void __launch_bounds__(kThreads)
+k_fwd_apply_quad(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ bc,
+                 const io_t *__restrict__ ac, const io_t *__restrict__ yi,
+                 const double *__restrict__ hin, io_t *__restrict__ y)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((idx >> 2) >= d.B * d.C)  // whole quads
+        return;
+    int64_t b, c, jj;
+    decode(d, idx >> 2, d.C, b, c, jj);
+    if ((c + 1) * d.L > d.T)
+        fwd_apply_quad<AV, HASB, true>(d, x, bc, ac, yi, hin, y, b, c, (int)(idx & 3));
+    else
+        fwd_apply_quad<AV, HASB, false>(d, x, bc, ac, yi, hin, y, b, c, (int)(idx & 3));
+}
+
+// Adjoint of chunk c from the entering state gin (transposed form, as in
+// bwd_apply_item without an FIR part): writes ybar to ybo and gx = b_0 ybar
+// to gx (either may be null; they may be the same buffer without b), and
+// gyi from chunk 0.
+template <bool AV, bool HASB, bool CLAMP, typename io_t>
+__device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__restrict__ gy,
+                                               const io_t *__restrict__ bc,
+                                               const io_t *__restrict__ ac,
+                                               const double *__restrict__ gin, io_t *gx,
+                                               io_t *__restrict__ gyi, io_t *ybo, int64_t b,
+                                               int64_t c, int q)
+{
+    constexpr int P = kQuadApplyPrefetch;
+    const int N = d.N;
+    const int64_t t0 = c * d.L;
+    const int64_t e0 = sig_at(d, b, t0);
+    const int64_t es = d.layout == FILT_LAYOUT_TB ? d.B : 1;
+    const int64_t as = es * N;
+    const int last = CLAMP ? (int)min<int64_t>(d.T - 1 - t0, d.L - 1) : (int)d.L - 1;
+    const io_t *g0 = gy + e0;
+    const io_t *ap = ac + e0 * N;
+    const io_t *gp = HASB ? bc + e0 : g0;
+    double st[4];  // st[i] = s_{4q+1+i}
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = 4 * q + i;
+        st[i] = (c + 1 < d.C && k < N) ? gin[(b * d.C + c) * N + k] : 0.0;
+    }
+    auto fetch = [&](int rel, QuadRaw<io_t> &r) {
+        const int rc = CLAMP ? min(rel, last) : rel;
+        quad_taps<AV>(ap + rc * as, q, N, r.a);
+        const io_t g = g0[rc * es];
+        r.s = (!CLAMP || rel <= last) ? g : io_t(0);
+        if constexpr (HASB)
+            r.g = gp[rc * es];
+    };
+    QuadRaw<io_t> buf[P];
+    static_for<P>([&](auto I) {
+        fetch((int)d.L - P + decltype(I)::value, buf[decltype(I)::value]);
+    });
+    for (int rel = (int)d.L - P; rel >= 0; rel -= P) {
+        static_for<P>([&](auto I) {
+            constexpr int s = P - 1 - decltype(I)::value;
+            const QuadRaw<io_t> r = buf[s];
+            fetch(max(rel - P + s, 0), buf[s]);
+            const double yb = (double)r.s + quad_dpp<kQuadLane0>(st[0]);
+            if (q == 0 && (!CLAMP || rel + s <= last)) {
+                const int64_t o = (int64_t)(rel + s) * es;
+                if (ybo != nullptr)
+                    ybo[e0 + o] = (io_t)yb;
+                if (gx != nullptr && (HASB || gx != ybo))
+                    gx[e0 + o] = (io_t)(HASB ? (double)r.g * yb : yb);
+            }
+            const double nx = quad_dpp<kQuadFromNext>(st[0]);
+            st[0] = __builtin_fma(quad_coef<AV>(r.a, 0, q, N), yb, st[1]);
+            st[1] = __builtin_fma(quad_coef<AV>(r.a, 1, q, N), yb, st[2]);
+            st[2] = __builtin_fma(quad_coef<AV>(r.a, 2, q, N), yb, st[3]);
+            st[3] = __builtin_fma(quad_coef<AV>(r.a, 3, q, N), yb, q == 3 ? 0.0 : nx);
+        });
+    }
+    if (c == 0 && gyi != nullptr) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (4 * q + i < N)
+                gyi[b * N + 4 * q + i] = (io_t)st[i];
+    }
+}
+
+template <bool AV, bool HASB, typename io_t>
+__global__ void __launch_bounds__(kThreads)
+k_bwd_apply_quad(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
+                 const io_t *__restrict__ ac, const double *__restrict__ gin, io_t *gx,
+                 io_t *__restrict__ gyi, io_t *ybo)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((idx >> 2) >= d.B * d.C)
+        return;
+    int64_t b, c, jj;
+    decode(d, idx >> 2, d.C, b, c, jj);
+    if ((c + 1) * d.L > d.T)
+        bwd_apply_quad<AV, HASB, true>(d, gy, bc, ac, gin, gx, gyi, ybo, b, c, (int)(idx & 3));
+    else
+        bwd_apply_quad<AV, HASB, false>(d, gy, bc, ac, gin, gx, gyi, ybo, b, c, (int)(idx & 3));
+}
+
+// Quad applies take per-sample problems of the order-16 bucket without an
+// FIR part and with FP64 state.
+template <int W, typename io_t, typename acc_t>
+constexpr bool kQuadApply = W == 16 && sizeof(acc_t) == 8;
+
+inline bool quad_apply_eligible(const Dims &d) { return d.tv && d.M == 0 && d.N > 0; }
+
+template <typename io_t>
+filt_status fwd_apply_quad_run(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
+                               const io_t *yi, const double *states, io_t *y, hipStream_t st)
+{
+    const int64_t lanes = d.B * d.C * 4;
+    const dim3 grid((unsigned)((lanes + kThreads - 1) / kThreads));
+#define FILT_QF(AVV, HB)                                                                           \
+    FILT_LAUNCH("fwd_apply", (k_fwd_apply_quad<AVV, HB, io_t>), grid, dim3(kThreads), 0, st, d,   \
+                x, bc, ac, yi, states, y)
+    if (d.a_vec) {
+        if (d.has_b)
+            FILT_QF(true, true);
+        else
+            FILT_QF(true, false);
+    } else {
+        if (d.has_b)
+            FILT_QF(false, true);
+        else
+            FILT_QF(false, false);
+    }
+#undef FILT_QF
+    return check_launch("forward apply");
+}
+
+template <typename io_t>
+filt_status bwd_apply_quad_run(const Dims &d, const io_t *gy, const io_t *bc, const io_t *ac,
+                               const double *states, io_t *gx, io_t *gyi, io_t *ybo,
+                               hipStream_t st)
+{
+    const int64_t lanes = d.B * d.C * 4;
+    const dim3 grid((unsigned)((lanes + kThreads - 1) / kThreads));
+#define FILT_QB(AVV, HB)                                                                           \
+    FILT_LAUNCH("bwd_apply", (k_bwd_apply_quad<AVV, HB, io_t>), grid, dim3(kThreads), 0, st, d,   \
+                gy, bc, ac, states, gx, gyi, ybo)
+    if (d.a_vec) {
+        if (d.has_b)
+            FILT_QB(true, true);
+        else
+            FILT_QB(true, false);
+    } else {
+        if (d.has_b)
+            FILT_QB(false, true);
+        else
+            FILT_QB(false, false);
+    }
+#undef FILT_QB
+    return check_launch("backward apply");
+}
+
 template <int W, bool FIR, typename io_t, typename acc_t>
 filt_status fwd_apply(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
                       const io_t *xi, const io_t *yi, const double *states, io_t *y,
@@ -443,6 +681,10 @@ filt_status forward_w(const Dims &d, const io_t *x, const io_t *bc, const io_t *
     if constexpr (sizeof(io_t) == 4 && sizeof(acc_t) == 8 && W <= 16) {
         if (stream_eligible(d))
             return stream_forward_run<W>(d, x, ac, yi, states, y, st);
+    }
+    if constexpr (kQuadApply<W, io_t, acc_t>) {
+        if (quad_apply_eligible(d))
+            return fwd_apply_quad_run<io_t>(d, x, bc, ac, yi, states, y, st);
     }
     if (d.M > 0)
         return fwd_apply<W, true, io_t, acc_t>(d, x, bc, ac, xi, yi, states, y, st);
@@ -526,10 +768,25 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
             return tv_coef_grads_run(d, yb, x, xi, y, yi, ga, nullptr, st);
         }
     }
-    // Order-16 per-sample problems: the fused adjoint with the coefficient
-    // products needs more registers than a wavefront has and spills to
-    // AGPRs on every step, so the apply writes the adjoint (FP32) and a
-    // fully parallel pass forms ga and gb from it.
+    // Order-16 per-sample problems without an FIR part: quad adjoint writing
+    // ybar (into gx itself without b, where gx = ybar), then the coefficient
+    // gradients from it in a fully parallel pass.
+    if constexpr (kQuadApply<W, io_t, acc_t>) {
+        if (quad_apply_eligible(d) &&
+            ((ga == nullptr && gb == nullptr) || (sizeof(io_t) == 4 && tv_coef_grads_fits(d)))) {
+            const bool coef = ga != nullptr || gb != nullptr;
+            io_t *yb = !coef ? nullptr : (gx != nullptr && !d.has_b) ? gx : (io_t *)(ws + w.yb);
+            filt_status s = bwd_apply_quad_run<io_t>(d, gy, bc, ac, states, gx, gyi, yb, st);
+            if (s != FILT_OK || !coef)
+                return s;
+            if constexpr (sizeof(io_t) == 4)
+                return tv_coef_grads_run(d, yb, x, xi, y, yi, ga, gb, st);
+        }
+    }
+    // Other order-16 per-sample problems: the fused adjoint with the
+    // coefficient products needs more registers than a wavefront has and
+    // spills to AGPRs on every step, so the apply writes the adjoint (FP32)
+    // and a fully parallel pass forms ga and gb from it.
     const bool split = d.tv && W >= 16 && sizeof(io_t) == 4 && (ga != nullptr || gb != nullptr) &&
                        tv_coef_grads_fits(d);
     io_t *ybo = split ? (io_t *)(ws + w.yb) : nullptr;

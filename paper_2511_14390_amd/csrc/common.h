@@ -211,6 +211,69 @@ __device__ __forceinline__ void ld_row_lti(const Dims &d, const io_t *bc, const 
     cvt_row<W, FIR>(ra, rb, ca, cb);
 }
 
+// f(std::integral_constant<int, i>) for i = 0..n-1, in order.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int n, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_seq(f, std::make_integer_sequence<int, n>{});
+}
+
+// FP64 value moved within lane quads (two 32-bit DPP moves, quad_perm
+// control); used by the recursions that split one chain's taps over a quad.
+template <int CTRL>
+__device__ __forceinline__ double quad_dpp(double v)
+{
+    // every source lane of a quad_perm is live, so bound_ctrl only spares the
+    // move that would preload an "old" value
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, true);
+}
+constexpr int kQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kQuadFromPrev = 0x90;  // quad_perm [0,0,1,2]: lane q reads lane q - 1
+constexpr int kQuadFromNext = 0xF9;  // quad_perm [1,2,3,3]: lane q reads lane q + 1
+constexpr int kQuadLane0 = 0x00;     // quad_perm [0,0,0,0]
+
+// One step's loads of a quad lane: its four taps of the coefficient row and
+// a signal sample with its gain.
+template <typename io_t>
+struct QuadRaw {
+    io_t a[4];  // taps 4q .. 4q + 3 of the coefficient row (a_{4q+1} .. a_{4q+4})
+    io_t s, g;  // signal sample and its gain (b_0, or 1 without b)
+};
+
+// Taps 4q .. 4q + 3 of one coefficient row (N == 16 and 16-byte aligned rows
+// with AV; else element loads, clamped into the row and zeroed on use).
+template <bool AV, typename io_t>
+__device__ __forceinline__ void quad_taps(const io_t *row, int q, int N, io_t (&v)[4])
+{
+    if constexpr (AV && sizeof(io_t) == 4) {
+        const float4 f = *reinterpret_cast<const float4 *>(row + 4 * q);
+        v[0] = f.x;
+        v[1] = f.y;
+        v[2] = f.z;
+        v[3] = f.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            v[i] = row[min(4 * q + i, N - 1)];
+    }
+}
+
+// -a_{4q+1+i} as a double (zero for taps past N).
+template <bool AV, typename io_t>
+__device__ __forceinline__ double quad_coef(const io_t (&v)[4], int i, int q, int N)
+{
+    if constexpr (AV && sizeof(io_t) == 4)
+        return -(double)v[i];
+    else
+        return 4 * q + i < N ? -(double)v[i] : 0.0;
+}
+
 // Prefetch depth (time steps) of the summary and apply loops.  The apply
 // kernels run one long sequential chain per (channel, chunk) and are
 // latency-bound, so they keep more steps in flight.

@@ -358,18 +358,6 @@ k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
 // write of EXEC), hence the s_nop 4 that opens each step.  All 16 lanes of a
 // row stay active for the whole chunk (lanes j >= N carry zero coefficients).
 
-// f(std::integral_constant<int, i>) for i = 0..n-1, in order.
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)
-{
-    (f(std::integral_constant<int, I>{}), ...);
-}
-template <int n, typename F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    static_for_seq(f, std::make_integer_sequence<int, n>{});
-}
-
 #define FILT_ROW_FMAC(lane, acc, src, mul)                                                         \
     "v_fmac_f64_dpp %" #acc ", %" #src ", %" #mul " row_newbcast:" #lane                          \
     " row_mask:0xf bank_mask:0xf\n"
@@ -549,18 +537,6 @@ __device__ __forceinline__ void bwd_row_item(const Dims &d, const io_t *__restri
 // Adjoint (transposed form): lane q keeps st[i] = s_{4q+1+i}; ybar = g + s_1
 // comes from lane 0 and s_k <- s_{k+1} - a_k ybar shifts within the lane,
 // s_{4q+5} arriving from lane q + 1 (zero past the last lane).
-template <int CTRL>
-__device__ __forceinline__ double quad_dpp(double v)
-{
-    // every source lane of a quad_perm is live, so bound_ctrl only spares the
-    // move that would preload an "old" value
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, true);
-}
-constexpr int kQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
-constexpr int kQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
-constexpr int kQuadFromPrev = 0x90;  // quad_perm [0,0,1,2]: lane q reads lane q - 1
-constexpr int kQuadFromNext = 0xF9;  // quad_perm [1,2,3,3]: lane q reads lane q + 1
-constexpr int kQuadLane0 = 0x00;     // quad_perm [0,0,0,0]
 
 // Workgroups of the row summaries: kRowGroupChunks items, waves 0-3 their
 // rows, wave 4 their particular solves.
@@ -568,40 +544,6 @@ constexpr int kRowGroupChunks = 16;
 constexpr int kRowGroupThreads = 16 * kRowGroupChunks + 64;
 
 constexpr int kQuadPrefetch = 4;  // steps in flight (chunk lengths are multiples of 32)
-
-template <typename io_t>
-struct QuadRaw {
-    io_t a[4];  // taps 4q .. 4q + 3 of the coefficient row (a_{4q+1} .. a_{4q+4})
-    io_t s, g;  // signal sample and its gain (b_0, or 1 without b)
-};
-
-// Taps 4q .. 4q + 3 of one coefficient row (N == 16 and 16-byte aligned rows
-// with AV; else element loads, clamped into the row and zeroed on use).
-template <bool AV, typename io_t>
-__device__ __forceinline__ void quad_taps(const io_t *row, int q, int N, io_t (&v)[4])
-{
-    if constexpr (AV && sizeof(io_t) == 4) {
-        const float4 f = *reinterpret_cast<const float4 *>(row + 4 * q);
-        v[0] = f.x;
-        v[1] = f.y;
-        v[2] = f.z;
-        v[3] = f.w;
-    } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            v[i] = row[min(4 * q + i, N - 1)];
-    }
-}
-
-// -a_{4q+1+i} as a double (zero for taps past N).
-template <bool AV, typename io_t>
-__device__ __forceinline__ double quad_coef(const io_t (&v)[4], int i, int q, int N)
-{
-    if constexpr (AV && sizeof(io_t) == 4)
-        return -(double)v[i];
-    else
-        return 4 * q + i < N ? -(double)v[i] : 0.0;
-}
 
 // Forward summaries of one workgroup's items, reading the coefficient rows
 // once.  The row lanes park every raw coefficient they consume in LDS (hand:
