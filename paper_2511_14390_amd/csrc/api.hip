@@ -88,8 +88,14 @@ int64_t auto_chunk(const filt_problem *p)
     int64_t L = (T + per - 1) / std::max<int64_t>(per, 1);
     if (p->time_varying) {
         // keep the 8 (N^2 + N) / L transition bytes per sample well below
-        // the 4 (N + M + 1) bytes of coefficients
-        L = std::max<int64_t>(L, 12 * (int64_t)p->N);
+        // the 4 (N + M + 1) bytes of coefficients.  The order-16 bucket in
+        // [T, B] takes longer chunks still (its applies run four lanes per
+        // chain and the carry is the longer part); in [B, T] a wavefront's
+        // chains sit L rows apart, and 16 N = 256 rows of 64 bytes is a
+        // power-of-two stride that piles their loads onto the same memory
+        // channels
+        const bool longer = p->N > 8 && p->layout == FILT_LAYOUT_TB;
+        L = std::max<int64_t>(L, (longer ? 16 : 12) * (int64_t)p->N);
     } else {
         L = std::max<int64_t>(L, 128);
     }

@@ -737,7 +737,7 @@ __device__ __forceinline__ void bwd_part_quad(const Dims &d, const io_t *__restr
 // the workgroup with the rows keeps part of that second read in cache.
 
 template <bool FIR, bool AV, bool FULL, typename io_t>
-__global__ void __launch_bounds__(kRowGroupThreads, 5)
+__global__ void __launch_bounds__(kRowGroupThreads, FIR ? 1 : 5)
 k_fwd_summary_rows(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
                    const io_t *__restrict__ bc, const io_t *__restrict__ ac, int64_t ncs,
                    double *__restrict__ summ)
