@@ -152,6 +152,56 @@ kb_bwd_apply(const SegDesc *__restrict__ segs, const Item *__restrict__ items, i
     }
 }
 
+// Order-16 bucket applies on lane quads (apply.h): four lanes per item.
+// The backward writes ybar into gx (gx = ybar without b) and gyi from chunk 0.
+template <bool AV>
+__global__ void __launch_bounds__(kThreads)
+kb_fwd_apply_quad(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+                  const float *__restrict__ x, const float *__restrict__ a,
+                  const float *__restrict__ yi, const double *__restrict__ ws,
+                  float *__restrict__ y)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((idx >> 2) >= n)  // whole quads
+        return;
+    const Item it = items[idx >> 2];
+    const SegDesc sd = segs[it.seg];
+    const Dims d = seg_dims(sd);
+    const float *yis = yi != nullptr ? yi + sd.ic_off : nullptr;
+    if (((int64_t)it.chunk + 1) * d.L > d.T)
+        fwd_apply_quad<AV, false, true>(d, x + sd.x_off, (const float *)nullptr, a + sd.a_off,
+                                        yis, ws + sd.states_off, y + sd.x_off, 0, it.chunk,
+                                        (int)(idx & 3));
+    else
+        fwd_apply_quad<AV, false, false>(d, x + sd.x_off, (const float *)nullptr, a + sd.a_off,
+                                         yis, ws + sd.states_off, y + sd.x_off, 0, it.chunk,
+                                         (int)(idx & 3));
+}
+
+template <bool AV>
+__global__ void __launch_bounds__(kThreads)
+kb_bwd_apply_quad(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+                  const float *__restrict__ gy, const float *__restrict__ a,
+                  const double *__restrict__ ws, float *gx, float *__restrict__ gyi)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((idx >> 2) >= n)
+        return;
+    const Item it = items[idx >> 2];
+    const SegDesc sd = segs[it.seg];
+    const Dims d = seg_dims(sd);
+    float *gxs = gx + sd.x_off;
+    float *gyis = gyi != nullptr ? gyi + sd.ic_off : nullptr;
+    if (((int64_t)it.chunk + 1) * d.L > d.T)
+        bwd_apply_quad<AV, false, true>(d, gy + sd.x_off, (const float *)nullptr, a + sd.a_off,
+                                        ws + sd.states_off, gxs, gyis, gxs, 0, it.chunk,
+                                        (int)(idx & 3));
+    else
+        bwd_apply_quad<AV, false, false>(d, gy + sd.x_off, (const float *)nullptr, a + sd.a_off,
+                                         ws + sd.states_off, gxs, gyis, gxs, 0, it.chunk,
+                                         (int)(idx & 3));
+}
+
 // Staged applies (stream.h) over the items (seg, chunk) of one bucket, one
 // wavefront per 64 items; Lc is the bucket's chunk length.
 template <int W, bool VEC>
@@ -419,6 +469,16 @@ filt_status batched_fwd_apply(const BucketArgs &b, const float *x, const float *
 {
     if (b.app_n == 0)
         return FILT_OK;
+    if constexpr (W == 16) {
+        const dim3 grid((unsigned)((b.app_n * 4 + kThreads - 1) / kThreads));
+        if (b.av)
+            FILT_LAUNCH("batched_fwd_apply", kb_fwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
+                        b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
+        else
+            FILT_LAUNCH("batched_fwd_apply", kb_fwd_apply_quad<false>, grid, dim3(kThreads), 0,
+                        st, b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
+        return check_launch("batched forward apply");
+    }
     unsigned g, t;
     persistent_grid(b.app_n, g, t);
     if (b.av)
@@ -497,15 +557,29 @@ filt_status batched_stream_bwd(const BucketArgs &b, int64_t Lc, const float *gy,
     return check_launch("batched staged backward apply");
 }
 
-// Order-16 bucket backward: the direct apply writes only gx (= ybar) and the
-// per-item pass forms ga (the fused products overflow the registers).
+// Order-16 bucket backward: the apply (quads) writes only gx (= ybar) and
+// the per-item pass forms ga.
 template <int W>
 filt_status batched_bwd_split(const BucketArgs &b, int64_t Lc, const float *gy, const float *y,
                               const float *a, const float *yi, const double *ws, float *gx,
                               float *ga, float *gyi, hipStream_t st)
 {
-    filt_status s = batched_bwd_apply<W>(b, gy, y, a, yi, ws, gx, nullptr, gyi, st);
-    if (s != FILT_OK || ga == nullptr || b.app_n == 0)
+    filt_status s = FILT_OK;
+    if (b.app_n == 0)
+        return s;
+    if constexpr (W == 16) {
+        const dim3 grid((unsigned)((b.app_n * 4 + kThreads - 1) / kThreads));
+        if (b.av)
+            FILT_LAUNCH("batched_bwd_apply", kb_bwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
+                        b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);
+        else
+            FILT_LAUNCH("batched_bwd_apply", kb_bwd_apply_quad<false>, grid, dim3(kThreads), 0,
+                        st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);
+        s = check_launch("batched backward apply");
+    } else {
+        s = batched_bwd_apply<W>(b, gy, y, a, yi, ws, gx, nullptr, gyi, st);
+    }
+    if (s != FILT_OK || ga == nullptr)
         return s;
     FILT_LAUNCH("batched_coef_grads", kb_coef_grads<W>, dim3((unsigned)b.app_n), dim3(256), 0, st,
                 b.segs, b.app_items, Lc, gx, y, yi, ga);

@@ -8,12 +8,14 @@
 // companion-form transitions have entries far above 1 when poles cluster near
 // the unit circle, and an FP32 Phi would lose the digits the carry needs.
 //
-// Per-sample coefficients: every chunk needs N + 1 solves.  Each lane runs S
-// of them side by side, so one coefficient row fetched (and converted) per
-// step feeds S recursions; nl = ceil((N + 1) / S) adjacent lanes cover one
-// chunk.  Rows are fetched two steps ahead of their use.  Time-invariant
-// coefficients: one particular solve per chunk, and the N homogeneous solves
-// once per channel (Phi is the same for every chunk).
+// Per-sample coefficients: every chunk needs N + 1 solves.  Orders up to 8:
+// each lane runs S of them side by side, so one coefficient row fetched (and
+// converted) per step feeds S recursions; nl = ceil((N + 1) / S) adjacent
+// lanes cover one chunk, rows fetched a few steps ahead of their use.
+// Orders 9..16: one 16-lane DPP row per chunk for the N homogeneous solves
+// and a lane quad for the particular one (the row solves below).
+// Time-invariant coefficients: one particular solve per chunk, and the N
+// homogeneous solves once per channel (Phi is the same for every chunk).
 //
 // Register histories live in W registers addressed modulo W; the time loop
 // is unrolled by W so every index is a compile-time constant.
