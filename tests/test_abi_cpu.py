@@ -144,6 +144,30 @@ def test_auto_chunk_multiple_of_32(L):
         assert c >= 32 and c % 32 == 0
 
 
+def test_auto_chunk_order16_per_sample_by_layout(L):
+    # [T, B]: chunks of at least 16 N; [B, T]: 12 N (16 N = 256 rows of 64
+    # bytes would be a power-of-two stride between a wavefront's chains)
+    p = dict(B=64, T=48000, N=16, time_varying=1)
+    tb = L.filt_auto_chunk(ctypes.byref(_prob(layout=F.FILT_LAYOUT_TB, **p)))
+    bt = L.filt_auto_chunk(ctypes.byref(_prob(layout=F.FILT_LAYOUT_BT, **p)))
+    assert (tb, bt) == (256, 192)
+    # orders up to 8 keep 12 N in both layouts
+    p8 = dict(B=64, T=48000, N=8, time_varying=1)
+    assert L.filt_auto_chunk(ctypes.byref(_prob(layout=F.FILT_LAYOUT_TB, **p8))) == 96
+
+
+def test_profile_filter_is_host_only_and_bounds_the_name(L):
+    L.filt_profile_only.argtypes = [ctypes.c_char_p]
+    L.filt_profile_only.restype = ctypes.c_int
+    try:
+        assert L.filt_profile_only(b"fwd_summary") == F.FILT_OK
+        assert L.filt_profile_only(b"x" * 63) == F.FILT_OK
+        assert L.filt_profile_only(b"x" * 64) == F.FILT_EINVAL
+        assert b"63" in L.filt_last_error()
+    finally:
+        assert L.filt_profile_only(None) == F.FILT_OK
+
+
 def test_python_binding_refuses_cpu_tensors():
     import torch
 
