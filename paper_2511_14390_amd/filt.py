@@ -47,7 +47,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it first "
-                               "(python -c 'import __graft_entry__ as g; g.build()')")
+                               "(python -m paper_2511_14390_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         P, S, I64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64
         PP = ctypes.POINTER(FiltProblem)
