@@ -64,16 +64,54 @@ __device__ __forceinline__ void stage_records(const double *__restrict__ base, i
     constexpr int U = 8;
     const unsigned n = (unsigned)k * (unsigned)rec;
     const unsigned nt = blockDim.x;
+    if (stride == rec && off == 0) {
+        // whole records back to back: one linear run, in rounds of U * nt
+        // elements without per-element tests, then one guarded round
+        const double *src = base + r_lo * stride;
+        const unsigned full = n / (U * nt) * (U * nt);
+        for (unsigned b0 = 0; b0 < full; b0 += U * nt) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                v[u] = src[b0 + threadIdx.x + u * nt];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                lds[b0 + threadIdx.x + u * nt] = v[u];
+        }
+        if (full < n) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned e = full + threadIdx.x + u * nt;
+                if (e < n)
+                    v[u] = src[e];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned e = full + threadIdx.x + u * nt;
+                if (e < n)
+                    lds[e] = v[u];
+            }
+        }
+        return;
+    }
+    // (record, word) of element e kept up to date by additions: e advances
+    // by nt, i.e. by dq records and dr words with a carry
     const unsigned urec = (unsigned)rec;
+    const unsigned dq = nt / urec, dr = nt - dq * urec;
+    unsigned r = threadIdx.x / urec, w = threadIdx.x - (threadIdx.x / urec) * urec;
     for (unsigned e0 = threadIdx.x; e0 < n; e0 += U * nt) {
         double v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const unsigned e = e0 + u * nt;
-            if (e < n) {
-                const unsigned r = e / urec;
-                const unsigned w = e - r * urec;
+            if (e < n)
                 v[u] = base[(r_lo + r) * stride + off + w];
+            w += dr;
+            r += dq;
+            if (w >= urec) {
+                w -= urec;
+                ++r;
             }
         }
 #pragma unroll
