@@ -85,7 +85,10 @@ def kernel_bytes(p, name):
     W = 1
     while W < max(p.N, p.M + 1):
         W *= 2
-    split = W >= 16
+    # order-16 bucket: with an FIR part or per-sample gains b the adjoint pass
+    # leaves the coefficient products to a separate pass; without them it
+    # forms ga itself
+    split = W >= 16 and (p.M > 0 or p.b is not None)
     table = {
         # time-invariant [B, T] problems on the matrix cores: the tile kernels
         # move only signals (the per-channel matrices stay in L2)
@@ -102,8 +105,8 @@ def kernel_bytes(p, name):
         # per-sample coefficient gradients: read ybar and y, write the rows
         "coef_grads": 4 + 4 + coef,
         # backward: read gy, y (+ x for M > 0) and coefficients; write gx and
-        # the per-sample coefficient gradients (register bucket 16 and up
-        # leaves the products to coef_grads: read gy, the row, write gx)
+        # the per-sample coefficient gradients (split: read gy, the row, write
+        # gx, the products left to coef_grads)
         "bwd_apply": (4 + coef + 4 + fir) if (split and p.time_varying)
                      else (4 + 4 + fir + 4 + 2 * coef),
         # chunk summaries read their phase's inputs once

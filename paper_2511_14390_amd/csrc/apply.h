@@ -492,14 +492,21 @@ k_fwd_apply_quad(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ bc
 // Adjoint of chunk c from the entering state gin (transposed form, as in
 // bwd_apply_item without an FIR part): writes ybar to ybo and gx = b_0 ybar
 // to gx (either may be null; they may be the same buffer without b), and
-// gyi from chunk 0.
-template <bool AV, bool HASB, bool CLAMP, typename io_t>
+// gyi from chunk 0.  GA: also the per-sample gradient rows
+// ga_k[t] = -ybar[t] y[t-k] (Sec. 3.1 Eq. 8 per sample), lane q its taps
+// 4q+1 .. 4q+4 from a window wy[i] = y[t - 4q - 1 - i] that slides down one
+// sample per step (one new y value per lane and step; y before time 0 from
+// the initial conditions yi).
+template <bool AV, bool HASB, bool CLAMP, bool GA, typename io_t>
 __device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__restrict__ gy,
                                                const io_t *__restrict__ bc,
                                                const io_t *__restrict__ ac,
                                                const double *__restrict__ gin, io_t *gx,
-                                               io_t *__restrict__ gyi, io_t *ybo, int64_t b,
-                                               int64_t c, int q)
+                                               io_t *__restrict__ gyi, io_t *ybo,
+                                               const io_t *__restrict__ y,
+                                               const io_t *__restrict__ yi,
+                                               io_t *__restrict__ ga, int64_t b, int64_t c,
+                                               int q)
 {
     constexpr int P = kQuadApplyPrefetch;
     const int N = d.N;
@@ -517,6 +524,20 @@ __device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__rest
         const int k = 4 * q + i;
         st[i] = (c + 1 < d.C && k < N) ? gin[(b * d.C + c) * N + k] : 0.0;
     }
+    // y at chunk-relative time tt: clamped below T (such steps store nothing),
+    // initial conditions before time 0 (zero past N, where no tap reads them)
+    auto yat = [&](int tt) -> io_t {
+        if (t0 + tt >= 0)
+            return y[e0 + min((int64_t)tt, d.T - 1 - t0) * es];
+        const int64_t m = -(t0 + tt);  // y[-m] = yi[m - 1]
+        return (yi != nullptr && m <= N) ? yi[b * N + (m - 1)] : io_t(0);
+    };
+    io_t wy[4];  // wy[i] = y[t - 4q - 1 - i] for the step t about to run
+    if constexpr (GA) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            wy[i] = yat((int)d.L - 1 - 4 * q - 1 - i);
+    }
     auto fetch = [&](int rel, QuadRaw<io_t> &r) {
         const int rc = CLAMP ? min(rel, last) : rel;
         quad_taps<AV>(ap + rc * as, q, N, r.a);
@@ -524,6 +545,8 @@ __device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__rest
         r.s = (!CLAMP || rel <= last) ? g : io_t(0);
         if constexpr (HASB)
             r.g = gp[rc * es];
+        if constexpr (GA)
+            r.y = yat(rel - 4 * q - 5);  // enters the window after this step
     };
     QuadRaw<io_t> buf[P];
     static_for<P>([&](auto I) {
@@ -535,6 +558,36 @@ __device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__rest
             const QuadRaw<io_t> r = buf[s];
             fetch(max(rel - P + s, 0), buf[s]);
             const double yb = (double)r.s + quad_dpp<kQuadLane0>(st[0]);
+            if constexpr (GA) {
+                if (!CLAMP || rel + s <= last) {
+                    io_t gv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        gv[i] = (io_t)(-yb * (double)wy[i]);
+                    io_t *o = ga + (e0 + (int64_t)(rel + s) * es) * N + 4 * q;
+                    if constexpr (sizeof(io_t) == 4) {
+                        if (d.ga_vec) {
+                            using f4 = float __attribute__((ext_vector_type(4)));
+                            const f4 v4 = {gv[0], gv[1], gv[2], gv[3]};
+                            __builtin_nontemporal_store(v4, reinterpret_cast<f4 *>(o));
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (4 * q + i < N)
+                                    __builtin_nontemporal_store(gv[i], o + i);
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (4 * q + i < N)
+                                o[i] = gv[i];
+                    }
+                }
+                wy[0] = wy[1];
+                wy[1] = wy[2];
+                wy[2] = wy[3];
+                wy[3] = r.y;
+            }
             if (q == 0 && (!CLAMP || rel + s <= last)) {
                 const int64_t o = (int64_t)(rel + s) * es;
                 if (ybo != nullptr)
@@ -557,11 +610,12 @@ __device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__rest
     }
 }
 
-template <bool AV, bool HASB, typename io_t>
+template <bool AV, bool HASB, bool GA, typename io_t>
 __global__ void __launch_bounds__(kThreads)
 k_bwd_apply_quad(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
                  const io_t *__restrict__ ac, const double *__restrict__ gin, io_t *gx,
-                 io_t *__restrict__ gyi, io_t *ybo)
+                 io_t *__restrict__ gyi, io_t *ybo, const io_t *__restrict__ y,
+                 const io_t *__restrict__ yi, io_t *__restrict__ ga)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if ((idx >> 2) >= d.B * d.C)
@@ -569,9 +623,11 @@ k_bwd_apply_quad(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ b
     int64_t b, c, jj;
     decode(d, idx >> 2, d.C, b, c, jj);
     if ((c + 1) * d.L > d.T)
-        bwd_apply_quad<AV, HASB, true>(d, gy, bc, ac, gin, gx, gyi, ybo, b, c, (int)(idx & 3));
+        bwd_apply_quad<AV, HASB, true, GA>(d, gy, bc, ac, gin, gx, gyi, ybo, y, yi, ga, b, c,
+                                           (int)(idx & 3));
     else
-        bwd_apply_quad<AV, HASB, false>(d, gy, bc, ac, gin, gx, gyi, ybo, b, c, (int)(idx & 3));
+        bwd_apply_quad<AV, HASB, false, GA>(d, gy, bc, ac, gin, gx, gyi, ybo, y, yi, ga, b, c,
+                                            (int)(idx & 3));
 }
 
 // Quad applies take per-sample problems of the order-16 bucket without an
@@ -605,27 +661,36 @@ filt_status fwd_apply_quad_run(const Dims &d, const io_t *x, const io_t *bc, con
     return check_launch("forward apply");
 }
 
+// ga non-null: the gradient rows are formed in the same pass (needs y, yi).
 template <typename io_t>
 filt_status bwd_apply_quad_run(const Dims &d, const io_t *gy, const io_t *bc, const io_t *ac,
                                const double *states, io_t *gx, io_t *gyi, io_t *ybo,
-                               hipStream_t st)
+                               const io_t *y, const io_t *yi, io_t *ga, hipStream_t st)
 {
     const int64_t lanes = d.B * d.C * 4;
     const dim3 grid((unsigned)((lanes + kThreads - 1) / kThreads));
-#define FILT_QB(AVV, HB)                                                                           \
-    FILT_LAUNCH("bwd_apply", (k_bwd_apply_quad<AVV, HB, io_t>), grid, dim3(kThreads), 0, st, d,   \
-                gy, bc, ac, states, gx, gyi, ybo)
+#define FILT_QB(AVV, HB, GAV)                                                                      \
+    FILT_LAUNCH("bwd_apply", (k_bwd_apply_quad<AVV, HB, GAV, io_t>), grid, dim3(kThreads), 0, st, \
+                d, gy, bc, ac, states, gx, gyi, ybo, y, yi, ga)
+#define FILT_QB_G(AVV, HB)                                                                         \
+    do {                                                                                           \
+        if (ga != nullptr)                                                                         \
+            FILT_QB(AVV, HB, true);                                                                \
+        else                                                                                       \
+            FILT_QB(AVV, HB, false);                                                               \
+    } while (0)
     if (d.a_vec) {
         if (d.has_b)
-            FILT_QB(true, true);
+            FILT_QB_G(true, true);
         else
-            FILT_QB(true, false);
+            FILT_QB_G(true, false);
     } else {
         if (d.has_b)
-            FILT_QB(false, true);
+            FILT_QB_G(false, true);
         else
-            FILT_QB(false, false);
+            FILT_QB_G(false, false);
     }
+#undef FILT_QB_G
 #undef FILT_QB
     return check_launch("backward apply");
 }
@@ -772,12 +837,16 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
     // ybar (into gx itself without b, where gx = ybar), then the coefficient
     // gradients from it in a fully parallel pass.
     if constexpr (kQuadApply<W, io_t, acc_t>) {
-        if (quad_apply_eligible(d) &&
-            ((ga == nullptr && gb == nullptr) || (sizeof(io_t) == 4 && tv_coef_grads_fits(d)))) {
-            const bool coef = ga != nullptr || gb != nullptr;
-            io_t *yb = !coef ? nullptr : (gx != nullptr && !d.has_b) ? gx : (io_t *)(ws + w.yb);
-            filt_status s = bwd_apply_quad_run<io_t>(d, gy, bc, ac, states, gx, gyi, yb, st);
-            if (s != FILT_OK || !coef)
+        // ga alone is formed inside the adjoint pass; with gb (an order-0
+        // FIR part) both come from ybar in the coalesced pass
+        if (quad_apply_eligible(d) && gb == nullptr)
+            return bwd_apply_quad_run<io_t>(d, gy, bc, ac, states, gx, gyi, nullptr, y, yi, ga,
+                                            st);
+        if (quad_apply_eligible(d) && sizeof(io_t) == 4 && tv_coef_grads_fits(d)) {
+            io_t *yb = (gx != nullptr && !d.has_b) ? gx : (io_t *)(ws + w.yb);
+            filt_status s = bwd_apply_quad_run<io_t>(d, gy, bc, ac, states, gx, gyi, yb, y, yi,
+                                                     nullptr, st);
+            if (s != FILT_OK)
                 return s;
             if constexpr (sizeof(io_t) == 4)
                 return tv_coef_grads_run(d, yb, x, xi, y, yi, ga, gb, st);

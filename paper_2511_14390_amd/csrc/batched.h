@@ -193,13 +193,15 @@ kb_bwd_apply_quad(const SegDesc *__restrict__ segs, const Item *__restrict__ ite
     float *gxs = gx + sd.x_off;
     float *gyis = gyi != nullptr ? gyi + sd.ic_off : nullptr;
     if (((int64_t)it.chunk + 1) * d.L > d.T)
-        bwd_apply_quad<AV, false, true>(d, gy + sd.x_off, (const float *)nullptr, a + sd.a_off,
-                                        ws + sd.states_off, gxs, gyis, gxs, 0, it.chunk,
-                                        (int)(idx & 3));
+        bwd_apply_quad<AV, false, true, false>(d, gy + sd.x_off, (const float *)nullptr,
+                                               a + sd.a_off, ws + sd.states_off, gxs, gyis, gxs,
+                                               (const float *)nullptr, (const float *)nullptr,
+                                               (float *)nullptr, 0, it.chunk, (int)(idx & 3));
     else
-        bwd_apply_quad<AV, false, false>(d, gy + sd.x_off, (const float *)nullptr, a + sd.a_off,
-                                         ws + sd.states_off, gxs, gyis, gxs, 0, it.chunk,
-                                         (int)(idx & 3));
+        bwd_apply_quad<AV, false, false, false>(d, gy + sd.x_off, (const float *)nullptr,
+                                                a + sd.a_off, ws + sd.states_off, gxs, gyis, gxs,
+                                                (const float *)nullptr, (const float *)nullptr,
+                                                (float *)nullptr, 0, it.chunk, (int)(idx & 3));
 }
 
 // Staged applies (stream.h) over the items (seg, chunk) of one bucket, one

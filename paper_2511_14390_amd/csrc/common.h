@@ -244,6 +244,7 @@ template <typename io_t>
 struct QuadRaw {
     io_t a[4];  // taps 4q .. 4q + 3 of the coefficient row (a_{4q+1} .. a_{4q+4})
     io_t s, g;  // signal sample and its gain (b_0, or 1 without b)
+    io_t y;     // adjoint with gradients: the y sample entering the window
 };
 
 // Taps 4q .. 4q + 3 of one coefficient row (N == 16 and 16-byte aligned rows
