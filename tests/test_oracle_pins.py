@@ -369,3 +369,70 @@ def test_metric_helper():
     ref = np.array([[1.0, -2.0], [0.5, 0.25]])
     got = ref + np.array([[0.0, 2e-4], [0.0, 0.0]])
     assert abs(chan_rel_err(got, ref, "BT") - 1e-4) < 1e-12
+
+
+# ------------------------------------------- per-sample initial-condition gradients
+#
+# The initial-condition gradients (Sec. 3.1 Eq. 9 for dL/dv(0), App. A) read the
+# coefficients of the first max(M, N) samples at their own times: x[-j] and
+# y[-j] enter output n = k - j through b_k[n] and a_k[n].  These pins use
+# coefficients that change on every sample (hop = 1), so a wrong time index in
+# those terms (a row of another sample, e.g. always time 0) changes the result.
+
+def _hop1_problem(seed, layout, T=14):
+    return W.random_problem(seed, B=2, T=T, M=3, N=4, time_varying=True, layout=layout, hop=1,
+                            rho_max=0.9)
+
+
+@pytest.mark.parametrize("layout", ["TB", "BT"])
+def test_per_sample_ic_grads_match_finite_differences_hop1(layout):
+    p = _hop1_problem(91, layout)
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout=layout)
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout=layout)
+    fd = _loss_grads_fd(p, layout)
+    for k in ("x", "a", "b", "xi", "yi"):
+        np.testing.assert_allclose(g[k], fd[k], rtol=1e-6, atol=1e-7, err_msg=k)
+
+
+def _naive_grads(p):
+    """Gradients of L = <gy, y> by a plain FP64 autograd loop over one
+    channel-major problem ([B, T] signals, [B, T, K] rows)."""
+    torch = pytest.importorskip("torch")
+    t = lambda v: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True)
+    x, a, b, xi, yi = t(p.x), t(p.a), t(p.b), t(p.xi), t(p.yi)
+    gy = torch.tensor(p.gy.astype(np.float64))
+    B, T = p.x.shape
+    M, N = p.b.shape[-1] - 1, p.a.shape[-1]
+    outs = []
+    for c in range(B):
+        hx = [xi[c, j] for j in range(M)]
+        hy = [yi[c, j] for j in range(N)]
+        row = []
+        for n in range(T):
+            xs = [x[c, n]] + hx
+            acc = sum(b[c, n, k] * xs[k] for k in range(M + 1))
+            acc = acc - sum(a[c, n, k - 1] * hy[k - 1] for k in range(1, N + 1))
+            row.append(acc)
+            hx = ([x[c, n]] + hx)[:M]
+            hy = ([acc] + hy)[:N]
+        outs.append(torch.stack(row))
+    (torch.stack(outs) * gy).sum().backward()
+    return {k: v.grad.numpy() for k, v in (("x", x), ("a", a), ("b", b), ("xi", xi), ("yi", yi))}
+
+
+@pytest.mark.parametrize("layout", ["TB", "BT"])
+def test_per_sample_ic_grads_match_naive_autograd_hop1(layout):
+    pb = _hop1_problem(92, "BT", T=13)
+    want = _naive_grads(pb)
+    if layout == "TB":
+        sw = lambda v: np.ascontiguousarray(np.swapaxes(v, 0, 1))
+        p = W.Problem(pb.name, "TB", sw(pb.x), sw(pb.a), sw(pb.b), pb.xi, pb.yi, sw(pb.gy))
+    else:
+        p = pb
+    y = oracle.forward(p.x, p.a, p.b, p.xi, p.yi, layout=layout)
+    g = oracle.backward(p.gy, p.x, y, p.a, p.b, p.xi, p.yi, layout=layout)
+    for name in ("x", "a", "b", "xi", "yi"):
+        got = g[name]
+        if layout == "TB" and name in ("x", "a", "b"):
+            got = np.swapaxes(got, 0, 1)
+        np.testing.assert_allclose(got, want[name], rtol=1e-10, atol=1e-12, err_msg=name)
