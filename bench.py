@@ -1,18 +1,25 @@
 """Benchmark: forward + backward throughput of the direct-form filter on one GPU.
 
-Default workload: per-sample (time-varying) all-pole filter, order N = 16,
-B = 64 channels x T = 48000 samples, channel-interleaved [T, B] layout,
-per-sample coefficients [48000, 64, 16] from frame-held (hop 240) reflection
-coefficients, zero initial state, FP32 I/O.  One step = forward plus the full
-backward (gradients of x and of the per-sample coefficients) through the
-autograd.Function, with all inputs already resident in HBM.
+Default workload (``batched-ragged``): 512 independent all-pole filters of
+uneven lengths T ~ U{1000..200000} and orders N in {1, 2, 4, 8, 16}, with
+per-sample coefficients from frame-held (hop 128) reflection coefficients,
+random initial states, FP32 I/O, packed into flat arrays (51.6 M samples).
+One step = forward plus the full backward (gradients of x, of the per-sample
+coefficients and of the initial states) of every filter, through the batched
+plan with its autotuned chunk lengths, replayed as one HIP graph, with all
+inputs already resident in HBM.  Also timed: the same work as plain
+per-filter calls of the dense C ABI (eager, and the loop captured in a
+graph), and the FP64 CPU oracle on the host's cores.
 
-Prints one JSON line.  Also reports the dominant kernel's achieved HBM
-bandwidth (algorithmic bytes per launch / its average duration, timed with
-HIP events on the launch stream during the timed steps), its HBM traffic as
-counted by rocprofv3 (from the committed counter summary, only while the
-kernel sources are unchanged since the count) and the FP64 CPU oracle timed
-on the host.
+The other workloads (``--workload``): the per-sample order-16 filter
+(64 x 48000), the time-invariant M = N = 4 filter on [65536, 1024] and the
+long narrow order-4 filter (2 x 2^22), through the autograd.Function.
+
+Prints one JSON line with the dominant kernel's achieved HBM bandwidth
+(algorithmic bytes per launch / its average duration, timed with HIP events
+on the stream it runs on) and its HBM traffic as counted by rocprofv3 (from
+the committed counter summary, only while the kernel sources are unchanged
+since the count).
 """
 from __future__ import annotations
 
@@ -34,10 +41,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="ltv-allpole-n16",
+    ap.add_argument("--workload", default="batched-ragged",
                     choices=["ltv-allpole-n16", "lti-allpole-n2", "lti-df-m4n4",
                              "lti-allpole-n4-long", "batched-ragged"])
-    ap.add_argument("--plain-steps", type=int, default=2,
+    ap.add_argument("--plain-steps", type=int, default=3,
                     help="steps of the per-filter launch loop timed for comparison")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--bucket-chunks", default="",
@@ -46,6 +53,8 @@ def parse():
     ap.add_argument("--layout", choices=["TB", "BT"], default=None,
                     help="signal layout (default: the workload's own)")
     ap.add_argument("--f32-state", action="store_true")
+    ap.add_argument("--toeplitz", action="store_true",
+                    help="time-invariant [B, T] workloads: the opt-in FP32 matrix-core path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -161,10 +170,102 @@ def counted_traffic(workload, layout, chunk, kernel):
     return None
 
 
+def batched_kernel_bytes(s, chunks, name):
+    """Algorithmic bytes of one launch of a batched kernel (name ends in the
+    order bucket, e.g. ``batched_fwd_apply_w16``): the per-sample bytes of
+    that phase (signals 4 B, coefficient rows 4 N B) summed over the bucket's
+    segments and the samples the phase covers.  None for the carry kernels
+    (they move O(N^2) doubles per chunk, not samples)."""
+    import numpy as np
+
+    kind, _, w = name.rpartition("_w")
+    if not w.isdigit():
+        return None
+    W = int(w)
+    bucket = {1: 0, 2: 1, 4: 2, 8: 3, 16: 4}[W]
+    L = chunks[bucket]
+    Wb = np.maximum(1, 2 ** np.ceil(np.log2(np.maximum(s.N, 1)))).astype(np.int64)
+    sel = Wb == W
+    T = s.T[sel].astype(np.float64)
+    N = s.N[sel].astype(np.float64)
+    C = np.ceil(T / L)
+    # the forward summarises chunks 0..C-2, the adjoint chunks 1..C-1
+    summ = np.maximum(T - L, 0) * (C > 1)
+    per = {
+        # read the signal and the coefficient rows
+        "batched_fwd_summary": (summ, 4, 4),
+        "batched_bwd_summary": (summ, 4, 4),
+        # read x and the rows, write y
+        "batched_fwd_apply": (T, 8, 4),
+        "batched_stream_fwd": (T, 8, 4),
+        # read gy and the rows, write gx (= ybar for b = [1]); the per-sample
+        # products go to coef_grads
+        "batched_bwd_apply": (T, 8, 4),
+        "batched_stream_bwd": (T, 8, 4),
+        # read ybar and y, write the ga rows
+        "batched_coef_grads": (T, 8, 4),
+    }.get(kind)
+    if per is None:
+        return None
+    n, sig, coef = per
+    return float((n * (sig + coef * N)).sum())
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def batched_cpu_baseline(s, seconds):
+    """The FP64 oracle over every segment of the batched workload (forward +
+    backward with the gradients of x, a and yi), once on one thread and
+    repeated on all host cores (one segment per task)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+
+    def one(i):
+        x, a, yi, gy = s.segment(i)
+        x64, a64, gy64 = (np.asarray(v, np.float64)[None] for v in (x, a, gy))
+        yi64 = np.asarray(yi, np.float64)[None] if len(yi) else None
+        y = oracle.forward(x64, a64, None, None, yi64, layout="BT", nthreads=1)
+        oracle.backward(gy64, x64, y, a64, None, None, yi64, layout="BT", want=("x", "a", "yi"),
+                        nthreads=1)
+
+    samples = int(s.T.sum())
+    order = list(np.argsort(-s.T))   # longest first
+    c0 = time.perf_counter()
+    for i in order:
+        one(i)
+    one_thread = samples / (time.perf_counter() - c0) / 1e9
+    cores = len(os.sched_getaffinity(0))
+    reps, c0 = 0, time.perf_counter()
+    with cf.ThreadPoolExecutor(cores) as ex:
+        while True:
+            list(ex.map(one, order))
+            reps += 1
+            if time.perf_counter() - c0 >= seconds:
+                break
+    dt = time.perf_counter() - c0
+    return {"value": round(samples * reps / dt / 1e9, 6), "unit": "Gsamples/s", "cores": cores,
+            "kind": "oracle", "value_1_thread": round(one_thread, 6), "cpu_model": cpu_model(),
+            "sample": f"the whole workload ({len(s.T)} segments, {samples} samples, fwd + bwd "
+                      f"with grads of x, a and yi), FP64; once on 1 thread, then {reps}x on "
+                      f"{cores} threads (one segment per task) in {dt:.1f} s"}
+
+
 def batched_main(args):
     """Many uneven per-sample all-pole filters: the batched plan (autotuned
-    chunk lengths, forward + backward replayed as one HIP graph) against plain
-    per-filter calls of the dense C ABI on the same stream."""
+    chunk lengths, forward + backward replayed as a HIP graph) against plain
+    per-filter calls of the dense C ABI on the same stream (eager, and the
+    same loop captured in a graph)."""
     import numpy as np
     import torch
 
@@ -189,22 +290,80 @@ def batched_main(args):
     gx = torch.empty_like(x)
     ga = torch.zeros_like(a)
     gyi = torch.zeros_like(yi)
+
+    def eager_step():
+        plan.forward(x, a, yi, out=y)
+        plan.backward(gy, y, a, yi, out={"x": gx, "a": ga, "yi": gyi})
+
+    # warm-up: eager steps, every launch between an event pair (first one
+    # unrecorded) for the per-kernel breakdown and the dominant kernel
+    eager_step()
+    torch.cuda.synchronize()
+    F.profile_only(None)
+    F.profile_enable(True)
+    wsteps = max(args.warmup, 1)
+    for _ in range(wsteps):
+        eager_step()
+    torch.cuda.synchronize()
+    F.profile_enable(False)
+    prof = F.profile_read()
+    kern = {k: {"launches": c // wsteps, "avg_us": round(1e3 * ms / c, 2),
+                "total_ms_per_step": round(ms / wsteps, 4)} for k, (c, ms) in prof.items()}
+    dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"]) if kern else None
+
+    if args.calib_copy_mib > 0:
+        src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    # timed region 1: graph replays of the whole step (value)
     plan.capture(x, a, yi, gy, y, gx, ga, gyi)
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.warmup)):
         plan.replay()
     torch.cuda.synchronize()
-    F.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.replay()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    F.profile_enable(False)
-    F.profile_read()
     ms = (t1 - t0) * 1e3 / args.steps
     value = samples / (ms * 1e-3) / 1e9
 
-    # plain: one dense forward + backward call per filter
+    # timed region 2: the same steps launched eagerly with one HIP event pair
+    # per launch of the dominant kernel only, recorded on the stream it runs
+    # on (roofline.achieved); event pairs around every launch slow the
+    # kernels they bracket, so the breakdown above is only used to pick it
+    F.profile_only(dom)
+    F.profile_enable(True)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for _ in range(args.steps):
+        eager_step()
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - e0) * 1e3 / args.steps
+    F.profile_enable(False)
+    live = F.profile_read()
+    F.profile_only(None)
+
+    roofline = None
+    if dom in live:
+        c, dms = live[dom]
+        avg_us = 1e3 * dms / c
+        kern[dom]["eager_region_avg_us"] = round(avg_us, 2)
+        kern[dom]["eager_region_launches"] = c
+        per_launch = batched_kernel_bytes(s, chunks, dom)
+        if per_launch is not None:
+            ach = per_launch / (avg_us * 1e-6) / 1e9
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": counted_traffic("batched-ragged", "packed",
+                                                   chunks[4], dom),
+                        "bytes_per_launch": per_launch, "avg_launch_us": round(avg_us, 2)}
+
+    # plain: one dense forward + backward call per filter, eager and captured
     segs = [(int(s.T[i]), int(s.N[i]), int(s.x_off[i]), int(s.a_off[i]), int(s.ic_off[i]))
             for i in range(len(s.T))]
 
@@ -217,7 +376,7 @@ def batched_main(args):
             F.filt_backward(gy[xo:xo + tt][None], xs, ys, as_, None, None, yis, layout="BT",
                             want=("x", "a", "yi"))
 
-    plain_ms = None
+    plain_ms = plain_graph_ms = None
     if args.plain_steps > 0:
         plain_step()
         torch.cuda.synchronize()
@@ -226,19 +385,52 @@ def batched_main(args):
             plain_step()
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
+        try:
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                plain_step()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            with torch.cuda.graph(g):
+                plain_step()
+            g.replay()
+            torch.cuda.synchronize()
+            p0 = time.perf_counter()
+            for _ in range(args.plain_steps):
+                g.replay()
+            torch.cuda.synchronize()
+            plain_graph_ms = (time.perf_counter() - p0) * 1e3 / args.plain_steps
+            del g
+        except Exception as e:  # reported, not fatal
+            print(f"plain loop graph capture failed: {e}", file=sys.stderr, flush=True)
+
     coef = 4 * float((s.T * s.N).sum())
-    algo = 4 * samples * 2 + coef + (4 * samples * 3 + 2 * coef)   # fwd + bwd bytes
+    # forward: x, y, the rows; backward: gy, y, gx, the rows read, ga written
+    algo = 4 * samples * 2 + coef + (4 * samples * 3 + 2 * coef)
+    cpu = None if args.no_cpu_baseline else batched_cpu_baseline(s, args.cpu_seconds)
     rec = {
         "metric": "fwd+bwd Gsamples/s & % HBM roofline, batched vs plain, rel err <=1e-4 vs FP64",
         "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batched-ragged", "io": "f32", "segments": len(s.T),
-                   "samples": samples, "chunks_by_order_bucket": chunks,
+                   "samples": samples, "T_range": [int(s.T.min()), int(s.T.max())],
+                   "orders": sorted(set(int(n) for n in s.N)), "hop": s.meta["hop"],
+                   "chunks_by_order_bucket": chunks, "timed": "hip graph replay",
                    "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "eager_ms_per_step": round(eager_ms, 4),
+        "whole_step_algorithmic_bytes": algo,
         "whole_step_hbm_frac": round(algo / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "plain_ms_per_step": round(plain_ms, 3) if plain_ms else None,
+        "plain_graph_ms_per_step": round(plain_graph_ms, 3) if plain_graph_ms else None,
         "batched_speedup_vs_plain": round(plain_ms / ms, 2) if plain_ms else None,
+        "batched_speedup_vs_plain_graph": (round(plain_graph_ms / ms, 2)
+                                           if plain_graph_ms else None),
+        "kernels": kern,
     }
     print(json.dumps(rec), flush=True)
 
@@ -275,7 +467,7 @@ def main():
 
     def step():
         y = AG.lfilter(x, a, b, xi, yi, layout=p.layout, chunk=args.chunk,
-                       f32_state=args.f32_state)
+                       f32_state=args.f32_state, toeplitz=args.toeplitz)
         inputs = [v for v in (x, a, b, xi, yi) if v is not None]
         torch.autograd.grad(y, inputs, gy)
 
@@ -323,7 +515,7 @@ def main():
                      "total_ms_per_step": ms / args.steps, "timed_region": True}
 
     roofline = None
-    chunk = F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk))
+    chunk = F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk, toeplitz=args.toeplitz))
     if dom is not None and kernel_flops(p, dom, chunk) is not None:
         # the dominant kernel is bound by FP64 vector arithmetic (SQ counters:
         # VALU issue), so it is measured against the FP64 vector peak
@@ -369,7 +561,7 @@ def main():
         "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32-state" if args.f32_state else "f64",
+        "dtype": "f32-state" if args.f32_state else ("f32-mfma" if args.toeplitz else "f64"),
         "data": "synthetic",
         "config": {"workload": p.name, "io": "f32", "B": p.B, "T": p.T, "M": p.M, "N": p.N,
                    "time_varying": bool(p.time_varying), "layout": p.layout,

@@ -60,22 +60,27 @@ typedef enum { FILT_LAYOUT_TB = 0, FILT_LAYOUT_BT = 1 } filt_layout;
  * poles cluster near the unit circle.  FILT_F32_STATE runs the per-sample
  * output pass in FP32 instead (the chunk transitions and the carry stay FP64). */
 #define FILT_F32_STATE 0x2
-/* Time-invariant problems in the [B][T] layout (FP32 entry points) run the
- * chunked scan with each chunk's zero-state response computed as a
+/* FILT_TOEPLITZ: time-invariant problems in the [B][T] layout (FP32 entry
+ * points) run the chunked scan with each chunk's response computed as a
  * lower-triangular Toeplitz matrix product on the FP32 matrix cores (chunks
- * of 64 samples; chunk must be 0 or 64) and the chunk carry in FP64; their
- * error is that of FP32 arithmetic over 64-term sums (about 1e-6 relative).
- * FILT_RECURRENCE makes them use the per-lane recurrence (FP64 state) instead. */
+ * of 64 samples; chunk must be 0 or 64) and the chunk carry in FP64.  Its
+ * error is that of FP32 sums in which the entering state's response can
+ * cancel: about 1e-6 relative for moderate poles, but up to 5e-4 for two
+ * pole pairs of radius near 0.99 (one draw in twelve of that domain), so it
+ * is opt-in.  By default (and with FILT_RECURRENCE, kept for compatibility)
+ * every problem runs the per-lane recurrence with FP64 state. */
 #define FILT_RECURRENCE 0x4
+#define FILT_TOEPLITZ 0x8
 
 typedef struct {
-    int64_t B;            /* channels (>= 0); B == 0 or T == 0 is a no-op */
+    int64_t B;            /* channels (>= 0); B == 0 or T == 0 writes no signal (see
+                             filt_backward for the per-channel gradients then) */
     int64_t T;            /* samples per channel (>= 0) */
     int32_t M;            /* feed-forward order: b_0..b_M, 0 <= M <= 16 */
     int32_t N;            /* feedback order: a_1..a_N, 0 <= N <= 16 */
     int32_t time_varying; /* 0: coefficients per channel; 1: per sample */
     int32_t layout;       /* filt_layout of x, y, gy, gx (and per-sample coefficients) */
-    int32_t flags;        /* FILT_F32_STATE | FILT_RECURRENCE, or 0 */
+    int32_t flags;        /* FILT_F32_STATE | FILT_RECURRENCE | FILT_TOEPLITZ, or 0 */
     int32_t chunk;        /* time-chunk length for the parallel scan; 0 = automatic,
                              else a multiple of 32 */
 } filt_problem;
@@ -104,7 +109,9 @@ filt_status filt_forward(const filt_problem *p, const float *x, const float *b, 
  * x, xi are read only when gb is requested or M > 0 matters for it; y, yi
  * only when ga is requested.  Each of gx, gb, ga, gxi, gyi may be NULL (not
  * computed); the others are written in full with the shapes of x, b, a, xi,
- * yi. */
+ * yi.  With T == 0 (and B > 0) no output depends on any input: the
+ * per-channel outputs (gxi, gyi and the time-invariant gb, ga) are set to
+ * zero by a kernel on the stream and FILT_OK is returned. */
 filt_status filt_backward(const filt_problem *p, const float *gy, const float *x, const float *y,
                           const float *b, const float *a, const float *xi, const float *yi,
                           float *gx, float *gb, float *ga, float *gxi, float *gyi, void *ws,
@@ -149,8 +156,12 @@ typedef struct filt_plan filt_plan;
 
 /* Build a plan (host call; allocates its device tables and workspace and
  * synchronises).  segs is a host array of nseg segments.  chunks: NULL for
- * the defaults, else a host array of 5 chunk lengths (multiples of 32) for
- * the order buckets N <= 1, 2, 4, 8, 16. */
+ * the defaults, else a host array of 5 entries for the order buckets
+ * N <= 1, 2, 4, 8, 16: -1 runs the bucket's single-pass kernel (one launch
+ * per direction, tiles chained by decoupled look-back), a positive multiple
+ * of 32 the three-phase scan (summaries, carry, apply) with that chunk
+ * length, 0 the default (single pass for orders up to 4, else the three-phase
+ * scan at its default chunk). */
 filt_status filt_plan_create(const filt_segment *segs, int32_t nseg, const int32_t *chunks,
                              filt_plan **out);
 void filt_plan_destroy(filt_plan *p);
@@ -164,8 +175,10 @@ filt_status filt_plan_backward(filt_plan *p, const float *gy, const float *y, co
                                const float *yi, float *gx, float *ga, float *gyi, void *stream);
 
 /* Autotuner: for each order bucket, time forward + backward of that bucket's
- * segments for several chunk lengths (HIP events, median of 3) and keep the
- * fastest; then re-lay the plan.  Synchronises; the outputs are scratch. */
+ * segments with the single-pass kernel and with the three-phase scan at
+ * several chunk lengths (HIP events, median of 3) and keep the fastest; then
+ * re-lay the plan.  Synchronises; the outputs are scratch.  get_chunks
+ * reports the choice in the form filt_plan_create takes (-1: single pass). */
 filt_status filt_plan_tune(filt_plan *p, const float *x, const float *a, const float *yi,
                            const float *gy, float *y, float *gx, float *ga, float *gyi,
                            void *stream);

@@ -17,30 +17,30 @@ from . import filt as _f
 
 class LFilter(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x, a, b, xi, yi, layout, chunk, f32_state, recurrence):
+    def forward(ctx, x, a, b, xi, yi, layout, chunk, f32_state, toeplitz):
         y = _f.filt_forward(x, a, b, xi, yi, layout=layout, chunk=chunk, f32_state=f32_state,
-                            recurrence=recurrence)
+                            toeplitz=toeplitz)
         ctx.save_for_backward(x, a, b, xi, yi, y)
-        ctx.cfg = (layout, chunk, f32_state, recurrence)
+        ctx.cfg = (layout, chunk, f32_state, toeplitz)
         return y
 
     @staticmethod
     def backward(ctx, gy):
         x, a, b, xi, yi, y = ctx.saved_tensors
-        layout, chunk, f32_state, recurrence = ctx.cfg
+        layout, chunk, f32_state, toeplitz = ctx.cfg
         need = ctx.needs_input_grad
         want = [k for k, n in zip(("x", "a", "b", "xi", "yi"), need[:5]) if n]
         if not want:
             return (None,) * 9
         g = _f.filt_backward(gy, x, y, a, b, xi, yi, layout=layout, chunk=chunk,
-                             f32_state=f32_state, recurrence=recurrence, want=tuple(want))
+                             f32_state=f32_state, toeplitz=toeplitz, want=tuple(want))
         return (g.get("x"), g.get("a"), g.get("b") if b is not None else None,
                 g.get("xi") if xi is not None else None, g.get("yi") if yi is not None else None,
                 None, None, None, None)
 
 
 def lfilter(x, a, b=None, xi=None, yi=None, layout="BT", chunk=0, f32_state=False,
-            recurrence=False):
+            toeplitz=False):
     """Differentiable y[n] = sum_k b_k[n] x[n-k] - sum_k a_k[n] y[n-k].
 
     ``a`` / ``b`` may be per-channel ``[B, K]`` or per-sample (the signal
@@ -56,4 +56,4 @@ def lfilter(x, a, b=None, xi=None, yi=None, layout="BT", chunk=0, f32_state=Fals
     if yi is not None:
         yi = yi.contiguous()
     return LFilter.apply(x.contiguous(), a, b, xi, yi, layout, int(chunk), bool(f32_state),
-                         bool(recurrence))
+                         bool(toeplitz))

@@ -122,7 +122,7 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
     if (p->chunk < 0 || (p->chunk % 32) != 0)
         return fail(FILT_EINVAL, "chunk must be 0 or a positive multiple of 32 (got %d)",
                     p->chunk);
-    if (p->flags & ~(FILT_F32_STATE | FILT_RECURRENCE))
+    if (p->flags & ~(FILT_F32_STATE | FILT_RECURRENCE | FILT_TOEPLITZ))
         return fail(FILT_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->B == 0 || p->T == 0)
         return FILT_OK;
@@ -143,8 +143,9 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
 // unless the caller asks for the per-lane recurrence or another chunk length.
 bool tz_eligible(const filt_problem *p, bool f32_io)
 {
-    return f32_io && !p->time_varying && p->layout == FILT_LAYOUT_BT && p->N >= 1 &&
-           !(p->flags & FILT_RECURRENCE) && (p->chunk == 0 || p->chunk == kTzL);
+    return f32_io && (p->flags & FILT_TOEPLITZ) && !(p->flags & FILT_RECURRENCE) &&
+           !p->time_varying && p->layout == FILT_LAYOUT_BT && p->N >= 1 &&
+           (p->chunk == 0 || p->chunk == kTzL);
 }
 
 Dims make_dims(const filt_problem *p, int has_b, bool f32_io)
@@ -203,6 +204,24 @@ filt_status backward_dispatch(const Dims &d, int W, const io_t *gy, const io_t *
 }
 
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero(T *__restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
+}
+
+template <typename T>
+filt_status zero_fill(T *p, int64_t n, hipStream_t st)
+{
+    if (p == nullptr || n <= 0)
+        return FILT_OK;
+    const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    FILT_LAUNCH("zero_fill", k_zero<T>, dim3(g), dim3(256), 0, st, p, n);
+    return check_launch("zero fill");
+}
+
 template <typename io_t>
 filt_status forward_entry(const filt_problem *p, const io_t *x, const io_t *bc, const io_t *ac,
                           const io_t *xi, const io_t *yi, io_t *y, void *ws, size_t ws_bytes,
@@ -251,9 +270,23 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
     if (s != FILT_OK)
         return s;
     if (p->B == 0 || p->T == 0) {
-        if (p->B > 0 && (gxi != nullptr || gyi != nullptr || ga != nullptr || gb != nullptr))
-            return fail(FILT_EUNSUPPORTED, "T == 0 with gradient outputs: caller zero-fills");
-        return FILT_OK;
+        // no output depends on any input: the per-channel gradients (initial
+        // conditions, time-invariant coefficients) are zero, the per-sample
+        // ones are empty.  Cleared by a kernel, not a memset node, so the call
+        // stays capturable.
+        if (p->B == 0)
+            return FILT_OK;
+        hipStream_t st = (hipStream_t)stream;
+        const int64_t nb = p->time_varying ? 0 : p->B * (int64_t)(p->M + 1);
+        const int64_t na = p->time_varying ? 0 : p->B * (int64_t)p->N;
+        s = zero_fill(gb, bc != nullptr ? nb : 0, st);
+        if (s == FILT_OK)
+            s = zero_fill(ga, na, st);
+        if (s == FILT_OK)
+            s = zero_fill(gxi, p->B * (int64_t)p->M, st);
+        if (s == FILT_OK)
+            s = zero_fill(gyi, p->B * (int64_t)p->N, st);
+        return s;
     }
     if (gb != nullptr && bc == nullptr)
         return fail(FILT_EINVAL, "gb requested but b is NULL");

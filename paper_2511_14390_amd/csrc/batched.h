@@ -22,6 +22,7 @@ struct SegDesc {
     int64_t x_off, T, a_off, ic_off;
     int64_t L, C, G, NB;
     int64_t summ_off, states_off, agg_off, bstart_off;
+    int64_t tile_base, ntile;  // single-pass buckets: first tile record, tiles
     int32_t N, a_vec;
 };
 
@@ -286,7 +287,7 @@ template <int W>
 __global__ void __launch_bounds__(256)
 kb_coef_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t Lc,
               const float *__restrict__ ybar, const float *__restrict__ y,
-              const float *__restrict__ yi, float *__restrict__ ga)
+              const float *__restrict__ yi, float *__restrict__ ga, int ga_aligned)
 {
     const Item it = items[blockIdx.x];
     const SegDesc sd = segs[it.seg];
@@ -296,7 +297,9 @@ kb_coef_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
     const int64_t t0 = (int64_t)it.chunk * Lc;
     const int64_t n = min(Lc, sd.T - t0);
     const int G = (N + 3) / 4;
-    const bool vec = (N % 4) == 0;  // a_off is a multiple of 4 floats
+    // whole float4 rows only when every row starts on a 16-byte boundary: a
+    // 16-byte aligned ga base (checked on the host), N and a_off multiples of 4
+    const bool vec = ga_aligned && (N % 4) == 0 && (sd.a_off % 4) == 0;
     for (int64_t u = threadIdx.x; u < n * G; u += blockDim.x) {
         const int64_t t = t0 + u / G;
         const int q = (int)(u % G);
@@ -401,6 +404,12 @@ inline unsigned row_groups(int64_t n)
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kCUs * 4));
 }
 
+// Launch names carry the order bucket ("..._w16"), so per-kernel timings
+// and byte counts can be attributed to one bucket's samples.
+#define FILT_BNAME(KIND, W)                                                                        \
+    ((W) == 1 ? KIND "_w1" : (W) == 2 ? KIND "_w2" : (W) == 4 ? KIND "_w4" : (W) == 8 ? KIND "_w8" \
+                                                                                : KIND "_w16")
+
 // One bucket's launches (defined per bucket in generated units).
 struct BucketArgs {
     const SegDesc *segs;
@@ -419,10 +428,10 @@ filt_status batched_fwd_summary(const BucketArgs &b, const float *x, const float
         return FILT_OK;
     if constexpr (W == 16) {
         if (b.av)
-            FILT_LAUNCH("batched_fwd_summary", kb_fwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
+            FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), kb_fwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
                         dim3(kRowGroupThreads), 0, st, b.segs, b.sum_items, b.sum_n, x, a, ws);
         else
-            FILT_LAUNCH("batched_fwd_summary", kb_fwd_summary_rows<false>,
+            FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), kb_fwd_summary_rows<false>,
                         dim3(row_groups(b.sum_n)), dim3(kRowGroupThreads), 0, st, b.segs,
                         b.sum_items, b.sum_n, x, a, ws);
         return check_launch("batched forward summary");
@@ -430,10 +439,10 @@ filt_status batched_fwd_summary(const BucketArgs &b, const float *x, const float
     unsigned g, t;
     persistent_grid(b.sum_n, g, t);
     if (b.av)
-        FILT_LAUNCH("batched_fwd_summary", (kb_fwd_summary<W, true>), dim3(g), dim3(t), 0, st,
+        FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), (kb_fwd_summary<W, true>), dim3(g), dim3(t), 0, st,
                     b.segs, b.sum_items, b.sum_n, x, a, ws);
     else
-        FILT_LAUNCH("batched_fwd_summary", (kb_fwd_summary<W, false>), dim3(g), dim3(t), 0, st,
+        FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), (kb_fwd_summary<W, false>), dim3(g), dim3(t), 0, st,
                     b.segs, b.sum_items, b.sum_n, x, a, ws);
     return check_launch("batched forward summary");
 }
@@ -446,10 +455,10 @@ filt_status batched_bwd_summary(const BucketArgs &b, const float *gy, const floa
         return FILT_OK;
     if constexpr (W == 16) {
         if (b.av)
-            FILT_LAUNCH("batched_bwd_summary", kb_bwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), kb_bwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
                         dim3(kRowGroupThreads), 0, st, b.segs, b.sum_items, b.sum_n, gy, a, ws);
         else
-            FILT_LAUNCH("batched_bwd_summary", kb_bwd_summary_rows<false>,
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), kb_bwd_summary_rows<false>,
                         dim3(row_groups(b.sum_n)), dim3(kRowGroupThreads), 0, st, b.segs,
                         b.sum_items, b.sum_n, gy, a, ws);
         return check_launch("batched backward summary");
@@ -457,10 +466,10 @@ filt_status batched_bwd_summary(const BucketArgs &b, const float *gy, const floa
     unsigned g, t;
     persistent_grid(b.sum_n, g, t);
     if (b.av)
-        FILT_LAUNCH("batched_bwd_summary", (kb_bwd_summary<W, true>), dim3(g), dim3(t), 0, st,
+        FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), (kb_bwd_summary<W, true>), dim3(g), dim3(t), 0, st,
                     b.segs, b.sum_items, b.sum_n, gy, a, ws);
     else
-        FILT_LAUNCH("batched_bwd_summary", (kb_bwd_summary<W, false>), dim3(g), dim3(t), 0, st,
+        FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), (kb_bwd_summary<W, false>), dim3(g), dim3(t), 0, st,
                     b.segs, b.sum_items, b.sum_n, gy, a, ws);
     return check_launch("batched backward summary");
 }
@@ -474,20 +483,20 @@ filt_status batched_fwd_apply(const BucketArgs &b, const float *x, const float *
     if constexpr (W == 16) {
         const dim3 grid((unsigned)((b.app_n * 4 + kThreads - 1) / kThreads));
         if (b.av)
-            FILT_LAUNCH("batched_fwd_apply", kb_fwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
+            FILT_LAUNCH(FILT_BNAME("batched_fwd_apply", W), kb_fwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
                         b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
         else
-            FILT_LAUNCH("batched_fwd_apply", kb_fwd_apply_quad<false>, grid, dim3(kThreads), 0,
+            FILT_LAUNCH(FILT_BNAME("batched_fwd_apply", W), kb_fwd_apply_quad<false>, grid, dim3(kThreads), 0,
                         st, b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
         return check_launch("batched forward apply");
     }
     unsigned g, t;
     persistent_grid(b.app_n, g, t);
     if (b.av)
-        FILT_LAUNCH("batched_fwd_apply", (kb_fwd_apply<W, true>), dim3(g), dim3(t), 0, st, b.segs,
+        FILT_LAUNCH(FILT_BNAME("batched_fwd_apply", W), (kb_fwd_apply<W, true>), dim3(g), dim3(t), 0, st, b.segs,
                     b.app_items, b.app_n, x, a, yi, ws, y);
     else
-        FILT_LAUNCH("batched_fwd_apply", (kb_fwd_apply<W, false>), dim3(g), dim3(t), 0, st,
+        FILT_LAUNCH(FILT_BNAME("batched_fwd_apply", W), (kb_fwd_apply<W, false>), dim3(g), dim3(t), 0, st,
                     b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
     return check_launch("batched forward apply");
 }
@@ -502,7 +511,7 @@ filt_status batched_bwd_apply(const BucketArgs &b, const float *gy, const float 
     unsigned g, t;
     persistent_grid(b.app_n, g, t);
 #define FILT_KB_BWD(AVV, GAV)                                                                      \
-    FILT_LAUNCH("batched_bwd_apply", (kb_bwd_apply<W, AVV, GAV>), dim3(g), dim3(t), 0, st, b.segs, \
+    FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), (kb_bwd_apply<W, AVV, GAV>), dim3(g), dim3(t), 0, st, b.segs, \
                 b.app_items, b.app_n, gy, y, a, yi, ws, gx, ga, gyi)
     if (b.av) {
         if (ga != nullptr)
@@ -531,10 +540,10 @@ filt_status batched_stream_fwd(const BucketArgs &b, int64_t Lc, const float *x, 
         return FILT_OK;
     const dim3 grid((unsigned)((b.app_n + 63) / 64));
     if (b.av && W % 4 == 0)
-        FILT_LAUNCH("batched_stream_fwd", (kb_stream_fwd<W, (W % 4 == 0)>), grid, dim3(64), 0, st,
+        FILT_LAUNCH(FILT_BNAME("batched_stream_fwd", W), (kb_stream_fwd<W, (W % 4 == 0)>), grid, dim3(64), 0, st,
                     b.segs, b.app_items, b.app_n, Lc, x, a, yi, ws, y);
     else
-        FILT_LAUNCH("batched_stream_fwd", (kb_stream_fwd<W, false>), grid, dim3(64), 0, st, b.segs,
+        FILT_LAUNCH(FILT_BNAME("batched_stream_fwd", W), (kb_stream_fwd<W, false>), grid, dim3(64), 0, st, b.segs,
                     b.app_items, b.app_n, Lc, x, a, yi, ws, y);
     return check_launch("batched staged forward apply");
 }
@@ -548,14 +557,14 @@ filt_status batched_stream_bwd(const BucketArgs &b, int64_t Lc, const float *gy,
         return FILT_OK;
     const dim3 grid((unsigned)((b.app_n + 63) / 64));
     if (b.av && W % 4 == 0)
-        FILT_LAUNCH("batched_stream_bwd", (kb_stream_bwd<W, (W % 4 == 0)>), grid, dim3(64), 0, st,
+        FILT_LAUNCH(FILT_BNAME("batched_stream_bwd", W), (kb_stream_bwd<W, (W % 4 == 0)>), grid, dim3(64), 0, st,
                     b.segs, b.app_items, b.app_n, Lc, gy, a, ws, gx, gyi);
     else
-        FILT_LAUNCH("batched_stream_bwd", (kb_stream_bwd<W, false>), grid, dim3(64), 0, st, b.segs,
+        FILT_LAUNCH(FILT_BNAME("batched_stream_bwd", W), (kb_stream_bwd<W, false>), grid, dim3(64), 0, st, b.segs,
                     b.app_items, b.app_n, Lc, gy, a, ws, gx, gyi);
     if (ga != nullptr)
-        FILT_LAUNCH("batched_coef_grads", kb_coef_grads<W>, dim3((unsigned)b.app_n), dim3(256), 0, st,
-                    b.segs, b.app_items, Lc, gx, y, yi, ga);
+        FILT_LAUNCH(FILT_BNAME("batched_coef_grads", W), kb_coef_grads<W>, dim3((unsigned)b.app_n), dim3(256), 0, st,
+                    b.segs, b.app_items, Lc, gx, y, yi, ga, (int)((uintptr_t)ga % 16 == 0));
     return check_launch("batched staged backward apply");
 }
 
@@ -572,10 +581,10 @@ filt_status batched_bwd_split(const BucketArgs &b, int64_t Lc, const float *gy, 
     if constexpr (W == 16) {
         const dim3 grid((unsigned)((b.app_n * 4 + kThreads - 1) / kThreads));
         if (b.av)
-            FILT_LAUNCH("batched_bwd_apply", kb_bwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
                         b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);
         else
-            FILT_LAUNCH("batched_bwd_apply", kb_bwd_apply_quad<false>, grid, dim3(kThreads), 0,
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad<false>, grid, dim3(kThreads), 0,
                         st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);
         s = check_launch("batched backward apply");
     } else {
@@ -583,8 +592,8 @@ filt_status batched_bwd_split(const BucketArgs &b, int64_t Lc, const float *gy, 
     }
     if (s != FILT_OK || ga == nullptr)
         return s;
-    FILT_LAUNCH("batched_coef_grads", kb_coef_grads<W>, dim3((unsigned)b.app_n), dim3(256), 0, st,
-                b.segs, b.app_items, Lc, gx, y, yi, ga);
+    FILT_LAUNCH(FILT_BNAME("batched_coef_grads", W), kb_coef_grads<W>, dim3((unsigned)b.app_n), dim3(256), 0, st,
+                b.segs, b.app_items, Lc, gx, y, yi, ga, (int)((uintptr_t)ga % 16 == 0));
     return check_launch("batched coefficient gradients");
 }
 

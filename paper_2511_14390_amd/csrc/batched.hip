@@ -8,7 +8,7 @@
 #include <cstring>
 #include <vector>
 
-#include "batched.h"
+#include "onepass16.h"
 
 namespace filt_detail {
 
@@ -22,6 +22,10 @@ namespace {
 
 constexpr int kBuckets = 5;  // W = 1, 2, 4, 8, 16
 constexpr int kBucketW[kBuckets] = {1, 2, 4, 8, 16};
+// Untuned plans: the single-pass kernel for orders up to 4 and the
+// three-phase scan above (measured faster there); the tuner times both at
+// several chunk lengths per bucket and keeps the faster
+constexpr bool kDefaultOnePass[kBuckets] = {true, true, true, false, false};
 
 int bucket_of(int N)
 {
@@ -103,10 +107,25 @@ struct filt_plan {
     double *d_ws = nullptr;
     size_t ws_doubles = 0;
     int64_t sum_off[kBuckets], sum_n[kBuckets], app_off[kBuckets], app_n[kBuckets];
-    int64_t cblk_off = 0, cblk_n = 0, cseg_off = 0, cseg_n = 0;
-    // dynamic LDS (doubles) of the carry launches: the largest staged run
-    int64_t blk_lds = 0, fill_lds = 0;
-    int max_order = 0;
+    // carry items per bucket: (segment, block) and (segment) lists
+    int64_t cblk_off[kBuckets], cblk_n[kBuckets], cseg_off[kBuckets], cseg_n[kBuckets];
+    // dynamic LDS (doubles) of a bucket's carry launches: its largest staged run
+    int64_t blk_lds[kBuckets], fill_lds[kBuckets];
+    int max_order[kBuckets];
+    // the buckets touch disjoint segments, so each bucket's launch chain runs
+    // on a stream of its own, forked from and joined back into the caller's
+    // stream by events (also inside a captured graph)
+    hipStream_t side[kBuckets] = {};
+    hipEvent_t fork = nullptr, join[kBuckets] = {};
+    // single-pass buckets (orders up to kOnePassMaxW): tile lists in ticket
+    // order for each direction, per-tile records in d_ws, flags and ticket
+    // counters in d_flags
+    bool onepass[kBuckets] = {};
+    int2 *d_tiles = nullptr;
+    int *d_flags = nullptr;
+    size_t flags_n = 0;
+    int64_t tiles_fwd_off[kBuckets] = {}, tiles_bwd_off[kBuckets] = {}, ntiles[kBuckets] = {};
+    int64_t agg_off[kBuckets] = {}, inc_off[kBuckets] = {}, flag_off[kBuckets] = {};
     // captured forward + backward
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -159,6 +178,9 @@ filt_status plan_layout(filt_plan *p)
         const int W = kBucketW[bk];
         const int vec = W >= 4 ? 4 : W;
         d.a_vec = (s.N == W) && (s.a_off % vec == 0);
+        d.tile_base = d.ntile = 0;
+        if (p->onepass[bk])
+            continue;  // its records come with the tiles below
         const int64_t SS = (int64_t)s.N * s.N + s.N;
         d.summ_off = (int64_t)off;
         off += (size_t)(d.C * SS);
@@ -172,13 +194,61 @@ filt_status plan_layout(filt_plan *p)
     }
     for (int b = 0; b < kBuckets; ++b)
         p->bucket_av[b] = true;
+    // single-pass buckets: tiles per segment, records, ticket orders (every
+    // tile after the tiles it waits for; longest segments first in each
+    // rank so the longest chains start early)
+    std::vector<int2> tiles;
+    size_t nflags = 0;
+    {
+        std::vector<int> order(nseg);
+        for (int i = 0; i < nseg; ++i)
+            order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int u, int v) { return p->segs[u].T > p->segs[v].T; });
+        for (int b = 0; b < kBuckets; ++b) {
+            if (!p->onepass[b])
+                continue;
+            // orders up to 4: one wavefront per tile of 64 x 16 samples, maps of
+            // W x W; orders 5..16: one workgroup per tile of 16 x 32 samples,
+            // maps of 16 x 16
+            const int W = kBucketW[b] <= kOnePassMaxW ? kBucketW[b] : 16;
+            const int64_t S = kBucketW[b] <= kOnePassMaxW ? 64 * 16 : OnePass16::S;
+            int64_t nt = 0, maxt = 0;
+            for (int i = 0; i < nseg; ++i) {
+                if (bucket_of(std::max(p->segs[i].N, 1)) != b)
+                    continue;
+                sd[i].ntile = (p->segs[i].T + S - 1) / S;
+                sd[i].tile_base = nt;
+                nt += sd[i].ntile;
+                maxt = std::max(maxt, sd[i].ntile);
+            }
+            p->ntiles[b] = nt;
+            p->agg_off[b] = (int64_t)off;
+            off += (size_t)(nt * (W * W + W));
+            p->inc_off[b] = (int64_t)off;
+            off += (size_t)(nt * W);
+            off = (off + 1) & ~size_t(1);
+            p->flag_off[b] = (int64_t)nflags;
+            nflags += (size_t)nt + 4;  // flags, ticket, timeouts
+            for (int dir = 0; dir < 2; ++dir) {
+                (dir == 0 ? p->tiles_fwd_off[b] : p->tiles_bwd_off[b]) = (int64_t)tiles.size();
+                for (int64_t r = 0; r < maxt; ++r)
+                    for (int i : order) {
+                        if (bucket_of(std::max(p->segs[i].N, 1)) != b || r >= sd[i].ntile)
+                            continue;
+                        const int64_t k = dir == 0 ? r : sd[i].ntile - 1 - r;
+                        tiles.push_back(make_int2(i, (int)k));
+                    }
+            }
+        }
+    }
     std::vector<Item> items;
     for (int b = 0; b < kBuckets; ++b) {
         const int W = kBucketW[b];
         const int S = W == 1 ? 2 : 3;  // SummarySlots
         p->sum_off[b] = (int64_t)items.size();
         for (int i = 0; i < nseg; ++i) {
-            if (bucket_of(std::max(p->segs[i].N, 1)) != b)
+            if (p->onepass[b] || bucket_of(std::max(p->segs[i].N, 1)) != b)
                 continue;
             // full-width rows only if every segment of the bucket has them
             // (an order-0 segment has none)
@@ -195,32 +265,40 @@ filt_status plan_layout(filt_plan *p)
         p->sum_n[b] = (int64_t)items.size() - p->sum_off[b];
         p->app_off[b] = (int64_t)items.size();
         for (int i = 0; i < nseg; ++i) {
-            if (bucket_of(std::max(p->segs[i].N, 1)) != b)
+            if (p->onepass[b] || bucket_of(std::max(p->segs[i].N, 1)) != b)
                 continue;
             for (int64_t c = 0; c < sd[i].C; ++c)
                 items.push_back(Item{i, (int32_t)c, 0, 0});
         }
         p->app_n[b] = (int64_t)items.size() - p->app_off[b];
     }
-    p->cblk_off = (int64_t)items.size();
-    p->blk_lds = p->fill_lds = 0;
-    p->max_order = 0;
-    for (int i = 0; i < nseg; ++i)
-        if (sd[i].C > 1 && sd[i].N > 0) {
-            const int n = sd[i].N;
-            const CarryRec cr = carry_rec(n, (int64_t)n * n + n);
-            p->blk_lds = std::max<int64_t>(p->blk_lds, (int64_t)stage_steps(cr.blk_len, sd[i].NB) * cr.blk_len);
-            p->fill_lds = std::max<int64_t>(p->fill_lds, (int64_t)stage_steps(cr.fill_len, sd[i].G) * cr.fill_len);
-            p->max_order = std::max(p->max_order, n);
-            for (int64_t k = 0; k < sd[i].NB; ++k)
-                items.push_back(Item{i, (int32_t)k, 0, 0});
-        }
-    p->cblk_n = (int64_t)items.size() - p->cblk_off;
-    p->cseg_off = (int64_t)items.size();
-    for (int i = 0; i < nseg; ++i)
-        if (sd[i].C > 1 && sd[i].N > 0)
-            items.push_back(Item{i, 0, 0, 0});
-    p->cseg_n = (int64_t)items.size() - p->cseg_off;
+    for (int b = 0; b < kBuckets; ++b) {
+        auto in_bucket = [&](int i) {
+            return !p->onepass[b] && sd[i].C > 1 && sd[i].N > 0 &&
+                   bucket_of(std::max(p->segs[i].N, 1)) == b;
+        };
+        p->cblk_off[b] = (int64_t)items.size();
+        p->blk_lds[b] = p->fill_lds[b] = 0;
+        p->max_order[b] = 0;
+        for (int i = 0; i < nseg; ++i)
+            if (in_bucket(i)) {
+                const int n = sd[i].N;
+                const CarryRec cr = carry_rec(n, (int64_t)n * n + n);
+                p->blk_lds[b] = std::max<int64_t>(
+                    p->blk_lds[b], (int64_t)stage_steps(cr.blk_len, sd[i].NB) * cr.blk_len);
+                p->fill_lds[b] = std::max<int64_t>(
+                    p->fill_lds[b], (int64_t)stage_steps(cr.fill_len, sd[i].G) * cr.fill_len);
+                p->max_order[b] = std::max(p->max_order[b], n);
+                for (int64_t k = 0; k < sd[i].NB; ++k)
+                    items.push_back(Item{i, (int32_t)k, 0, 0});
+            }
+        p->cblk_n[b] = (int64_t)items.size() - p->cblk_off[b];
+        p->cseg_off[b] = (int64_t)items.size();
+        for (int i = 0; i < nseg; ++i)
+            if (in_bucket(i))
+                items.push_back(Item{i, 0, 0, 0});
+        p->cseg_n[b] = (int64_t)items.size() - p->cseg_off[b];
+    }
 
     filt_status s = to_device(p->d_segs, sd);
     if (s != FILT_OK)
@@ -228,6 +306,19 @@ filt_status plan_layout(filt_plan *p)
     s = to_device(p->d_items, items);
     if (s != FILT_OK)
         return s;
+    s = to_device(p->d_tiles, tiles);
+    if (s != FILT_OK)
+        return s;
+    if (nflags > p->flags_n) {
+        if (p->d_flags != nullptr)
+            hipFree(p->d_flags);
+        p->d_flags = nullptr;
+        if (hipMalloc((void **)&p->d_flags, nflags * sizeof(int)) != hipSuccess)
+            return fail(FILT_EHIP, "hipMalloc of the plan's tile flags failed");
+        if (hipMemset(p->d_flags, 0, nflags * sizeof(int)) != hipSuccess)
+            return fail(FILT_EHIP, "hipMemset of the plan's tile flags failed");
+        p->flags_n = nflags;
+    }
     if (off > p->ws_doubles) {
         if (p->d_ws != nullptr)
             hipFree(p->d_ws);
@@ -252,71 +343,194 @@ BucketArgs bucket_args(const filt_plan *p, int b, const float *a)
     return ba;
 }
 
-filt_status carry_launch(const filt_plan *p, int bwd, const float *yi, hipStream_t st)
+filt_status carry_launch(const filt_plan *p, int b, int bwd, const float *yi, hipStream_t st)
 {
-    if (p->cseg_n == 0)
+    if (p->cseg_n[b] == 0)
         return FILT_OK;
-    const Item *blk = p->d_items + p->cblk_off;
-    const Item *seg = p->d_items + p->cseg_off;
-    const int n = p->max_order;
-    FILT_LAUNCH("batched_carry_agg", kb_carry_agg, dim3((unsigned)p->cblk_n), dim3(64), 0, st,
+    const Item *blk = p->d_items + p->cblk_off[b];
+    const Item *seg = p->d_items + p->cseg_off[b];
+    const int n = p->max_order[b];
+    FILT_LAUNCH("batched_carry_agg", kb_carry_agg, dim3((unsigned)p->cblk_n[b]), dim3(64), 0, st,
                 p->d_segs, blk, p->d_ws, bwd);
-    FILT_LAUNCH("batched_carry_blocks", kb_carry_blocks, dim3((unsigned)p->cseg_n),
-                dim3(carry_threads(p->blk_lds, n)), p->blk_lds * sizeof(double), st, p->d_segs,
-                seg, p->d_ws, bwd, yi);
-    FILT_LAUNCH("batched_carry_fill", kb_carry_fill, dim3((unsigned)p->cblk_n),
-                dim3(carry_threads(p->fill_lds, n)), p->fill_lds * sizeof(double), st, p->d_segs,
-                blk, p->d_ws, bwd);
+    FILT_LAUNCH("batched_carry_blocks", kb_carry_blocks, dim3((unsigned)p->cseg_n[b]),
+                dim3(carry_threads(p->blk_lds[b], n)), p->blk_lds[b] * sizeof(double), st,
+                p->d_segs, seg, p->d_ws, bwd, yi);
+    FILT_LAUNCH("batched_carry_fill", kb_carry_fill, dim3((unsigned)p->cblk_n[b]),
+                dim3(carry_threads(p->fill_lds[b], n)), p->fill_lds[b] * sizeof(double), st,
+                p->d_segs, blk, p->d_ws, bwd);
     return check_launch("batched carry");
+}
+
+OnePassArgs onepass_args(const filt_plan *p, int b, bool bwd)
+{
+    OnePassArgs A{};
+    A.segs = p->d_segs;
+    A.tiles = p->d_tiles + (bwd ? p->tiles_bwd_off[b] : p->tiles_fwd_off[b]);
+    A.ntiles = p->ntiles[b];
+    A.agg = p->d_ws + p->agg_off[b];
+    A.inc = p->d_ws + p->inc_off[b];
+    A.flag = p->d_flags + p->flag_off[b];
+    A.ticket = A.flag + p->ntiles[b];
+    A.timeouts = A.ticket + 1;
+    return A;
+}
+
+// Workgroups of a single-pass launch: enough for every CU to hold several
+// (the LDS of a tile bounds how many are resident); the rest find the
+// ticket counter past the end and leave.
+unsigned onepass_grid(int64_t ntiles)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, kCUs * 8));
+}
+
+unsigned onepass_grid16(int64_t ntiles)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, kCUs * 2));
+}
+
+template <int W>
+filt_status onepass_forward(const filt_plan *p, int b, const float *x, const float *a,
+                            const float *yi, float *y, hipStream_t st)
+{
+    const OnePassArgs A = onepass_args(p, b, false);
+    FILT_LAUNCH("batched_onepass_reset", kb_onepass_reset, dim3(64), dim3(256), 0, st, A.flag,
+                A.ntiles, A.ticket);
+    if constexpr (W <= kOnePassMaxW)
+        FILT_LAUNCH(FILT_BNAME("batched_onepass_fwd", W), kb_onepass_fwd<W>,
+                    dim3(onepass_grid(A.ntiles)), dim3(64), 0, st, A, x, a, yi, y);
+    else
+        FILT_LAUNCH(FILT_BNAME("batched_onepass_fwd", W), kb_onepass16_fwd,
+                    dim3(onepass_grid16(A.ntiles)), dim3(OnePass16::kThreads), 0, st, A, x, a, yi,
+                    y);
+    return check_launch("batched single-pass forward");
+}
+
+template <int W>
+filt_status onepass_backward(const filt_plan *p, int b, const float *gy, const float *y,
+                             const float *a, const float *yi, float *gx, float *ga, float *gyi,
+                             hipStream_t st)
+{
+    const OnePassArgs A = onepass_args(p, b, true);
+    FILT_LAUNCH("batched_onepass_reset", kb_onepass_reset, dim3(64), dim3(256), 0, st, A.flag,
+                A.ntiles, A.ticket);
+    if constexpr (W <= kOnePassMaxW)
+        FILT_LAUNCH(FILT_BNAME("batched_onepass_bwd", W), kb_onepass_bwd<W>,
+                    dim3(onepass_grid(A.ntiles)), dim3(64), 0, st, A, gy, a, y, yi, gx, ga, gyi);
+    else
+        FILT_LAUNCH(FILT_BNAME("batched_onepass_bwd", W), kb_onepass16_bwd,
+                    dim3(onepass_grid16(A.ntiles)), dim3(OnePass16::kThreads), 0, st, A, gy, a, y,
+                    yi, gx, ga, gyi);
+    return check_launch("batched single-pass backward");
+}
+
+// One bucket's forward: summaries, carry, apply.
+template <int W, int B>
+filt_status bucket_forward(const filt_plan *p, const float *x, const float *a, const float *yi,
+                           float *y, hipStream_t st)
+{
+    if (p->onepass[B])
+        return onepass_forward<W>(p, B, x, a, yi, y, st);
+    filt_status s = batched_fwd_summary<W>(bucket_args(p, B, a), x, a, p->d_ws, st);
+    if (s == FILT_OK)
+        s = carry_launch(p, B, 0, yi, st);
+    if (s != FILT_OK)
+        return s;
+    if constexpr (kStreamBucket<W>)
+        return batched_stream_fwd<W>(bucket_args(p, B, a), p->chunk[B], x, a, yi, p->d_ws, y, st);
+    return batched_fwd_apply<W>(bucket_args(p, B, a), x, a, yi, p->d_ws, y, st);
+}
+
+// One bucket's backward: summaries, carry, adjoint apply (+ coefficient
+// gradients).
+template <int W, int B>
+filt_status bucket_backward(const filt_plan *p, const float *gy, const float *y, const float *a,
+                            const float *yi, float *gx, float *ga, float *gyi, hipStream_t st)
+{
+    if (p->onepass[B])
+        return onepass_backward<W>(p, B, gy, y, a, yi, gx, ga, gyi, st);
+    filt_status s = batched_bwd_summary<W>(bucket_args(p, B, a), gy, a, p->d_ws, st);
+    if (s == FILT_OK)
+        s = carry_launch(p, B, 1, nullptr, st);
+    if (s != FILT_OK)
+        return s;
+    if (gx == nullptr)
+        return batched_bwd_apply<W>(bucket_args(p, B, a), gy, y, a, yi, p->d_ws, gx, ga, gyi, st);
+    if constexpr (kStreamBucket<W>)
+        return batched_stream_bwd<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx,
+                                     ga, gyi, st);
+    return batched_bwd_split<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx, ga,
+                                gyi, st);
+}
+
+// Does the plan have work in bucket b?
+bool bucket_busy(const filt_plan *p, int b)
+{
+    return p->sum_n[b] > 0 || p->app_n[b] > 0 || (p->onepass[b] && p->ntiles[b] > 0);
+}
+
+
+// Runs fn(b, stream) for every busy bucket in mask, each on its own stream
+// forked from st, the longest-running (highest order) first; st waits for
+// all of them.  With one busy bucket it runs on st directly.
+template <typename F>
+filt_status fork_buckets(const filt_plan *p, hipStream_t st, unsigned mask, F &&fn)
+{
+    int busy = 0;
+    for (int b = 0; b < kBuckets; ++b)
+        busy += ((mask >> b) & 1u) && bucket_busy(p, b);
+    if (busy <= 1 || p->fork == nullptr) {
+        filt_status s = FILT_OK;
+        for (int b = kBuckets - 1; b >= 0 && s == FILT_OK; --b)
+            if (((mask >> b) & 1u) && bucket_busy(p, b))
+                s = fn(b, st);
+        return s;
+    }
+    if (hipEventRecord(p->fork, st) != hipSuccess)
+        return fail(FILT_EHIP, "hipEventRecord (fork) failed");
+    filt_status s = FILT_OK;
+    for (int b = kBuckets - 1; b >= 0; --b) {
+        if (!(((mask >> b) & 1u) && bucket_busy(p, b)))
+            continue;
+        if (hipStreamWaitEvent(p->side[b], p->fork, 0) != hipSuccess)
+            return fail(FILT_EHIP, "hipStreamWaitEvent (fork) failed");
+        if (s == FILT_OK)
+            s = fn(b, p->side[b]);
+        // join even after a failed launch so a capture stays well formed
+        if (hipEventRecord(p->join[b], p->side[b]) != hipSuccess ||
+            hipStreamWaitEvent(st, p->join[b], 0) != hipSuccess)
+            return fail(FILT_EHIP, "event join of a bucket stream failed");
+    }
+    return s;
 }
 
 // The launch sequence of one direction, restricted to the buckets in mask.
 filt_status run_forward(const filt_plan *p, const float *x, const float *a, const float *yi,
                         float *y, hipStream_t st, unsigned mask = 0x1f)
 {
-    filt_status s = FILT_OK;
-#define FILT_BUCKETS(CALL)                                                                         \
-    if ((mask & 1u) && s == FILT_OK) s = CALL(1, 0);                                               \
-    if ((mask & 2u) && s == FILT_OK) s = CALL(2, 1);                                               \
-    if ((mask & 4u) && s == FILT_OK) s = CALL(4, 2);                                               \
-    if ((mask & 8u) && s == FILT_OK) s = CALL(8, 3);                                               \
-    if ((mask & 16u) && s == FILT_OK) s = CALL(16, 4);
-#define FWD_SUM(W, B) batched_fwd_summary<W>(bucket_args(p, B, a), x, a, p->d_ws, st)
-#define FWD_APP(W, B)                                                                              \
-    (kStreamBucket<W> ? batched_stream_fwd<W>(bucket_args(p, B, a), p->chunk[B], x, a, yi, p->d_ws, \
-                                              y, st)                                               \
-                      : batched_fwd_apply<W>(bucket_args(p, B, a), x, a, yi, p->d_ws, y, st))
-    FILT_BUCKETS(FWD_SUM)
-    if (s == FILT_OK)
-        s = carry_launch(p, 0, yi, st);
-    FILT_BUCKETS(FWD_APP)
-#undef FWD_SUM
-#undef FWD_APP
-    return s;
+    return fork_buckets(p, st, mask, [&](int b, hipStream_t s) -> filt_status {
+        switch (b) {
+        case 0: return bucket_forward<1, 0>(p, x, a, yi, y, s);
+        case 1: return bucket_forward<2, 1>(p, x, a, yi, y, s);
+        case 2: return bucket_forward<4, 2>(p, x, a, yi, y, s);
+        case 3: return bucket_forward<8, 3>(p, x, a, yi, y, s);
+        default: return bucket_forward<16, 4>(p, x, a, yi, y, s);
+        }
+    });
 }
 
 filt_status run_backward(const filt_plan *p, const float *gy, const float *y, const float *a,
                          const float *yi, float *gx, float *ga, float *gyi, hipStream_t st,
                          unsigned mask = 0x1f)
 {
-    filt_status s = FILT_OK;
-#define BWD_SUM(W, B) batched_bwd_summary<W>(bucket_args(p, B, a), gy, a, p->d_ws, st)
-#define BWD_APP(W, B)                                                                              \
-    (gx == nullptr                                                                                 \
-         ? batched_bwd_apply<W>(bucket_args(p, B, a), gy, y, a, yi, p->d_ws, gx, ga, gyi, st)       \
-     : kStreamBucket<W>                                                                            \
-         ? batched_stream_bwd<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx, ga,  \
-                                 gyi, st)                                                          \
-         : batched_bwd_split<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx, ga,   \
-                                gyi, st))
-    FILT_BUCKETS(BWD_SUM)
-    if (s == FILT_OK)
-        s = carry_launch(p, 1, nullptr, st);
-    FILT_BUCKETS(BWD_APP)
-#undef BWD_SUM
-#undef BWD_APP
-#undef FILT_BUCKETS
-    return s;
+    return fork_buckets(p, st, mask, [&](int b, hipStream_t s) -> filt_status {
+        switch (b) {
+        case 0: return bucket_backward<1, 0>(p, gy, y, a, yi, gx, ga, gyi, s);
+        case 1: return bucket_backward<2, 1>(p, gy, y, a, yi, gx, ga, gyi, s);
+        case 2: return bucket_backward<4, 2>(p, gy, y, a, yi, gx, ga, gyi, s);
+        case 3: return bucket_backward<8, 3>(p, gy, y, a, yi, gx, ga, gyi, s);
+        default: return bucket_backward<16, 4>(p, gy, y, a, yi, gx, ga, gyi, s);
+        }
+    });
 }
 
 filt_status check_plan(const filt_plan *p)
@@ -350,13 +564,24 @@ filt_status filt_plan_create(const filt_segment *segs, int32_t nseg, const int32
     filt_plan *p = new filt_plan();
     p->segs.assign(segs, segs + nseg);
     for (int b = 0; b < kBuckets; ++b) {
-        int64_t L = chunks != nullptr && chunks[b] > 0 ? chunks[b] : default_chunk(kBucketW[b]);
-        if (L % 32 != 0) {
+        const int32_t c = chunks != nullptr ? chunks[b] : 0;
+        if (c < -1 || (c > 0 && c % 32 != 0)) {
             delete p;
-            return fail(FILT_EINVAL, "chunk %lld for bucket %d is not a multiple of 32",
-                        (long long)L, b);
+            return fail(FILT_EINVAL,
+                        "chunk %d for bucket %d: -1 (single pass), 0 (default) or a positive "
+                        "multiple of 32",
+                        (int)c, b);
         }
-        p->chunk[b] = L;
+        p->chunk[b] = c > 0 ? c : default_chunk(kBucketW[b]);
+        p->onepass[b] = c < 0 || (c == 0 && kDefaultOnePass[b]);
+    }
+    bool ev_ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+    for (int b = 0; b < kBuckets && ev_ok; ++b)
+        ev_ok = hipStreamCreateWithFlags(&p->side[b], hipStreamNonBlocking) == hipSuccess &&
+                hipEventCreateWithFlags(&p->join[b], hipEventDisableTiming) == hipSuccess;
+    if (!ev_ok) {
+        filt_plan_destroy(p);
+        return fail(FILT_EHIP, "creating the plan's bucket streams failed");
     }
     const filt_status s = plan_layout(p);
     if (s != FILT_OK) {
@@ -372,6 +597,18 @@ void filt_plan_destroy(filt_plan *p)
     if (p == nullptr)
         return;
     drop_graph(p);
+    for (int b = 0; b < kBuckets; ++b) {
+        if (p->side[b] != nullptr)
+            hipStreamDestroy(p->side[b]);
+        if (p->join[b] != nullptr)
+            hipEventDestroy(p->join[b]);
+    }
+    if (p->fork != nullptr)
+        hipEventDestroy(p->fork);
+    if (p->d_tiles != nullptr)
+        hipFree(p->d_tiles);
+    if (p->d_flags != nullptr)
+        hipFree(p->d_flags);
     if (p->d_segs != nullptr)
         hipFree(p->d_segs);
     if (p->d_items != nullptr)
@@ -389,7 +626,7 @@ filt_status filt_plan_get_chunks(const filt_plan *p, int32_t *chunks)
     if (chunks == nullptr)
         return fail(FILT_EINVAL, "chunks is NULL");
     for (int b = 0; b < kBuckets; ++b)
-        chunks[b] = (int32_t)p->chunk[b];
+        chunks[b] = p->onepass[b] ? -1 : (int32_t)p->chunk[b];
     return FILT_OK;
 }
 
@@ -439,10 +676,15 @@ filt_status filt_plan_tune(filt_plan *p, const float *x, const float *a, const f
             continue;
         const int W = kBucketW[b];
         int64_t best = p->chunk[b];
+        bool best_one = p->onepass[b];
         float best_ms = 1e30f;
-        for (int64_t L : cands) {
-            if (L < 4 * W)
+        // candidate 0: the single-pass kernel (its tiles have a fixed
+        // length); then the three-phase scan at each chunk length
+        for (int ci = -1; ci < (int)(sizeof cands / sizeof cands[0]); ++ci) {
+            const int64_t L = ci < 0 ? p->chunk[b] : cands[ci];
+            if (ci >= 0 && L < 4 * W)
                 continue;
+            p->onepass[b] = ci < 0;
             p->chunk[b] = L;
             s = plan_layout(p);
             if (s != FILT_OK)
@@ -463,9 +705,11 @@ filt_status filt_plan_tune(filt_plan *p, const float *x, const float *a, const f
             if (med[1] < best_ms) {
                 best_ms = med[1];
                 best = L;
+                best_one = ci < 0;
             }
         }
         p->chunk[b] = best;
+        p->onepass[b] = best_one;
         if (s != FILT_OK)
             break;
     }

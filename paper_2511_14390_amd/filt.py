@@ -24,6 +24,7 @@ FILT_OK, FILT_EINVAL, FILT_EUNSUPPORTED, FILT_EWORKSPACE, FILT_EHIP = range(5)
 FILT_LAYOUT_TB, FILT_LAYOUT_BT = 0, 1
 FILT_F32_STATE = 0x2
 FILT_RECURRENCE = 0x4
+FILT_TOEPLITZ = 0x8
 
 
 class FiltProblem(ctypes.Structure):
@@ -90,7 +91,8 @@ def _layout_code(layout):
     raise ValueError("layout must be 'TB' or 'BT'")
 
 
-def problem(x, a, b=None, layout="BT", chunk=0, f32_state=False, recurrence=False):
+def problem(x, a, b=None, layout="BT", chunk=0, f32_state=False, recurrence=False,
+            toeplitz=False):
     """Build the filt_problem for these tensors (shapes checked here)."""
     if x.dim() != 2:
         raise ValueError("x must be 2-D")
@@ -104,7 +106,8 @@ def problem(x, a, b=None, layout="BT", chunk=0, f32_state=False, recurrence=Fals
         want = (B, K) if not tv else ((T, B, K) if layout == "TB" else (B, T, K))
         if tuple(c.shape) != want:
             raise ValueError(f"coefficient shape {tuple(c.shape)} != {want}")
-    flags = (FILT_F32_STATE if f32_state else 0) | (FILT_RECURRENCE if recurrence else 0)
+    flags = ((FILT_F32_STATE if f32_state else 0) | (FILT_RECURRENCE if recurrence else 0)
+             | (FILT_TOEPLITZ if toeplitz else 0))
     p = FiltProblem(B, T, M, N, int(tv), _layout_code(layout), flags, int(chunk))
     return p
 
@@ -142,7 +145,7 @@ def _stream(device, stream):
 
 
 def filt_forward(x, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0, f32_state=False,
-                 recurrence=False, out=None, ws=None, stream=None):
+                 recurrence=False, toeplitz=False, out=None, ws=None, stream=None):
     """y = direct-form filter of x (see include/filt.h).  Returns y."""
     dev, dt = x.device, x.dtype
     if dt not in (torch.float32, torch.float64):
@@ -151,7 +154,7 @@ def filt_forward(x, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0, f32_st
         raise ValueError("filt_forward runs on the GPU only")
     x = x.contiguous()
     a, b, xi, yi = (_prep(t, dt, dev, n) for t, n in ((a, "a"), (b, "b"), (xi, "xi"), (yi, "yi")))
-    p = problem(x, a, b, layout, chunk, f32_state, recurrence)
+    p = problem(x, a, b, layout, chunk, f32_state, recurrence, toeplitz)
     y = out if out is not None else torch.empty_like(x)
     ws, need = _workspace(p, dev, ws)
     fn = lib().filt_forward_f64 if dt == torch.float64 else lib().filt_forward
@@ -161,8 +164,8 @@ def filt_forward(x, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0, f32_st
 
 
 def filt_backward(gy, x, y, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0,
-                  f32_state=False, recurrence=False, want=("x", "a", "b", "xi", "yi"), ws=None,
-                  stream=None):
+                  f32_state=False, recurrence=False, toeplitz=False,
+                  want=("x", "a", "b", "xi", "yi"), ws=None, stream=None):
     """Closed-form gradients (see include/filt.h).  Returns a dict with the
     requested keys among x, a, b, xi, yi (b only if b was given; xi / yi
     always have shapes [B, M] / [B, N])."""
@@ -172,19 +175,13 @@ def filt_backward(gy, x, y, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0
     gy = gy.contiguous()
     x, y, a, b, xi, yi = (_prep(t, dt, dev, n) for t, n in
                           ((x, "x"), (y, "y"), (a, "a"), (b, "b"), (xi, "xi"), (yi, "yi")))
-    p = problem(gy, a, b, layout, chunk, f32_state, recurrence)
+    p = problem(gy, a, b, layout, chunk, f32_state, recurrence, toeplitz)
     B, M, N = p.B, p.M, p.N
     gx = torch.empty_like(gy) if "x" in want else None
     ga = torch.empty_like(a) if ("a" in want and a is not None and N > 0) else None
     gb = torch.empty_like(b) if ("b" in want and b is not None) else None
     gxi = torch.empty((B, M), dtype=dt, device=dev) if "xi" in want else None
     gyi = torch.empty((B, N), dtype=dt, device=dev) if "yi" in want else None
-    if p.T == 0:
-        out = {}
-        for k, v in (("x", gx), ("a", ga), ("b", gb), ("xi", gxi), ("yi", gyi)):
-            if v is not None:
-                out[k] = v.zero_()
-        return out
     ws, need = _workspace(p, dev, ws)
     fn = lib().filt_backward_f64 if dt == torch.float64 else lib().filt_backward
     _check(fn(ctypes.byref(p), _ptr(gy), _ptr(x), _ptr(y), _ptr(b), _ptr(a), _ptr(xi), _ptr(yi),

@@ -186,5 +186,33 @@ def test_plan_create_rejects_bad_segments_on_host(L):
     assert L.filt_plan_create(bad_len, 1, None, ctypes.byref(h)) == F.FILT_EINVAL
     bad_chunk = (ctypes.c_int32 * 5)(48, 64, 64, 64, 64)
     ok = (F.FiltSegment * 1)(F.FiltSegment(0, 100, 0, 0, 2, 0))
+    assert L.filt_plan_create(ok, 1, (ctypes.c_int32 * 5)(-2, 64, 64, 64, 64),
+                              ctypes.byref(h)) == F.FILT_EINVAL
+    ok = (F.FiltSegment * 1)(F.FiltSegment(0, 100, 0, 0, 2, 0))
     assert L.filt_plan_create(ok, 1, bad_chunk, ctypes.byref(h)) == F.FILT_EINVAL
     assert L.filt_plan_create(ok, 1, None, None) == F.FILT_EINVAL
+
+
+def test_empty_backward_is_ok_on_host(L):
+    # B == 0, or T == 0 with no per-channel gradient requested: nothing to
+    # write and nothing launched (T == 0 with gxi / gyi / ga / gb zero-fills
+    # them on the stream; that case runs in the GPU tests)
+    for kw in (dict(B=0), dict(T=0)):
+        p = _prob(M=1, **kw)
+        rc = L.filt_backward(ctypes.byref(p), *([None] * 12), None, ctypes.c_size_t(0), None)
+        assert rc == F.FILT_OK, kw
+    p = _prob(B=0, T=0, M=1)
+    fake = ctypes.c_void_p(0x1000)  # B == 0: never touched
+    rc = L.filt_backward(ctypes.byref(p), *([fake] * 12), None, ctypes.c_size_t(0), None)
+    assert rc == F.FILT_OK
+
+
+def test_plan_api_is_all_pole_per_sample(L):
+    # the batched plan covers filters with b = [1] (M = 0) and per-sample
+    # coefficients only: its segment descriptor has no FIR order and the plan
+    # calls take no b / xi / gb / gxi
+    F._plan_lib()
+    fields = [f[0] for f in F.FiltSegment._fields_]
+    assert fields == ["x_off", "T", "a_off", "ic_off", "N", "reserved"]
+    assert len(L.filt_plan_forward.argtypes) == 6
+    assert len(L.filt_plan_backward.argtypes) == 9

@@ -83,8 +83,9 @@ def test_batched_short_empty_and_passthrough_segments(gpu_device):
     s = W.Segments(T, N, x_off, a_off, ic_off, rng.standard_normal(int(T.sum())).astype(np.float32),
                    a, rng.normal(0, 0.1, int(N.sum())).astype(np.float32),
                    rng.standard_normal(int(T.sum())).astype(np.float32))
-    _, _, y, g = _run_plan(s, gpu_device, chunks=[32, 32, 32, 64, 64])
-    _check_segments(s, y, g, TIGHT, which=[0, 2, 3, 4, 5])
+    for chunks in ([32, 32, 32, 64, 64], [-1, -1, -1, -1, -1]):
+        _, _, y, g = _run_plan(s, gpu_device, chunks=chunks)
+        _check_segments(s, y, g, TIGHT, which=[0, 2, 3, 4, 5])
 
 
 def test_batched_equals_dense_per_filter_calls(gpu_device):
@@ -94,7 +95,7 @@ def test_batched_equals_dense_per_filter_calls(gpu_device):
     for i in range(len(s.T)):
         t, n = int(s.T[i]), int(s.N[i])
         xo, ao, io = int(s.x_off[i]), int(s.a_off[i]), int(s.ic_off[i])
-        L = chunks[max(n - 1, 0).bit_length()]
+        L = max(chunks[max(n - 1, 0).bit_length()], 0)  # -1: single pass, dense auto chunk
         xs = x[xo:xo + t][None]
         as_ = a[ao:ao + t * n].view(1, t, n)
         yis = yi[io:io + n][None]
@@ -137,8 +138,82 @@ def test_autotuner_picks_valid_chunks_and_stays_exact(gpu_device):
     plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off)
     chunks = plan.tune(x, a, yi, gy)
     print(f"[batched] tuned chunks {chunks}", flush=True)
-    assert all(c >= 32 and c % 32 == 0 for c in chunks)
+    # -1: the single-pass kernel; else the three-phase scan's chunk length
+    assert all(c == -1 or (c >= 32 and c % 32 == 0) for c in chunks)
     y = plan.forward(x, a, yi)
     g = plan.backward(gy, y, a, yi)
     torch.cuda.synchronize()
     _check_segments(s, y, g, TIGHT)
+
+
+def _check_segments_threaded(s, y, g, tol, label):
+    """Per-segment comparison with the oracle, segments spread over host
+    threads (the oracle's C calls release the interpreter lock)."""
+    import concurrent.futures as cf
+    import os
+
+    y = y.cpu().numpy()
+    gx, ga, gyi = (g[k].cpu().numpy() for k in ("x", "a", "yi"))
+
+    def one(i):
+        t, n = int(s.T[i]), int(s.N[i])
+        xo, ao, io = int(s.x_off[i]), int(s.a_off[i]), int(s.ic_off[i])
+        yo, go = _oracle_segment(s, i)
+        e = [chan_rel_err(y[xo:xo + t][None], yo[None], "BT"),
+             chan_rel_err(gx[xo:xo + t][None], go["x"], "BT")]
+        if n > 0:
+            e.append(chan_rel_err(ga[ao:ao + t * n].reshape(1, t, n), go["a"], "BT"))
+            e.append(vec_rel_err(gyi[io:io + n][None], go["yi"]))
+        return i, t, n, max(e)
+
+    with cf.ThreadPoolExecutor(min(16, len(os.sched_getaffinity(0)))) as ex:
+        res = list(ex.map(one, range(len(s.T))))
+    worst = max(r[3] for r in res)
+    print(f"[batched] {label}: {len(s.T)} segments, worst rel err {worst:.2e}", flush=True)
+    bad = [r for r in res if r[3] > tol]
+    assert not bad, bad[:5]
+
+
+def test_batched_full_size_workload_per_segment(gpu_device):
+    # the benchmark's workload at full size: 512 segments, T up to 200 000
+    # (order-16 carries over about 520 chunks stage their records in several
+    # rounds), with the chunk lengths the tuner picks on the device
+    s = W.config5()
+    x, a, yi, gy = _to(gpu_device, s.x, s.a, s.yi, s.gy)
+    plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off)
+    chunks = plan.tune(x, a, yi, gy)
+    y = plan.forward(x, a, yi)
+    g = plan.backward(gy, y, a, yi)
+    torch.cuda.synchronize()
+    _check_segments_threaded(s, y, g, TIGHT, f"full size, chunks {chunks}")
+
+
+@pytest.mark.parametrize("chunks", [[192, 192, 192, 192, 192], [64, 64, 128, 128, 384],
+                                    [-1, -1, -1, -1, -1], [-1, 128, -1, 256, -1]])
+def test_batched_long_order16_segment(gpu_device, chunks):
+    # an order-16 segment of 200 000 samples among shorter ones of every
+    # order: about 1042 chunks at 192 (G = NB = 33) and 521 at 384
+    T = np.array([200000, 150001, 3000, 70000, 99999, 1000], dtype=np.int64)
+    N = np.array([16, 8, 16, 4, 2, 1], dtype=np.int32)
+    s = _packed(T, N, seed=21)
+    _, _, y, g = _run_plan(s, gpu_device, chunks=chunks)
+    _check_segments_threaded(s, y, g, TIGHT, f"long order 16, chunks {chunks}")
+
+
+def _packed(T, N, seed, hop=128):
+    rng = np.random.default_rng(seed)
+    x_off = np.concatenate([[0], np.cumsum(T)[:-1]]).astype(np.int64)
+    a_len = (T * N + 3) // 4 * 4
+    a_off = np.concatenate([[0], np.cumsum(a_len)[:-1]]).astype(np.int64)
+    ic_off = np.concatenate([[0], np.cumsum(N)[:-1]]).astype(np.int64)
+    a = np.zeros(int(a_len.sum()), np.float32)
+    for i in range(len(T)):
+        t, n = int(T[i]), int(N[i])
+        if t and n:
+            k = rng.uniform(-0.9, 0.9, (-(-t // hop), n))
+            frames = W.bandwidth_expand(W.reflection_to_direct(k), 0.99)
+            a[a_off[i]:a_off[i] + t * n] = W.frame_held(frames, t, hop, 0).reshape(-1)
+    return W.Segments(T, N, x_off, a_off, ic_off,
+                      rng.standard_normal(int(T.sum())).astype(np.float32), a,
+                      rng.normal(0, 0.1, int(N.sum())).astype(np.float32),
+                      rng.standard_normal(int(T.sum())).astype(np.float32))

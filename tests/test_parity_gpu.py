@@ -25,13 +25,13 @@ def _dev(v, dev, dtype=torch.float32):
 
 
 def run_gpu(p, dev, chunk=0, f32_state=False, dtype=torch.float32,
-            want=("x", "a", "b", "xi", "yi"), recurrence=False):
+            want=("x", "a", "b", "xi", "yi"), recurrence=False, toeplitz=False):
     t = lambda v: _dev(v, dev, dtype)
     x, a, b, xi, yi, gy = map(t, (p.x, p.a, p.b, p.xi, p.yi, p.gy))
     y = F.filt_forward(x, a, b, xi, yi, layout=p.layout, chunk=chunk, f32_state=f32_state,
-                       recurrence=recurrence)
+                       recurrence=recurrence, toeplitz=toeplitz)
     g = F.filt_backward(gy, x, y, a, b, xi, yi, layout=p.layout, chunk=chunk,
-                        f32_state=f32_state, recurrence=recurrence, want=want)
+                        f32_state=f32_state, recurrence=recurrence, toeplitz=toeplitz, want=want)
     torch.cuda.synchronize()
     return y.cpu().numpy(), {k: v.cpu().numpy() for k, v in g.items()}
 
@@ -199,3 +199,107 @@ def test_fp64_io_path_matches_oracle_tightly(gpu_device):
     yg, gg = run_gpu(p, gpu_device, dtype=torch.float64, chunk=64)
     yo, go = run_oracle(p)
     compare(p, yg, gg, yo, go, out_tol=1e-10, grad_tol=1e-9, label="f64")
+
+
+# ---------------------------------------------------------------------------
+# The exact forms the benchmark and the batched plan run, and the hard inputs
+
+
+@pytest.mark.parametrize("layout,chunk", [("TB", 256), ("BT", 192)])
+def test_config2_full_bench_forms(gpu_device, layout, chunk):
+    # config 2 as timed: per-sample order 16, no b, no initial conditions,
+    # [T, B] at chunk 256 (the quad adjoint forms ga itself) and [B, T] at 192
+    p = W.config2()
+    if layout == "TB":
+        sw = lambda v: np.ascontiguousarray(np.swapaxes(v, 0, 1))
+        p = W.Problem(p.name, "TB", sw(p.x), sw(p.a), None, None, None, sw(p.gy), dict(p.meta))
+    yg, gg = run_gpu(p, gpu_device, chunk=chunk, want=("x", "a"))
+    yo, go = run_oracle(p, nthreads=16)
+    compare(p, yg, gg, yo, go, label=f"config2 {layout} chunk={chunk}")
+
+
+@pytest.mark.parametrize("N,layout,chunk,T", [(16, "TB", 256, 1100), (12, "TB", 96, 1000),
+                                              (12, "BT", 96, 1000), (16, "BT", 192, 900)])
+def test_per_sample_order_9_16_without_b_with_yi(gpu_device, N, layout, chunk, T):
+    # per-sample orders 9..16 without b take the quad adjoint that forms the
+    # ga rows itself; with initial conditions (gyi and ga's first rows)
+    p = W.random_problem(5000 + N + T, B=6, T=T, M=0, N=N, time_varying=True, layout=layout,
+                         hop=16, rho_max=0.99, with_b=False)
+    yg, gg = run_gpu(p, gpu_device, chunk=chunk, want=("x", "a", "yi"))
+    yo, go = run_oracle(p)
+    compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6, label=f"quad-ga chunk={chunk}")
+
+
+@pytest.mark.parametrize("layout", ["TB", "BT"])
+def test_fp64_io_order16_quad_path(gpu_device, layout):
+    p = W.random_problem(5100, B=4, T=1000, M=0, N=16, time_varying=True, layout=layout,
+                         hop=16, rho_max=0.99, with_b=False)
+    yg, gg = run_gpu(p, gpu_device, dtype=torch.float64, chunk=256 if layout == "TB" else 192,
+                     want=("x", "a", "yi"))
+    yo, go = run_oracle(p)
+    compare(p, yg, gg, yo, go, out_tol=1e-9, grad_tol=1e-9, label="f64 order-16")
+
+
+@pytest.mark.parametrize("layout", ["TB", "BT"])
+def test_order16_long_signal_multi_round_carry(gpu_device, layout):
+    # T = 200 000 at chunk 192: about 1042 chunks, carry blocks G = NB = 33, so
+    # the carry stages its 272-double step records in several rounds of 16
+    p = W.random_problem(5200, B=2, T=200000, M=0, N=16, time_varying=True, layout=layout,
+                         hop=128, rho_max=0.99, with_b=False)
+    yg, gg = run_gpu(p, gpu_device, chunk=192, want=("x", "a", "yi"))
+    yo, go = run_oracle(p)
+    compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6, label="order-16 long")
+
+
+SWEEP = [(M, N, tv, layout, T, chunk) for (M, N, tv, layout, T, chunk) in CASES if tv]
+
+
+RHO_LADDER = (0.99, 0.95, 0.9, 0.8, 0.7, 0.6, 0.5)
+BOUND = 1e6
+
+
+def bounded_case(seed, B, T, M, N, layout, hop):
+    """The largest frozen-time pole radius of the ladder whose time-varying
+    system stays bounded over the test (oracle |y| and |gx| below BOUND).
+    Frames of every-sample coefficients with poles near the unit circle make
+    the time-varying system grow without bound even though every frozen frame
+    is stable (|y| reaches 1e84 for order 8 at radius 0.99); such outputs
+    leave the FP32 range, so no relative error exists for them."""
+    for rho in RHO_LADDER:
+        p = W.random_problem(seed, B=B, T=T, M=M, N=N, time_varying=True, layout=layout, hop=hop,
+                             rho_max=rho)
+        yo, go = run_oracle(p)
+        if max(np.abs(yo).max(), np.abs(go["x"]).max()) < BOUND:
+            return p, rho, yo, go
+    raise AssertionError("no bounded case on the ladder")
+
+
+@pytest.mark.parametrize("hop", [16, 1])
+@pytest.mark.parametrize("M,N,tv,layout,T,chunk", SWEEP)
+def test_per_sample_sweep_radius_099(gpu_device, M, N, tv, layout, T, chunk, hop):
+    # frozen-time pole radius up to 0.99 (down the ladder only where the
+    # time-varying system would grow without bound) with frames of 16 samples
+    # and with coefficients that change every sample, on the default
+    # FP64-state path
+    p, rho, yo, go = bounded_case(6000 + 31 * M + 7 * N + T + hop, 5, T, M, N, layout, hop)
+    yg, gg = run_gpu(p, gpu_device, chunk=chunk)
+    compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6,
+            label=f"r{rho} hop={hop} chunk={chunk}")
+
+
+def test_backward_with_no_samples_zero_fills_per_channel_grads(gpu_device):
+    # T == 0: nothing depends on the initial conditions or the coefficients
+    dev = gpu_device
+    B, M, N = 3, 2, 4
+    x = torch.empty(B, 0, device=dev)
+    a = torch.randn(B, N, device=dev)
+    b = torch.randn(B, M + 1, device=dev)
+    xi = torch.randn(B, M, device=dev)
+    yi = torch.randn(B, N, device=dev)
+    y = F.filt_forward(x, a, b, xi, yi)
+    assert y.shape == (B, 0)
+    g = F.filt_backward(torch.empty(B, 0, device=dev), x, y, a, b, xi, yi)
+    torch.cuda.synchronize()
+    for k in ("a", "b", "xi", "yi"):
+        assert torch.count_nonzero(g[k]).item() == 0, k
+    assert g["x"].shape == (B, 0)
