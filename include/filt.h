@@ -117,6 +117,19 @@ filt_status filt_backward(const filt_problem *p, const float *gy, const float *x
                           float *gx, float *gb, float *ga, float *gxi, float *gyi, void *ws,
                           size_t ws_bytes, void *stream);
 
+/* filt_forward without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Arguments as filt_forward.  The workspace is a
+ * static device array of the library (64 MiB on every device it runs on,
+ * held until the process ends); the call allocates nothing.  Problems whose
+ * workspace (filt_workspace_bytes) exceeds 64 MiB are rejected on the host
+ * with FILT_EWORKSPACE.  Every call on one device shares that array and
+ * leaves its contents behind: calls that overlap on one device (concurrent
+ * streams, or threads) race and must be serialised by the caller. */
+filt_status filt_forward_noalloc(const filt_problem *p, const float *x, const float *b,
+                                 const float *a, const float *xi, const float *yi, float *y,
+                                 void *stream);
+
 /* The same two operations on FP64 data, computed in FP64 (for numerical
  * gradient checks).  Arguments as above with double in place of float. */
 filt_status filt_forward_f64(const filt_problem *p, const double *x, const double *b,

@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "common.h"
 
@@ -325,12 +326,68 @@ filt_status backward_entry(const filt_problem *p, const io_t *gy, const io_t *x,
 }
 
 
+// ------------------------------------------------------------ static scratch
+//
+// filt_forward_noalloc runs the forward with its workspace in this array
+// instead of a caller buffer.  Every device the library runs on holds its
+// own copy from module load until the process ends.  In host code `scratch`
+// only names the symbol: its device address is looked up once per device
+// (with that device current) and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+filt_status scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(FILT_EHIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(FILT_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(FILT_EHIP, "hipGetSymbolAddress of the static scratch failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FILT_OK;
+}
+
 }  // namespace filt_detail
 
 using namespace filt_detail;
 
 
 extern "C" {
+
+filt_status filt_forward_noalloc(const filt_problem *p, const float *x, const float *b,
+                                 const float *a, const float *xi, const float *yi, float *y,
+                                 void *stream)
+{
+    filt_status s = validate(p, x, b, a);
+    if (s != FILT_OK)
+        return s;
+    if (p->B == 0 || p->T == 0)
+        return FILT_OK;
+    // the workspace this problem needs, with the 256-byte alignment margin
+    const size_t need = ws_plan(make_dims(p, b != nullptr, true)).total;
+    if (need > kScratchBytes)
+        return fail(FILT_EWORKSPACE,
+                    "problem needs %zu bytes of workspace, the static scratch holds %zu "
+                    "(use filt_forward with a caller workspace)",
+                    need, kScratchBytes);
+    void *ws = nullptr;
+    s = scratch_of_current_device(&ws);
+    if (s != FILT_OK)
+        return s;
+    return forward_entry<float>(p, x, b, a, xi, yi, y, ws, kScratchBytes, stream);
+}
 
 filt_status filt_workspace_bytes(const filt_problem *p, size_t *bytes)
 {
