@@ -341,67 +341,134 @@ inline void persistent_grid(int64_t n, unsigned &blocks, unsigned &threads)
     blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
 }
 
-// Order-16 bucket: summaries on DPP rows (summary.h).  Items are (seg,
-// chunk), kRowGroupChunks of them per workgroup: waves 0-3 one 16-lane row per
-// item, wave 4 the items' particular solves (a quad each).  Every segment of
-// the bucket has the same chunk length, so the rows of a wave run in step.
-// FULL: every segment has order 16 and 16-byte aligned rows.
+// Order-16 bucket summaries by duality, one 16-lane DPP row per chunk and
+// no driven solve (sixteen chunks per 256-thread workgroup, no LDS, no
+// barriers).  Forward: row lane i runs the adjoint solve seeded with
+// s_{i+1} = 1 at the chunk's end (the cotangent of the state component i
+// leaving the chunk); its adjoint state at the chunk's start is row i of
+// Phi_c, and sum_t ybar_i[t] x[t] is s_c[i].  Adjoint: row lane j runs the
+// forward solve from the unit state e_j; its final state is row j of the
+// chunk's adjoint map (Phi_c transposed) and sum_t gy[t] y_j[t] is that
+// map's driven part.  Coefficients and the signal are read 16 steps ahead.
 template <bool FULL>
-__global__ void __launch_bounds__(kRowGroupThreads, 5)
-kb_fwd_summary_rows(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+__global__ void __launch_bounds__(256)
+kb_fwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
                     const float *__restrict__ x, const float *__restrict__ a,
                     double *__restrict__ ws)
 {
-    __shared__ float hand[2][kHandSteps][16][16];
-    const int t = threadIdx.x;
-    const int k = t >= 16 * kRowGroupChunks ? (t - 16 * kRowGroupChunks) >> 2 : t >> 4;
-    // every thread of the workgroup takes the same passes (the group holds
-    // barriers); a lane past the end works on the last item and stores nothing
-    for (int64_t first = (int64_t)blockIdx.x * kRowGroupChunks; first < n;
-         first += (int64_t)gridDim.x * kRowGroupChunks) {
-        const bool act = first + k < n;
-        const Item it = items[act ? first + k : n - 1];
-        const SegDesc sd = segs[it.seg];
-        fwd_rows_group<FULL, false>(seg_dims(sd), x + sd.x_off, (const float *)nullptr,
-                                    a + sd.a_off, ws + sd.summ_off, 0, it.chunk, act, hand);
-    }
-}
-
-template <bool FULL>
-__global__ void __launch_bounds__(kRowGroupThreads, 5)
-kb_bwd_summary_rows(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
-                    const float *__restrict__ gy, const float *__restrict__ a,
-                    double *__restrict__ ws)
-{
-    const int t = threadIdx.x;
-    for (int64_t first = (int64_t)blockIdx.x * kRowGroupChunks; first < n;
-         first += (int64_t)gridDim.x * kRowGroupChunks) {
-        const int k = t >= 16 * kRowGroupChunks ? (t - 16 * kRowGroupChunks) >> 2 : t >> 4;
-        if (first + k >= n)
-            continue;
-        const Item it = items[first + k];
+    const int row = threadIdx.x >> 4, j = threadIdx.x & 15;
+    for (int64_t first = (int64_t)blockIdx.x * 16; first < n; first += (int64_t)gridDim.x * 16) {
+        const int64_t g = first + row;
+        if (g >= n)
+            continue;  // the whole row: its DPP broadcasts stay inside it
+        const Item it = items[g];
         const SegDesc sd = segs[it.seg];
         const Dims d = seg_dims(sd);
-        const int64_t c = it.chunk + 1;  // chunks 1..C-1 pass a state to an earlier chunk
-        if (t >= 16 * kRowGroupChunks) {
-            if ((c + 1) * d.L > d.T)
-                bwd_part_quad<FULL, true>(d, gy + sd.x_off, a + sd.a_off, ws + sd.summ_off, 0, c,
-                                          t & 3);
-            else
-                bwd_part_quad<FULL, false>(d, gy + sd.x_off, a + sd.a_off, ws + sd.summ_off, 0, c,
-                                           t & 3);
-        } else {
-            bwd_row_item<FULL>(d, a + sd.a_off, ws + sd.summ_off, 0, c, t & 15);
+        const int64_t c = it.chunk;  // chunks 0..C-2 are whole
+        const RowCoef<float, FULL> rc = row_coef<float, FULL>(d, a + sd.a_off, 0, c, j);
+        const float *xp = x + sd.x_off + c * d.L;
+        const int L = (int)d.L;
+        double ss[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            ss[e] = (rc.live && e == ((j + 2) & 15)) ? 1.0 : 0.0;
+        float cb[16], xb[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            cb[s] = rc.p[(int64_t)(L - 16 + s) * rc.stride];
+            xb[s] = xp[L - 16 + s];
+        }
+        double acc = 0.0;
+        for (int rel = L - 16; rel >= 0; rel -= 16) {
+            static_for<16>([&](auto I) {
+                constexpr int s = 15 - decltype(I)::value;
+                const double cf = rc.cvt(cb[s]);
+                const double xv = (double)xb[s];
+                const int nx = max(rel - 16 + s, 0);
+                cb[s] = rc.p[(int64_t)nx * rc.stride];
+                xb[s] = xp[nx];
+                acc = __builtin_fma(ss[(1 - s) & 15], xv, acc);
+                row_bwd_step<s>(cf, ss);
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        }
+        if (rc.live) {
+            const int N = d.N;
+            double *o = ws + sd.summ_off + c * ((int64_t)N * N + N);
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < N)
+                    o[j * N + i] = ss[(i + 2) & 15];
+            o[(int64_t)N * N + j] = acc;
         }
     }
 }
 
-// Workgroups for the row summaries: one per kRowGroupChunks items, at most
-// four per CU (five waves each, all resident).
-inline unsigned row_groups(int64_t n)
+template <bool FULL>
+__global__ void __launch_bounds__(256)
+kb_bwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
+                    const float *__restrict__ gy, const float *__restrict__ a,
+                    double *__restrict__ ws)
 {
-    const int64_t want = (n + kRowGroupChunks - 1) / kRowGroupChunks;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kCUs * 4));
+    const int row = threadIdx.x >> 4, j = threadIdx.x & 15;
+    for (int64_t first = (int64_t)blockIdx.x * 16; first < n; first += (int64_t)gridDim.x * 16) {
+        const int64_t g = first + row;
+        if (g >= n)
+            continue;
+        const Item it = items[g];
+        const SegDesc sd = segs[it.seg];
+        const Dims d = seg_dims(sd);
+        const int64_t c = it.chunk + 1;  // chunks 1..C-1 pass a state to an earlier chunk
+        const RowCoef<float, FULL> rc = row_coef<float, FULL>(d, a + sd.a_off, 0, c, j);
+        const float *gp = gy + sd.x_off + c * d.L;
+        const int L = (int)d.L;
+        // a last chunk cut short by the signal's end: steps past T take zero
+        // coefficients and zero gy (reads clamped to its last sample)
+        const int valid = (int)min<int64_t>(d.L, d.T - c * d.L);
+        double h[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            h[e] = (rc.live && e == ((-1 - j) & 15)) ? 1.0 : 0.0;
+        float cb[16], gb[16];
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int r = min(s, valid - 1);
+            cb[s] = rc.p[(int64_t)r * rc.stride];
+            gb[s] = gp[r];
+        }
+        double acc = 0.0;
+        for (int rel = 0; rel < L; rel += 16) {
+            static_for<16>([&](auto I) {
+                constexpr int s = decltype(I)::value;
+                const bool in = rel + s < valid;
+                const double cf = in ? rc.cvt(cb[s]) : 0.0;
+                const double gv = in ? (double)gb[s] : 0.0;
+                const int nx = min(rel + 16 + s, valid - 1);
+                cb[s] = rc.p[(int64_t)nx * rc.stride];
+                gb[s] = gp[nx];
+                h[s] = row_fwd_step<s>(cf, h);
+                acc = __builtin_fma(gv, h[s], acc);
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        }
+        if (rc.live) {
+            const int N = d.N;
+            double *o = ws + sd.summ_off + c * ((int64_t)N * N + N);
+            // a chunk cut short only ever sees a zero state from above
+            const bool whole = valid == L;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < N)
+                    o[j * N + i] = whole ? h[15 - i] : 0.0;
+            o[(int64_t)N * N + j] = acc;
+        }
+    }
+}
+
+inline unsigned dual_groups(int64_t n)
+{
+    const int64_t want = (n + 15) / 16;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, kCUs * 8));
 }
 
 // Launch names carry the order bucket ("..._w16"), so per-kernel timings
@@ -428,12 +495,13 @@ filt_status batched_fwd_summary(const BucketArgs &b, const float *x, const float
         return FILT_OK;
     if constexpr (W == 16) {
         if (b.av)
-            FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), kb_fwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
-                        dim3(kRowGroupThreads), 0, st, b.segs, b.sum_items, b.sum_n, x, a, ws);
+            FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), kb_fwd_summary_dual<true>,
+                        dim3(dual_groups(b.sum_n)), dim3(256), 0, st, b.segs, b.sum_items, b.sum_n,
+                        x, a, ws);
         else
-            FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), kb_fwd_summary_rows<false>,
-                        dim3(row_groups(b.sum_n)), dim3(kRowGroupThreads), 0, st, b.segs,
-                        b.sum_items, b.sum_n, x, a, ws);
+            FILT_LAUNCH(FILT_BNAME("batched_fwd_summary", W), kb_fwd_summary_dual<false>,
+                        dim3(dual_groups(b.sum_n)), dim3(256), 0, st, b.segs, b.sum_items, b.sum_n,
+                        x, a, ws);
         return check_launch("batched forward summary");
     }
     unsigned g, t;
@@ -455,12 +523,13 @@ filt_status batched_bwd_summary(const BucketArgs &b, const float *gy, const floa
         return FILT_OK;
     if constexpr (W == 16) {
         if (b.av)
-            FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), kb_bwd_summary_rows<true>, dim3(row_groups(b.sum_n)),
-                        dim3(kRowGroupThreads), 0, st, b.segs, b.sum_items, b.sum_n, gy, a, ws);
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), kb_bwd_summary_dual<true>,
+                        dim3(dual_groups(b.sum_n)), dim3(256), 0, st, b.segs, b.sum_items, b.sum_n,
+                        gy, a, ws);
         else
-            FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), kb_bwd_summary_rows<false>,
-                        dim3(row_groups(b.sum_n)), dim3(kRowGroupThreads), 0, st, b.segs,
-                        b.sum_items, b.sum_n, gy, a, ws);
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_summary", W), kb_bwd_summary_dual<false>,
+                        dim3(dual_groups(b.sum_n)), dim3(256), 0, st, b.segs, b.sum_items, b.sum_n,
+                        gy, a, ws);
         return check_launch("batched backward summary");
     }
     unsigned g, t;

@@ -208,11 +208,15 @@ filt_status plan_layout(filt_plan *p)
         for (int b = 0; b < kBuckets; ++b) {
             if (!p->onepass[b])
                 continue;
-            // orders up to 4: one wavefront per tile of 64 x 16 samples, maps of
+            // orders up to 4: one wavefront per tile of 64 lanes x 32 (orders 1, 2)
+            // or 16 (order 4) samples, maps of
             // W x W; orders 5..16: one workgroup per tile of 16 x 32 samples,
             // maps of 16 x 16
             const int W = kBucketW[b] <= kOnePassMaxW ? kBucketW[b] : 16;
-            const int64_t S = kBucketW[b] <= kOnePassMaxW ? 64 * 16 : OnePass16::S;
+            const int64_t S = kBucketW[b] == 1   ? OnePass<1>::S
+                              : kBucketW[b] == 2 ? OnePass<2>::S
+                              : kBucketW[b] == 4 ? OnePass<4>::S
+                                                 : OnePass16::S;
             int64_t nt = 0, maxt = 0;
             for (int i = 0; i < nseg; ++i) {
                 if (bucket_of(std::max(p->segs[i].N, 1)) != b)
@@ -380,7 +384,7 @@ OnePassArgs onepass_args(const filt_plan *p, int b, bool bwd)
 // ticket counter past the end and leave.
 unsigned onepass_grid(int64_t ntiles)
 {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, kCUs * 8));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, kCUs * 16));
 }
 
 unsigned onepass_grid16(int64_t ntiles)

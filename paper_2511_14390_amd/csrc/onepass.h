@@ -39,7 +39,7 @@ namespace filt_detail {
 
 template <int W>
 struct OnePass {
-    static constexpr int L = 16;               // samples per lane (sub-chunk)
+    static constexpr int L = W <= 2 ? 32 : 16; // samples per lane (sub-chunk)
     static constexpr int S = 64 * L;           // samples per tile
     static constexpr int XS = L + 1;           // LDS floats per lane, signal
     static constexpr int YS = W + L + 1;       // LDS floats per lane, y with W of history
@@ -416,19 +416,16 @@ __device__ __forceinline__ void publish_inclusive(const OnePassArgs &A, int64_t 
     }
 }
 
-// Tickets are handed out in runs of kTicketRun consecutive ones per atomic
-// (one counter shared by every workgroup serialises its atomics).  A
-// workgroup works through its run in order, so every tile it waits for still
-// holds a smaller ticket: done, earlier in its own run, or held by a running
-// workgroup.
-constexpr int kTicketRun = 1;
-
-__device__ __forceinline__ int64_t take_tickets(int *ticket, int lane)
+// One ticket per atomic, taken when the wavefront is free to start the
+// tile (holding tickets ahead would make the tiles that wait for them wait
+// longer: every delay before a tile publishes its aggregate holds up the
+// tiles after it in the same segment).
+__device__ __forceinline__ int64_t take_ticket(int *ticket, int lane)
 {
     int t = 0;
     if (lane == 0)
-        t = atomicAdd(ticket, kTicketRun);
-    return __shfl(t, 0, 64);
+        t = atomicAdd(ticket, 1);
+    return __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
 }
 
 // ------------------------------------------------------------------ forward
@@ -444,15 +441,11 @@ kb_onepass_fwd(OnePassArgs A, const float *__restrict__ x, const float *__restri
     __shared__ __align__(16) float cs[64 * G::CS];
     __shared__ double stage[G::kLook * G::REC];
     const int lane = threadIdx.x;
-    int64_t tk = 0, run_end = 0;
     for (;;) {
-        if (tk == run_end) {
-            tk = take_tickets(A.ticket, lane);
-            run_end = tk + kTicketRun;
-        }
+        const int64_t tk = take_ticket(A.ticket, lane);
         if (tk >= A.ntiles)
             return;
-        const int2 it = A.tiles[tk++];
+        const int2 it = A.tiles[tk];
         const SegDesc sd = A.segs[it.x];
         const int64_t k = it.y;
         const int64_t t0 = k * G::S;
@@ -567,15 +560,11 @@ kb_onepass_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__restr
     __shared__ __align__(16) float cs[64 * G::CS];
     __shared__ double stage[G::kLook * G::REC];
     const int lane = threadIdx.x;
-    int64_t tk = 0, run_end = 0;
     for (;;) {
-        if (tk == run_end) {
-            tk = take_tickets(A.ticket, lane);
-            run_end = tk + kTicketRun;
-        }
+        const int64_t tk = take_ticket(A.ticket, lane);
         if (tk >= A.ntiles)
             return;
-        const int2 it = A.tiles[tk++];
+        const int2 it = A.tiles[tk];
         const SegDesc sd = A.segs[it.x];
         const int64_t k = it.y;
         const int64_t t0 = k * G::S;
