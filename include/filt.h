@@ -130,6 +130,23 @@ filt_status filt_forward_noalloc(const filt_problem *p, const float *x, const fl
                                  const float *a, const float *xi, const float *yi, float *y,
                                  void *stream);
 
+/* Forward-mode derivative (Jacobian-vector product): the tangent dy of the
+ * output along tangents of the inputs,
+ *   dy[n] = sum_k b_k[n] dx[n-k] + sum_k db_k[n] x[n-k]
+ *           - sum_k da_k[n] y[n-k] - sum_k a_k[n] dy[n-k],
+ * with dx[-j] = dxi[j-1], dy[-j] = dyi[j-1] and the histories of x and y from
+ * xi and yi (Eq. 1 differentiated; the same recursion as the forward, run on
+ * the tangent input).  x, y (= filt_forward's output), b, a, xi, yi as for
+ * filt_backward; each tangent dx, db, da, dxi, dyi has the shape of its
+ * input and may be NULL (zero).  x is read only with db, y and yi only with
+ * da.  dy [layout] is written in full.  ws: at least
+ * filt_jvp_workspace_bytes(p) bytes. */
+filt_status filt_jvp_workspace_bytes(const filt_problem *p, size_t *bytes);
+filt_status filt_jvp(const filt_problem *p, const float *x, const float *y, const float *b,
+                     const float *a, const float *xi, const float *yi, const float *dx,
+                     const float *db, const float *da, const float *dxi, const float *dyi,
+                     float *dy, void *ws, size_t ws_bytes, void *stream);
+
 /* The same two operations on FP64 data, computed in FP64 (for numerical
  * gradient checks).  Arguments as above with double in place of float. */
 filt_status filt_forward_f64(const filt_problem *p, const double *x, const double *b,

@@ -1,16 +1,19 @@
 """``torch.autograd.Function`` over the C ABI: differentiable direct-form filter.
 
-Forward calls ``filt_forward``; backward calls ``filt_backward`` (the
-closed-form adjoint of Sec. 3.1 Eqs. 7-9 run in reverse time, fused with the
-gradient reductions).  Only the inputs and the output ``y`` are saved: in the
+Forward calls ``filt_forward``; forward-mode AD (dual tensors of
+``torch.autograd.forward_ad``) calls ``filt_jvp``; backward calls
+``filt_backward`` (the closed-form adjoint of Sec. 3.1 Eqs. 7-9 run in
+reverse time, fused with the gradient reductions).  Only the inputs and the output ``y`` are saved: in the
 direct form the filter state at any chunk boundary is a slice of ``y``
 (the last N outputs) and of ``x``, so nothing else needs to be stored and the
 backward recomputes everything else from them.  Gradients are requested only
-for the inputs that need them (``ctx.needs_input_grad``).
+for the inputs that need them (``ctx.needs_input_grad``).  The backward is
+not itself differentiable (second derivatives through it raise).
 """
 from __future__ import annotations
 
 import torch
+from torch.autograd.function import once_differentiable
 
 from . import filt as _f
 
@@ -21,10 +24,21 @@ class LFilter(torch.autograd.Function):
         y = _f.filt_forward(x, a, b, xi, yi, layout=layout, chunk=chunk, f32_state=f32_state,
                             toeplitz=toeplitz)
         ctx.save_for_backward(x, a, b, xi, yi, y)
+        ctx.save_for_forward(x, a, b, xi, yi, y)
         ctx.cfg = (layout, chunk, f32_state, toeplitz)
         return y
 
     @staticmethod
+    def jvp(ctx, dx, da, db, dxi, dyi, *_):
+        # forward mode: the tangent of y is the same recursion run on the
+        # tangent input (filt_jvp)
+        x, a, b, xi, yi, y = ctx.saved_tensors
+        layout, chunk, _, _ = ctx.cfg
+        return _f.filt_jvp(x, y, a, b, xi, yi, dx=dx, db=db, da=da, dxi=dxi, dyi=dyi,
+                           layout=layout, chunk=chunk)
+
+    @staticmethod
+    @once_differentiable
     def backward(ctx, gy):
         x, a, b, xi, yi, y = ctx.saved_tensors
         layout, chunk, f32_state, toeplitz = ctx.cfg

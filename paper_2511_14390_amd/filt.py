@@ -195,6 +195,41 @@ def filt_backward(gy, x, y, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0
     return out
 
 
+def filt_jvp(x, y, a, b=None, xi=None, yi=None, *, dx=None, db=None, da=None, dxi=None,
+             dyi=None, layout="BT", chunk=0, ws=None, stream=None):
+    """Forward-mode derivative: the tangent of y = filt_forward(x, a, b, xi,
+    yi) along the given input tangents (None = zero).  y is the forward's
+    output.  See filt_jvp in include/filt.h."""
+    dev = x.device
+    if dev.type != "cuda":
+        raise ValueError("filt_jvp runs on the GPU only")
+    if x.dtype != torch.float32:
+        raise ValueError("filt_jvp takes float32 tensors")
+    L = lib()
+    if not getattr(L, "_jvp_ready", False):
+        PP, P = ctypes.POINTER(FiltProblem), ctypes.c_void_p
+        L.filt_jvp_workspace_bytes.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+        L.filt_jvp_workspace_bytes.restype = ctypes.c_int
+        L.filt_jvp.argtypes = [PP] + [P] * 12 + [P, ctypes.c_size_t, P]
+        L.filt_jvp.restype = ctypes.c_int
+        L._jvp_ready = True
+    x = x.contiguous()
+    y, a, b, xi, yi, dx, db, da, dxi, dyi = (
+        _prep(t, torch.float32, dev, n) for t, n in
+        ((y, "y"), (a, "a"), (b, "b"), (xi, "xi"), (yi, "yi"), (dx, "dx"), (db, "db"),
+         (da, "da"), (dxi, "dxi"), (dyi, "dyi")))
+    p = problem(x, a, b, layout, chunk)
+    n = ctypes.c_size_t(0)
+    _check(L.filt_jvp_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    if ws is None or ws.numel() < n.value:
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+    dy = torch.empty_like(x)
+    _check(L.filt_jvp(ctypes.byref(p), _ptr(x), _ptr(y), _ptr(b), _ptr(a), _ptr(xi), _ptr(yi),
+                      _ptr(dx), _ptr(db), _ptr(da), _ptr(dxi), _ptr(dyi), _ptr(dy), _ptr(ws),
+                      ctypes.c_size_t(ws.numel()), _stream(dev, stream)))
+    return dy
+
+
 def profile_enable(on: bool):
     """Start (True) or stop (False) per-kernel event timing inside the library."""
     L = lib()
