@@ -123,3 +123,71 @@ def backward(gy, x, y, a, b=None, xi=None, yi=None, layout="BT", nthreads=1,
         if v is not None:
             out[k] = v
     return out
+
+
+# ---------------------------------------------------------------------------
+# Frame-held coefficients (parameter-varying filters whose coefficients change
+# once per frame of `hop` samples; the paper's closing remarks on
+# parameter-varying cases, with the gradients of Sec. 3.1 Eqs. 6-9).
+#
+# A frame-held row set has F = ceil(T / hop) rows per channel: [F, B, K]
+# (layout "TB") or [B, F, K] ("BT").  Sample t uses the row of frame t // hop,
+# so the filter is the per-sample one on the expanded rows, and by the chain
+# rule the gradient of a frame's row is the sum of the per-sample gradient
+# rows over the frame's samples.
+
+
+def _frame_axis(layout):
+    if layout not in ("TB", "BT"):
+        raise ValueError("layout must be 'TB' or 'BT'")
+    return 0 if layout == "TB" else 1
+
+
+def frame_expand(c, T, hop, layout="BT"):
+    """Per-sample rows (the layout of a per-sample coefficient array) from
+    frame-held rows: row t is the row of frame t // hop."""
+    c = _f64(c)
+    hop = int(hop)
+    if hop < 1:
+        raise ValueError("hop must be >= 1")
+    ax = _frame_axis(layout)
+    F = -(-int(T) // hop)
+    if c.ndim != 3 or c.shape[ax] != F:
+        raise ValueError(f"frame rows must have {F} frames on axis {ax}, got {c.shape}")
+    return np.take(c, np.arange(int(T)) // hop, axis=ax)
+
+
+def frame_reduce(g, hop, layout="BT"):
+    """Gradient of frame-held rows from per-sample gradient rows: the sum of
+    the rows of each frame's samples (the last frame may be shorter)."""
+    g = _f64(g)
+    hop = int(hop)
+    ax = _frame_axis(layout)
+    T = g.shape[ax]
+    if T == 0:
+        return np.zeros(g.shape[:ax] + (0,) + g.shape[ax + 1:])
+    return np.add.reduceat(g, np.arange(0, T, hop), axis=ax)
+
+
+def forward_frames(x, a, b=None, xi=None, yi=None, hop=1, layout="BT", nthreads=1):
+    """Forward with frame-held a (and b, if given)."""
+    x = _f64(x)
+    T = x.shape[0] if layout == "TB" else x.shape[1]
+    ae = None if a is None else frame_expand(a, T, hop, layout)
+    be = None if b is None else frame_expand(b, T, hop, layout)
+    return forward(x, ae, be, xi, yi, layout=layout, nthreads=nthreads)
+
+
+def backward_frames(gy, x, y, a, b=None, xi=None, yi=None, hop=1, layout="BT", nthreads=1,
+                    want=("x", "a", "b", "xi", "yi")):
+    """Closed-form gradients with frame-held a (and b): the per-sample
+    backward on the expanded rows, its a / b rows reduced per frame."""
+    x = _f64(x)
+    T = x.shape[0] if layout == "TB" else x.shape[1]
+    ae = None if a is None else frame_expand(a, T, hop, layout)
+    be = None if b is None else frame_expand(b, T, hop, layout)
+    g = backward(gy, x, y, ae, be, xi, yi, layout=layout, nthreads=nthreads, want=want)
+    for k in ("a", "b"):
+        if k in g:
+            g[k] = frame_reduce(g[k], hop, layout)
+    return g

@@ -14,7 +14,9 @@ Recipes (sign convention ``A(z) = 1 + sum_k a_k z^-k``, paper Eq. 1):
   ``gamma = min(1, rho_max / rho)``, ``rho`` the largest pole radius of the
   frame, so every frame's poles lie within ``rho_max``.
 * Per-sample coefficients are frame-held: one draw per frame of ``hop``
-  samples, repeated over the frame (the last frame truncated).
+  samples, repeated over the frame (the last frame truncated).  With
+  ``frames=True`` the generators return the frame rows themselves
+  (``ceil(T / hop)`` rows per channel) from the same draws instead.
 * Initial conditions ``N(0, 0.1)`` use 0.1 as the standard deviation.
 """
 from __future__ import annotations
@@ -126,10 +128,10 @@ def _f32(v):
     return None if v is None else np.ascontiguousarray(np.asarray(v, dtype=F32))
 
 
-def _reflection_frames(rng, lead_shape, F, N, hop, T, axis, rho_max=0.99):
+def _reflection_frames(rng, lead_shape, F, N, hop, T, axis, rho_max=0.99, expand=True):
     k = rng.uniform(-0.9, 0.9, lead_shape[:axis] + (F,) + lead_shape[axis:] + (N,))
     a = bandwidth_expand(reflection_to_direct(k), rho_max)
-    return frame_held(a, T, hop, axis)
+    return frame_held(a, T, hop, axis) if expand else a
 
 
 def config1(B=4, T=4096, seed=1001):
@@ -146,17 +148,18 @@ def config1(B=4, T=4096, seed=1001):
                    {"seed": seed})
 
 
-def config2(B=64, T=48000, N=16, hop=240, seed=1002):
+def config2(B=64, T=48000, N=16, hop=240, seed=1002, frames=False):
     """Per-sample all-pole (LPC-like): per channel and frame of `hop` samples,
     reflection coefficients U(-0.9, 0.9) -> step-up -> bandwidth expansion to
-    radius 0.99, held over the frame; x~N(0,1); zero initial state; [B, T]."""
+    radius 0.99, held over the frame; x~N(0,1); zero initial state; [B, T].
+    frames=True: a holds the [B, ceil(T / hop), N] frame rows."""
     rng = np.random.default_rng(seed)
     F = -(-T // hop)
-    a = _reflection_frames(rng, (B,), F, N, hop, T, axis=1)
+    a = _reflection_frames(rng, (B,), F, N, hop, T, axis=1, expand=not frames)
     x = rng.standard_normal((B, T))
     gy = rng.standard_normal((B, T))
     return Problem("ltv-allpole-n16", "BT", _f32(x), _f32(a), None, None, None, _f32(gy),
-                   {"seed": seed, "hop": hop})
+                   {"seed": seed, "hop": hop, "frames": frames})
 
 
 def config3(B=1024, T=65536, seed=1003):
@@ -206,24 +209,35 @@ class Segments:
     gy: np.ndarray           # [sum T] f32
     meta: dict = field(default_factory=dict)
 
+    @property
+    def rows(self):
+        """Coefficient rows per segment: T_i, or ceil(T_i / hop) frames."""
+        if self.meta.get("frames"):
+            h = int(self.meta["hop"])
+            return (self.T + h - 1) // h
+        return self.T
+
     def segment(self, i):
-        t, n = int(self.T[i]), int(self.N[i])
+        t, n, r = int(self.T[i]), int(self.N[i]), int(self.rows[i])
         xo, ao, io = int(self.x_off[i]), int(self.a_off[i]), int(self.ic_off[i])
-        return (self.x[xo:xo + t], self.a[ao:ao + t * n].reshape(t, n), self.yi[io:io + n],
+        return (self.x[xo:xo + t], self.a[ao:ao + r * n].reshape(r, n), self.yi[io:io + n],
                 self.gy[xo:xo + t])
 
 
-def config5(nseg=512, Tmin=1000, Tmax=200000, orders=(1, 2, 4, 8, 16), hop=128, seed=1005):
+def config5(nseg=512, Tmin=1000, Tmax=200000, orders=(1, 2, 4, 8, 16), hop=128, seed=1005,
+            frames=False):
     """Batched uneven filters: T_i ~ U{Tmin..Tmax}, N_i uniform over `orders`,
     per-sample coefficients from frame-held reflection coefficients
     U(-0.9, 0.9) with `hop`, bandwidth-expanded to radius 0.99; x~N(0,1);
-    y initial conditions ~N(0, 0.1)."""
+    y initial conditions ~N(0, 0.1).  frames=True: each segment's block holds
+    its ceil(T_i / hop) frame rows instead of T_i sample rows."""
     rng = np.random.default_rng(seed)
     T = rng.integers(Tmin, Tmax + 1, nseg).astype(np.int64)
     N = rng.choice(np.asarray(orders), nseg).astype(np.int32)
     x_off = np.concatenate([[0], np.cumsum(T)[:-1]]).astype(np.int64)
+    R = (T + hop - 1) // hop if frames else T
     # coefficient blocks start on 16-byte boundaries (multiples of 4 floats)
-    a_len = (T * N + 3) // 4 * 4
+    a_len = (R * N + 3) // 4 * 4
     a_off = np.concatenate([[0], np.cumsum(a_len)[:-1]]).astype(np.int64)
     ic_off = np.concatenate([[0], np.cumsum(N)[:-1]]).astype(np.int64)
     x = np.empty(int(T.sum()), dtype=F32)
@@ -233,31 +247,34 @@ def config5(nseg=512, Tmin=1000, Tmax=200000, orders=(1, 2, 4, 8, 16), hop=128, 
     for i in range(nseg):
         t, n = int(T[i]), int(N[i])
         F = -(-t // hop)
-        ai = _reflection_frames(rng, (), F, n, hop, t, axis=0)
-        a[a_off[i]:a_off[i] + t * n] = ai.reshape(-1)
+        ai = _reflection_frames(rng, (), F, n, hop, t, axis=0, expand=not frames)
+        a[a_off[i]:a_off[i] + ai.size] = ai.reshape(-1)
         x[x_off[i]:x_off[i] + t] = rng.standard_normal(t)
         yi[ic_off[i]:ic_off[i] + n] = rng.normal(0.0, 0.1, n)
         gy[x_off[i]:x_off[i] + t] = rng.standard_normal(t)
     return Segments(T, N, x_off, a_off, ic_off, x, a, yi, gy,
-                    {"seed": seed, "hop": hop, "nseg": nseg})
+                    {"seed": seed, "hop": hop, "nseg": nseg, "frames": frames})
 
 
 def random_problem(seed, B, T, M, N, time_varying, layout, rho_max=0.95, hop=8,
-                   with_xi=True, with_yi=True, with_b=True):
+                   with_xi=True, with_yi=True, with_b=True, frames=False):
     """Small random stable problem for parity tests.  Time-invariant
     denominators come from random pole pairs (plus one real pole for odd N);
-    per-sample ones from frame-held reflection coefficients."""
+    per-sample ones from frame-held reflection coefficients (frames=True:
+    the frame rows themselves, ceil(T / hop) per channel)."""
     rng = np.random.default_rng(seed)
     if time_varying:
         axis = 0 if layout == "TB" else 1
         F = -(-T // hop)
+        R = F if frames else T
+        held = (lambda v: v) if frames else (lambda v: frame_held(v, T, hop, axis))
         if N > 0:
             k = rng.uniform(-0.9, 0.9, ((F, B) if axis == 0 else (B, F)) + (N,))
-            a = frame_held(bandwidth_expand(reflection_to_direct(k), rho_max), T, hop, axis)
+            a = held(bandwidth_expand(reflection_to_direct(k), rho_max))
         else:
-            a = np.zeros(((T, B) if axis == 0 else (B, T)) + (0,))
+            a = np.zeros(((R, B) if axis == 0 else (B, R)) + (0,))
         bf = rng.standard_normal(((F, B) if axis == 0 else (B, F)) + (M + 1,))
-        b = frame_held(bf, T, hop, axis)
+        b = held(bf)
     else:
         den = np.ones((B, 1))
         for _ in range(N // 2):
@@ -278,4 +295,4 @@ def random_problem(seed, B, T, M, N, time_varying, layout, rho_max=0.95, hop=8,
     xi = rng.normal(0.0, 0.1, (B, M)) if (with_xi and M > 0) else None
     yi = rng.normal(0.0, 0.1, (B, N)) if (with_yi and N > 0) else None
     return Problem(f"rand-s{seed}", layout, _f32(x), _f32(a), _f32(b), _f32(xi), _f32(yi),
-                   _f32(gy), {"seed": seed})
+                   _f32(gy), {"seed": seed, "hop": hop if frames else 1, "frames": frames})
