@@ -26,7 +26,13 @@
  * - Coefficients: a holds a_1..a_N (a_0 = 1 is implicit, sign as in Eq. 1;
  *   callers normalise by a_0), b holds b_0..b_M.  Time-invariant: a[B][N],
  *   b[B][M+1].  Per-sample (time_varying = 1): the signal layout with the tap
- *   index innermost, [T][B][K] (TB) or [B][T][K] (BT).
+ *   index innermost, [T][B][K] (TB) or [B][T][K] (BT).  Frame-held
+ *   (time_varying = h >= 2, the parameter-varying case of the paper's closing
+ *   remarks): one row per frame of h samples, frame f applying to samples
+ *   [f h, min((f + 1) h, T)), F = ceil(T / h) rows per channel laid out as
+ *   [F][B][K] (TB) or [B][F][K] (BT); needs T < 2^31.  The gradients of
+ *   frame-held rows have the same shapes and are the per-sample gradients
+ *   summed over each frame's samples (the chain rule through the hold).
  * - Initial conditions, most recent first: xi[B][M] with xi[b][j-1] = x[-j],
  *   yi[B][N] with yi[b][j-1] = y[-j].  NULL means zero.
  * - Errors: the return value; a thread-local message is available from
@@ -78,7 +84,8 @@ typedef struct {
     int64_t T;            /* samples per channel (>= 0) */
     int32_t M;            /* feed-forward order: b_0..b_M, 0 <= M <= 16 */
     int32_t N;            /* feedback order: a_1..a_N, 0 <= N <= 16 */
-    int32_t time_varying; /* 0: coefficients per channel; 1: per sample */
+    int32_t time_varying; /* 0: coefficients per channel; 1: per sample; h >= 2: per
+                             frame of h samples (see the conventions above) */
     int32_t layout;       /* filt_layout of x, y, gy, gx (and per-sample coefficients) */
     int32_t flags;        /* FILT_F32_STATE | FILT_RECURRENCE | FILT_TOEPLITZ, or 0 */
     int32_t chunk;        /* time-chunk length for the parallel scan; 0 = automatic,
@@ -104,7 +111,8 @@ filt_status filt_forward(const filt_problem *p, const float *x, const float *b, 
  *   ybar[n] = gy[n] - sum_k a_k[n+k] ybar[n+k]     (reverse time, zero past T-1)
  *   gx[n]   = sum_k b_k[n+k] ybar[n+k]
  *   gb_k[n] = ybar[n] x[n-k],  ga_k[n] = -ybar[n] y[n-k]
- *             (summed over n when time_varying == 0)
+ *             (summed over n when time_varying == 0, over each frame's
+ *             samples when it is a hop h >= 2)
  *   gxi[j-1] = sum_{k>=j} b_k[k-j] ybar[k-j],  gyi[j-1] = -sum_{k>=j} a_k[k-j] ybar[k-j]
  * x, xi are read only when gb is requested or M > 0 matters for it; y, yi
  * only when ga is requested.  Each of gx, gb, ga, gxi, gyi may be NULL (not

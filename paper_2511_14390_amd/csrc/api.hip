@@ -118,8 +118,9 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
                     kMaxOrder, p->M, p->N);
     if (p->layout != FILT_LAYOUT_TB && p->layout != FILT_LAYOUT_BT)
         return fail(FILT_EINVAL, "layout must be FILT_LAYOUT_TB or FILT_LAYOUT_BT");
-    if (p->time_varying != 0 && p->time_varying != 1)
-        return fail(FILT_EINVAL, "time_varying must be 0 or 1");
+    if (p->time_varying < 0)
+        return fail(FILT_EINVAL, "time_varying must be 0, 1 or a hop >= 2 (got %d)",
+                    p->time_varying);
     if (p->chunk < 0 || (p->chunk % 32) != 0)
         return fail(FILT_EINVAL, "chunk must be 0 or a positive multiple of 32 (got %d)",
                     p->chunk);
@@ -127,6 +128,9 @@ filt_status validate(const filt_problem *p, const void *x_or_gy, const void *b, 
         return fail(FILT_EINVAL, "unknown flags 0x%x", p->flags);
     if (p->B == 0 || p->T == 0)
         return FILT_OK;
+    if (p->time_varying > 1 && p->T >= ((int64_t)1 << 31))
+        return fail(FILT_EUNSUPPORTED, "frame-held coefficients need T < 2^31 (T=%lld)",
+                    (long long)p->T);
     if (p->layout == FILT_LAYOUT_TB &&
         p->B * (int64_t)(std::max(p->N, p->M + 1) + 1) >= ((int64_t)1 << 31))
         return fail(FILT_EUNSUPPORTED, "[T][B] layout with B * taps >= 2^31 (B=%lld)",
@@ -157,7 +161,7 @@ Dims make_dims(const filt_problem *p, int has_b, bool f32_io)
     d.T = p->T;
     d.M = p->M;
     d.N = p->N;
-    d.tv = p->time_varying;
+    set_rows(d, p->time_varying);
     d.layout = p->layout;
     d.has_b = has_b;
     d.L = d.tz ? kTzL : (p->chunk > 0 ? p->chunk : auto_chunk(p));

@@ -32,8 +32,8 @@ __device__ __forceinline__ void fwd_apply_item(const Dims &d, const io_t *__rest
     if constexpr (!TV)
         ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
     const Cursor<io_t> xc = cursor(d, x, b, t0, 1);
-    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
-    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
+    const Cursor<io_t> acur = row_cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = row_cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     io_t *yrow = y + sig_at(d, b, t0);
     const int64_t ystride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
     // y history: hy[t mod W] = y[t]; x history likewise
@@ -161,8 +161,8 @@ __device__ __forceinline__ void bwd_apply_item(
     if constexpr (!TV)
         ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
     const Cursor<io_t> gc = cursor(d, gy, b, t0, 1);
-    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
-    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
+    const Cursor<io_t> acur = row_cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = row_cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     const int64_t sstride = d.layout == FILT_LAYOUT_TB ? d.B : 1;
     io_t *gxrow = gx != nullptr ? gx + sig_at(d, b, t0) : nullptr;
     // the adjoint itself, for a separate coefficient-gradient pass
@@ -635,7 +635,10 @@ k_bwd_apply_quad(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ b
 template <int W, typename io_t, typename acc_t>
 constexpr bool kQuadApply = W == 16 && sizeof(acc_t) == 8;
 
-inline bool quad_apply_eligible(const Dims &d) { return d.tv && d.M == 0 && d.N > 0; }
+inline bool quad_apply_eligible(const Dims &d)
+{
+    return d.tv && d.fd.m == 0 && d.M == 0 && d.N > 0;
+}
 
 template <typename io_t>
 filt_status fwd_apply_quad_run(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
@@ -855,9 +858,11 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
     // Other order-16 per-sample problems: the fused adjoint with the
     // coefficient products needs more registers than a wavefront has and
     // spills to AGPRs on every step, so the apply writes the adjoint (FP32)
-    // and a fully parallel pass forms ga and gb from it.
-    const bool split = d.tv && W >= 16 && sizeof(io_t) == 4 && (ga != nullptr || gb != nullptr) &&
-                       tv_coef_grads_fits(d);
+    // and a fully parallel pass forms ga and gb from it.  Frame-held rows
+    // always take that route: their gradients are sums over each frame.
+    const bool frames = d.tv && d.fd.m != 0;
+    const bool split = (ga != nullptr || gb != nullptr) &&
+                       (frames || (d.tv && W >= 16 && sizeof(io_t) == 4 && tv_coef_grads_fits(d)));
     io_t *ybo = split ? (io_t *)(ws + w.yb) : nullptr;
     io_t *ga_f = split ? nullptr : ga;
     io_t *gb_f = split ? nullptr : gb;
@@ -869,6 +874,8 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
                                                                part, ybo, st);
     if (s != FILT_OK)
         return s;
+    if (split && frames)
+        return frame_coef_grads_run<io_t>(d, ybo, x, xi, y, yi, ga, gb, st);
     if constexpr (sizeof(io_t) == 4) {
         if (split)
             return tv_coef_grads_run(d, ybo, x, xi, y, yi, ga, gb, st);

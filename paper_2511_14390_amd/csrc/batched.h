@@ -40,6 +40,8 @@ __device__ __forceinline__ Dims seg_dims(const SegDesc &s)
     d.M = 0;
     d.N = s.N;
     d.tv = 1;
+    d.F = s.T;
+    d.hop = 1;
     d.layout = FILT_LAYOUT_BT;
     d.has_b = 0;
     d.L = s.L;

@@ -58,11 +58,44 @@ void prof_end(int slot, hipStream_t st);
 constexpr int kThreads = 256;
 constexpr int kMaxOrder = 16;
 
+// Frame-held coefficients: with a hop h >= 2 the coefficient row of time t
+// is that of frame t / h (rows at frame rate, F = ceil(T / h) per channel).
+// The division is a multiply-high and a shift, exact for t < 2^31 (checked on
+// the host): with l = ceil(log2 h) and m = ceil(2^(31+l) / h), the excess
+// m h - 2^(31+l) is below h <= 2^l, so floor(t m / 2^(31+l)) = floor(t / h).
+// m = 0 marks per-sample rows.
+struct FrameDiv {
+    uint32_t m;
+    int sh;  // l - 1
+};
+
+inline FrameDiv frame_div(int64_t hop)
+{
+    FrameDiv f{0u, 0};
+    if (hop <= 1)
+        return f;
+    int l = 0;
+    while ((int64_t(1) << l) < hop)
+        ++l;
+    const uint64_t num = uint64_t(1) << (31 + l);
+    f.m = (uint32_t)((num + (uint64_t)hop - 1) / (uint64_t)hop);
+    f.sh = l - 1;
+    return f;
+}
+
+__device__ __forceinline__ uint32_t frame_of(const FrameDiv &f, uint32_t t)
+{
+    return __umulhi(t, f.m) >> f.sh;
+}
+
 // Device-side description of one problem.
 struct Dims {
     int64_t B, T;
     int M, N;
     int tv, layout;
+    int64_t F;      // coefficient rows per channel in time: T per sample, or frames
+    int64_t hop;    // samples per coefficient row (1 per sample)
+    FrameDiv fd;    // frame-held rows when fd.m != 0 (hop >= 2)
     int has_b;
     int64_t L, C;   // chunk length (multiple of 32) and number of chunks
     int64_t G, NB;  // carry: steps per block and number of blocks
@@ -81,7 +114,8 @@ __device__ __forceinline__ int64_t row_at(const Dims &d, int64_t b, int64_t t, i
 {
     if (!d.tv)
         return b * K;
-    return (d.layout == FILT_LAYOUT_TB ? t * d.B + b : b * d.T + t) * (int64_t)K;
+    const int64_t r = d.fd.m != 0 ? (int64_t)frame_of(d.fd, (uint32_t)t) : t;
+    return (d.layout == FILT_LAYOUT_TB ? r * d.B + b : b * d.F + r) * (int64_t)K;
 }
 
 // x[t] for any t: negative times from xi (x[-j] = xi[j-1]), past T -> 0.
@@ -110,16 +144,23 @@ __device__ __forceinline__ acc_t ld_y(const Dims &d, const io_t *y, const io_t *
 // t - t0 clamped into [lo, hi] so every address stays inside [0, T-1].  Steps
 // fetched past the end of a signal are only ever used with zero input and
 // zero state, or not at all.  One multiply-add per access, no layout branch.
+// Frame-held rows (fd.m != 0): p0 is the row of t0's frame, stride the
+// elements per frame, and the row of time t sits frame(t) - frame(t0) rows on.
 template <typename T>
 struct Cursor {
     const T *p0;     // element of time t0
     int stride;      // elements per time step (the host checks it fits)
     int lo, hi;      // clamp of t - t0
+    FrameDiv fd;
+    uint32_t t0, f0; // frame-held rows: the chunk start and its frame
 
-    __device__ __forceinline__ const T *at(int64_t t0, int64_t t) const
+    __device__ __forceinline__ const T *at(int64_t t0_, int64_t t) const
     {
-        const int r = min(max((int)(t - t0), lo), hi);
-        return p0 + (int64_t)r * stride;
+        const int r = min(max((int)(t - t0_), lo), hi);
+        if (fd.m == 0)
+            return p0 + (int64_t)r * stride;
+        const int df = (int)frame_of(fd, t0 + (uint32_t)r) - (int)f0;
+        return p0 + (int64_t)df * stride;
     }
 };
 
@@ -136,6 +177,25 @@ __device__ __forceinline__ Cursor<T> cursor(const Dims &d, const T *base, int64_
     const int64_t hi = d.T - 1 - t0 > d.L + 4 ? d.L + 4 : d.T - 1 - t0;
     c.lo = (int)lo;
     c.hi = (int)hi;
+    c.fd = FrameDiv{0u, 0};
+    c.t0 = 0;
+    c.f0 = 0;
+    return c;
+}
+
+// Cursor over the coefficient rows (K taps) of channel b from chunk start
+// t0: per-sample rows as cursor(), frame-held rows one row per frame.
+template <typename T>
+__device__ __forceinline__ Cursor<T> row_cursor(const Dims &d, const T *base, int64_t b,
+                                                int64_t t0, int K, int back = 4)
+{
+    Cursor<T> c = cursor(d, base, b, t0, K, back);
+    if (d.tv && d.fd.m != 0) {
+        c.fd = d.fd;
+        c.t0 = (uint32_t)t0;
+        c.f0 = frame_of(d.fd, (uint32_t)t0);
+        c.p0 = base + row_at(d, b, t0, K);
+    }
     return c;
 }
 
@@ -457,6 +517,23 @@ filt_status carry_run(const Dims &d, const CarryArgs &a, const void *init, bool 
 filt_status fir_states_run(const Dims &d, const double *summ, double *states, hipStream_t st);
 filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb, bool f64,
                            hipStream_t st);
+
+// Frame rows of a problem: time_varying = 0 (per channel), 1 (per sample)
+// or h >= 2 (per frame of h samples).
+inline void set_rows(Dims &d, int64_t time_varying)
+{
+    d.tv = time_varying != 0;
+    d.hop = time_varying > 1 ? time_varying : 1;
+    d.F = d.tv ? (d.T + d.hop - 1) / d.hop : 0;
+    d.fd = frame_div(d.hop);
+}
+
+// Frame-held rows: ga / gb of every frame from a stored adjoint,
+// ga_k[f] = -sum_{t in f} ybar[t] y[t-k], gb_k[f] = sum_{t in f} ybar[t] x[t-k].
+template <typename io_t>
+filt_status frame_coef_grads_run(const Dims &d, const io_t *ybar, const io_t *x,
+                                 const io_t *xi, const io_t *y, const io_t *yi, io_t *ga,
+                                 io_t *gb, hipStream_t st);
 
 // grads.hip: per-sample coefficient gradients from a stored adjoint,
 // ga_k[n] = -ybar[n] y[n-k] and gb_k[n] = ybar[n] x[n-k] (Eq. 8-9 per sample).

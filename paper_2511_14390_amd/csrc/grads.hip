@@ -81,7 +81,131 @@ k_tv_coef_grads(Dims d, const float *__restrict__ ybar, const float *__restrict_
     }
 }
 
+// Frame-held coefficients: the gradient of a frame's row is the sum of the
+// per-sample products over the frame's samples (Sec. 3.1 Eqs. 8-9 through
+// the frame hold, by the chain rule):
+//   out[row(b, f)][j] = sign * sum_{t in frame f} ybar[t] s[t - k0 - j],
+// s[-i] = hist[b][i-1] for i <= nh, else 0.  FP64 sums.
+
+// Value of signal s at (b, t), from the history before time 0.
+template <typename io_t>
+__device__ __forceinline__ double sig_hist(const Dims &d, const io_t *s, const io_t *hist,
+                                           int nh, int64_t b, int64_t t)
+{
+    if (t >= 0)
+        return (double)s[sig_at(d, b, t)];
+    return (hist != nullptr && -t <= nh) ? (double)hist[b * nh + (-t - 1)] : 0.0;
+}
+
+// [B, T]: one wavefront per (channel, frame); lanes take the frame's samples
+// (coalesced), each lane sums its products for every tap, and the wavefront
+// adds the 64 partial sums of each tap.
+template <typename io_t>
+__global__ void __launch_bounds__(kGradThreads)
+k_frame_grads_bt(Dims d, const io_t *__restrict__ ybar, const io_t *__restrict__ s,
+                 const io_t *__restrict__ hist, int nh, int k0, int K, double sign,
+                 io_t *__restrict__ out)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * kGradThreads + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wave >= d.B * d.F)
+        return;  // whole wavefronts
+    const int64_t b = wave / d.F, f = wave % d.F;
+    const int64_t t0 = f * d.hop, t1 = min(t0 + d.hop, d.T);
+    double acc[kMaxOrder + 1];
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j)
+        acc[j] = 0.0;
+    for (int64_t t = t0 + lane; t < t1; t += 64) {
+        const double yb = (double)ybar[sig_at(d, b, t)];
+#pragma unroll
+        for (int j = 0; j <= kMaxOrder; ++j)
+            if (j < K)
+                acc[j] += yb * sig_hist(d, s, hist, nh, b, t - k0 - j);
+    }
+    io_t *o = out + row_at(d, b, t0, K);
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j) {
+        if (j < K) {
+            double v = acc[j];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1)
+                v += __shfl_xor(v, m, 64);
+            if (lane == 0)
+                o[j] = (io_t)(sign * v);
+        }
+    }
+}
+
+// [T, B]: one lane per (channel, frame), neighbouring lanes neighbouring
+// channels (every load of a wavefront is one contiguous run); the lane walks
+// its frame and keeps the K sums.
+template <typename io_t>
+__global__ void __launch_bounds__(kGradThreads)
+k_frame_grads_tb(Dims d, const io_t *__restrict__ ybar, const io_t *__restrict__ s,
+                 const io_t *__restrict__ hist, int nh, int k0, int K, double sign,
+                 io_t *__restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * kGradThreads + threadIdx.x;
+    if (g >= d.B * d.F)
+        return;
+    const int64_t b = g % d.B, f = g / d.B;
+    const int64_t t0 = f * d.hop, t1 = min(t0 + d.hop, d.T);
+    double acc[kMaxOrder + 1];
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j)
+        acc[j] = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const double yb = (double)ybar[sig_at(d, b, t)];
+#pragma unroll
+        for (int j = 0; j <= kMaxOrder; ++j)
+            if (j < K)
+                acc[j] += yb * sig_hist(d, s, hist, nh, b, t - k0 - j);
+    }
+    io_t *o = out + row_at(d, b, t0, K);
+#pragma unroll
+    for (int j = 0; j <= kMaxOrder; ++j)
+        if (j < K)
+            o[j] = (io_t)(sign * acc[j]);
+}
+
 }  // namespace
+
+template <typename io_t>
+filt_status frame_coef_grads_run(const Dims &d, const io_t *ybar, const io_t *x,
+                                 const io_t *xi, const io_t *y, const io_t *yi, io_t *ga,
+                                 io_t *gb, hipStream_t st)
+{
+    if (d.B * d.F == 0)
+        return FILT_OK;
+    auto launch = [&](const io_t *sig, const io_t *hist, int nh, int k0, int K, double sign,
+                      io_t *o) {
+        if (d.layout == FILT_LAYOUT_BT) {
+            const int64_t threads = d.B * d.F * 64;
+            FILT_LAUNCH("frame_coef_grads", k_frame_grads_bt<io_t>,
+                        dim3((unsigned)((threads + kGradThreads - 1) / kGradThreads)),
+                        dim3(kGradThreads), 0, st, d, ybar, sig, hist, nh, k0, K, sign, o);
+        } else {
+            const int64_t threads = d.B * d.F;
+            FILT_LAUNCH("frame_coef_grads", k_frame_grads_tb<io_t>,
+                        dim3((unsigned)((threads + kGradThreads - 1) / kGradThreads)),
+                        dim3(kGradThreads), 0, st, d, ybar, sig, hist, nh, k0, K, sign, o);
+        }
+    };
+    if (ga != nullptr && d.N > 0)
+        launch(y, yi, d.N, 1, d.N, -1.0, ga);
+    if (gb != nullptr)
+        launch(x, xi, d.M, 0, d.M + 1, 1.0, gb);
+    return check_launch("frame coefficient gradients");
+}
+
+template filt_status frame_coef_grads_run<float>(const Dims &, const float *,
+                                                 const float *, const float *, const float *,
+                                                 const float *, float *, float *, hipStream_t);
+template filt_status frame_coef_grads_run<double>(const Dims &, const double *,
+                                                  const double *, const double *, const double *,
+                                                  const double *, double *, double *,
+                                                  hipStream_t);
 
 bool tv_coef_grads_fits(const Dims &d)
 {

@@ -120,7 +120,7 @@ filt_status filt_jvp(const filt_problem *p, const float *x, const float *y, cons
     d.T = p->T;
     d.M = p->M;
     d.N = p->N;
-    d.tv = p->time_varying;
+    set_rows(d, p->time_varying);
     d.layout = p->layout;
     hipStream_t st = (hipStream_t)stream;
     char *base = (char *)(((uintptr_t)ws + 255) & ~uintptr_t(255));

@@ -390,7 +390,8 @@ k_stream_bwd(Dims d, const float *__restrict__ gy, const float *__restrict__ a,
 // per lane and step, and the direct path keeps more of them in flight).
 inline bool stream_eligible(const Dims &d)
 {
-    return d.tv && d.layout == FILT_LAYOUT_BT && !d.has_b && d.M == 0 && d.N > 0 && d.N <= 8;
+    return d.tv && d.fd.m == 0 && d.layout == FILT_LAYOUT_BT && !d.has_b && d.M == 0 &&
+           d.N > 0 && d.N <= 8;
 }
 
 template <int W>

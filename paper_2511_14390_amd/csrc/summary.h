@@ -124,8 +124,8 @@ __device__ __forceinline__ void fwd_summary_item(const Dims &d, const io_t *__re
     if constexpr (!TV)
         ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
     const Cursor<io_t> xc = cursor(d, x, b, t0, 1);
-    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
-    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
+    const Cursor<io_t> acur = row_cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = row_cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     double h[S][W], hx[W], wgt[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) {
@@ -283,8 +283,8 @@ __device__ __forceinline__ void bwd_summary_item(const Dims &d, const io_t *__re
     if constexpr (!TV)
         ld_row_lti<W, FIR>(d, bc, ac, b, la, lb);
     const Cursor<io_t> gc = cursor(d, gy, b, t0, 1);
-    const Cursor<io_t> acur = cursor(d, ac, b, t0, d.N);
-    const Cursor<io_t> bcur = cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
+    const Cursor<io_t> acur = row_cursor(d, ac, b, t0, d.N);
+    const Cursor<io_t> bcur = row_cursor(d, bc, b, t0, d.has_b ? d.M + 1 : 0);
     double ss[S][W], rs[S][W], wgt[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) {
@@ -817,7 +817,7 @@ filt_status fwd_summary_fir(const Dims &d, const io_t *x, const io_t *xi, const 
     const int N = d.N;
     const int64_t ncs = d.C - 1;  // chunks with a successor
     if constexpr (W == 16) {
-        if (d.tv) {
+        if (d.tv && d.fd.m == 0) {
             const unsigned gr = (unsigned)((d.B * ncs + kRowGroupChunks - 1) / kRowGroupChunks);
 #define FILT_ROWS(AV, FULL)                                                                        \
     FILT_LAUNCH("fwd_summary", (k_fwd_summary_rows<FIR, AV, FULL, io_t>), dim3(gr),               \
@@ -872,7 +872,7 @@ filt_status bwd_summary_fir(const Dims &d, const io_t *gy, const io_t *bc, const
     const int N = d.N;
     const int64_t ncs = d.C - 1;  // chunks 1..C-1 pass a state to an earlier chunk
     if constexpr (W == 16 && !FIR) {
-        if (d.tv) {
+        if (d.tv && d.fd.m == 0) {
             const unsigned gr = (unsigned)((d.B * ncs + kRowGroupChunks - 1) / kRowGroupChunks);
 #define FILT_ROWS(AV, FULL)                                                                        \
     FILT_LAUNCH("bwd_summary", (k_bwd_summary_rows<AV, FULL, io_t>), dim3(gr),                    \

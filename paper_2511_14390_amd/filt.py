@@ -92,23 +92,31 @@ def _layout_code(layout):
 
 
 def problem(x, a, b=None, layout="BT", chunk=0, f32_state=False, recurrence=False,
-            toeplitz=False):
-    """Build the filt_problem for these tensors (shapes checked here)."""
+            toeplitz=False, hop=1):
+    """Build the filt_problem for these tensors (shapes checked here).
+    Coefficients with a time axis are per sample (hop = 1) or frame-held:
+    hop >= 2 samples per row, ceil(T / hop) rows per channel."""
     if x.dim() != 2:
         raise ValueError("x must be 2-D")
+    hop = int(hop)
+    if hop < 1:
+        raise ValueError("hop must be >= 1")
     T, B = (x.shape[0], x.shape[1]) if layout == "TB" else (x.shape[1], x.shape[0])
     N = 0 if a is None else a.shape[-1]
     M = 0 if b is None else b.shape[-1] - 1
     tv = (a is not None and a.dim() == 3) or (b is not None and b.dim() == 3)
+    if hop > 1 and not tv:
+        raise ValueError("hop > 1 needs coefficients with a time axis")
+    R = -(-T // hop)
     for c, K in ((a, N), (b, M + 1)):
         if c is None:
             continue
-        want = (B, K) if not tv else ((T, B, K) if layout == "TB" else (B, T, K))
+        want = (B, K) if not tv else ((R, B, K) if layout == "TB" else (B, R, K))
         if tuple(c.shape) != want:
             raise ValueError(f"coefficient shape {tuple(c.shape)} != {want}")
     flags = ((FILT_F32_STATE if f32_state else 0) | (FILT_RECURRENCE if recurrence else 0)
              | (FILT_TOEPLITZ if toeplitz else 0))
-    p = FiltProblem(B, T, M, N, int(tv), _layout_code(layout), flags, int(chunk))
+    p = FiltProblem(B, T, M, N, hop if tv else 0, _layout_code(layout), flags, int(chunk))
     return p
 
 
@@ -145,8 +153,9 @@ def _stream(device, stream):
 
 
 def filt_forward(x, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0, f32_state=False,
-                 recurrence=False, toeplitz=False, out=None, ws=None, stream=None):
-    """y = direct-form filter of x (see include/filt.h).  Returns y."""
+                 recurrence=False, toeplitz=False, hop=1, out=None, ws=None, stream=None):
+    """y = direct-form filter of x (see include/filt.h).  Returns y.
+    hop >= 2: a and b hold one row per frame of hop samples."""
     dev, dt = x.device, x.dtype
     if dt not in (torch.float32, torch.float64):
         raise ValueError("x must be float32 or float64")
@@ -154,7 +163,7 @@ def filt_forward(x, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0, f32_st
         raise ValueError("filt_forward runs on the GPU only")
     x = x.contiguous()
     a, b, xi, yi = (_prep(t, dt, dev, n) for t, n in ((a, "a"), (b, "b"), (xi, "xi"), (yi, "yi")))
-    p = problem(x, a, b, layout, chunk, f32_state, recurrence, toeplitz)
+    p = problem(x, a, b, layout, chunk, f32_state, recurrence, toeplitz, hop)
     y = out if out is not None else torch.empty_like(x)
     ws, need = _workspace(p, dev, ws)
     fn = lib().filt_forward_f64 if dt == torch.float64 else lib().filt_forward
@@ -164,18 +173,19 @@ def filt_forward(x, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0, f32_st
 
 
 def filt_backward(gy, x, y, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0,
-                  f32_state=False, recurrence=False, toeplitz=False,
+                  f32_state=False, recurrence=False, toeplitz=False, hop=1,
                   want=("x", "a", "b", "xi", "yi"), ws=None, stream=None):
     """Closed-form gradients (see include/filt.h).  Returns a dict with the
     requested keys among x, a, b, xi, yi (b only if b was given; xi / yi
-    always have shapes [B, M] / [B, N])."""
+    always have shapes [B, M] / [B, N]; with hop >= 2 the a / b gradients
+    have one row per frame, like a and b)."""
     dev, dt = gy.device, gy.dtype
     if dev.type != "cuda":
         raise ValueError("filt_backward runs on the GPU only")
     gy = gy.contiguous()
     x, y, a, b, xi, yi = (_prep(t, dt, dev, n) for t, n in
                           ((x, "x"), (y, "y"), (a, "a"), (b, "b"), (xi, "xi"), (yi, "yi")))
-    p = problem(gy, a, b, layout, chunk, f32_state, recurrence, toeplitz)
+    p = problem(gy, a, b, layout, chunk, f32_state, recurrence, toeplitz, hop)
     B, M, N = p.B, p.M, p.N
     gx = torch.empty_like(gy) if "x" in want else None
     ga = torch.empty_like(a) if ("a" in want and a is not None and N > 0) else None
@@ -196,7 +206,7 @@ def filt_backward(gy, x, y, a, b=None, xi=None, yi=None, *, layout="BT", chunk=0
 
 
 def filt_jvp(x, y, a, b=None, xi=None, yi=None, *, dx=None, db=None, da=None, dxi=None,
-             dyi=None, layout="BT", chunk=0, ws=None, stream=None):
+             dyi=None, layout="BT", chunk=0, hop=1, ws=None, stream=None):
     """Forward-mode derivative: the tangent of y = filt_forward(x, a, b, xi,
     yi) along the given input tangents (None = zero).  y is the forward's
     output.  See filt_jvp in include/filt.h."""
@@ -218,7 +228,7 @@ def filt_jvp(x, y, a, b=None, xi=None, yi=None, *, dx=None, db=None, da=None, dx
         _prep(t, torch.float32, dev, n) for t, n in
         ((y, "y"), (a, "a"), (b, "b"), (xi, "xi"), (yi, "yi"), (dx, "dx"), (db, "db"),
          (da, "da"), (dxi, "dxi"), (dyi, "dyi")))
-    p = problem(x, a, b, layout, chunk)
+    p = problem(x, a, b, layout, chunk, hop=hop)
     n = ctypes.c_size_t(0)
     _check(L.filt_jvp_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
     if ws is None or ws.numel() < n.value:

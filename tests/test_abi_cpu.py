@@ -2,6 +2,8 @@
 declared in include/filt.h, and rejects bad arguments on the host (before any
 GPU work is queued)."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -69,7 +71,8 @@ def test_workspace_query(L):
     (dict(N=17), F.FILT_EUNSUPPORTED),
     (dict(M=20), F.FILT_EUNSUPPORTED),
     (dict(layout=7), F.FILT_EINVAL),
-    (dict(time_varying=2), F.FILT_EINVAL),
+    (dict(time_varying=-1), F.FILT_EINVAL),
+    (dict(time_varying=3, T=1 << 31), F.FILT_EUNSUPPORTED),
     (dict(chunk=48), F.FILT_EINVAL),
     (dict(flags=0x80), F.FILT_EINVAL),
 ])
@@ -191,6 +194,29 @@ def test_plan_create_rejects_bad_segments_on_host(L):
     ok = (F.FiltSegment * 1)(F.FiltSegment(0, 100, 0, 0, 2, 0))
     assert L.filt_plan_create(ok, 1, bad_chunk, ctypes.byref(h)) == F.FILT_EINVAL
     assert L.filt_plan_create(ok, 1, None, None) == F.FILT_EINVAL
+
+
+def test_frame_held_workspace_query(L):
+    # time_varying = h >= 2: rows at frame rate; same workspace rules as per
+    # sample (the adjoint is staged for the per-frame gradient reduction)
+    for h in (2, 128, 240, 100000):
+        rc, n = _ws(L, _prob(T=48000, N=16, time_varying=h))
+        assert rc == F.FILT_OK and n > 0, h
+
+
+def test_frame_division_is_exact():
+    # the kernels find a sample's frame as (t * m) >> (31 + l) with
+    # l = ceil(log2 h), m = ceil(2^(31+l) / h); exact for every t < 2^31
+    rng = np.random.default_rng(4)
+    hops = [2, 3, 5, 7, 100, 128, 240, 1000, 4095, 65537, (1 << 30) + 3, (1 << 31) - 1]
+    ts = np.concatenate([np.arange(0, 5000), rng.integers(0, 1 << 31, 200000),
+                         [(1 << 31) - 1, (1 << 31) - 2]]).astype(np.uint64)
+    for h in hops:
+        l = max(int(h - 1).bit_length(), 1)
+        m = ((1 << (31 + l)) + h - 1) // h
+        assert m < (1 << 32)
+        q = ((ts * np.uint64(m)) >> np.uint64(32)) >> np.uint64(l - 1)
+        assert np.array_equal(q, ts // np.uint64(h)), h
 
 
 def test_empty_backward_is_ok_on_host(L):
