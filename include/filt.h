@@ -176,8 +176,11 @@ filt_status filt_backward_f64(const filt_problem *p, const double *gy, const dou
  * compute for it with B = 1 in the [B][T] layout.
  *
  * Segment i covers samples [x_off, x_off + T) of x / y / gy / gx, its
- * coefficient rows a[a_off + t*N .. a_off + t*N + N) for t < T (a_1..a_N of
- * time t) and its initial conditions yi[ic_off .. ic_off + N) (y[-1] first).
+ * coefficient rows a[a_off + r*N .. a_off + r*N + N) (a_1..a_N) and its
+ * initial conditions yi[ic_off .. ic_off + N) (y[-1] first).  With hop 0 or 1
+ * the rows are per sample (r = t < T); with hop h >= 2 they are frame-held
+ * (r = t / h < ceil(T / h)), and ga holds per-frame gradients (each the sum
+ * over the frame's samples), as filt_backward with time_varying = h.
  * Segments must not overlap in the outputs.  Coefficient blocks that start on
  * a multiple of 4 floats (16 bytes) are read as whole vectors.
  * ------------------------------------------------------------------------ */
@@ -187,7 +190,7 @@ typedef struct {
     int64_t a_off;  /* first coefficient in a / ga */
     int64_t ic_off; /* first initial condition in yi / gyi */
     int32_t N;      /* order, 0 <= N <= 16 */
-    int32_t reserved;
+    int32_t hop;    /* 0 or 1: a row per sample; h >= 2: a row per frame of h samples */
 } filt_segment;
 
 typedef struct filt_plan filt_plan;
@@ -205,8 +208,8 @@ filt_status filt_plan_create(const filt_segment *segs, int32_t nseg, const int32
 void filt_plan_destroy(filt_plan *p);
 
 /* Forward / backward of every segment, asynchronous on stream, no
- * allocation.  Backward: ga (per-sample, the layout of a) and gyi may be NULL;
- * y is needed for ga.  gx may be NULL. */
+ * allocation.  Backward: ga (the layout of a: per sample or per frame) and
+ * gyi may be NULL; y is needed for ga.  gx may be NULL. */
 filt_status filt_plan_forward(filt_plan *p, const float *x, const float *a, const float *yi,
                               float *y, void *stream);
 filt_status filt_plan_backward(filt_plan *p, const float *gy, const float *y, const float *a,

@@ -20,12 +20,12 @@ from . import filt as _f
 
 class LFilter(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, x, a, b, xi, yi, layout, chunk, f32_state, toeplitz):
+    def forward(ctx, x, a, b, xi, yi, layout, chunk, f32_state, toeplitz, hop):
         y = _f.filt_forward(x, a, b, xi, yi, layout=layout, chunk=chunk, f32_state=f32_state,
-                            toeplitz=toeplitz)
+                            toeplitz=toeplitz, hop=hop)
         ctx.save_for_backward(x, a, b, xi, yi, y)
         ctx.save_for_forward(x, a, b, xi, yi, y)
-        ctx.cfg = (layout, chunk, f32_state, toeplitz)
+        ctx.cfg = (layout, chunk, f32_state, toeplitz, hop)
         return y
 
     @staticmethod
@@ -33,33 +33,36 @@ class LFilter(torch.autograd.Function):
         # forward mode: the tangent of y is the same recursion run on the
         # tangent input (filt_jvp)
         x, a, b, xi, yi, y = ctx.saved_tensors
-        layout, chunk, _, _ = ctx.cfg
+        layout, chunk, _, _, hop = ctx.cfg
         return _f.filt_jvp(x, y, a, b, xi, yi, dx=dx, db=db, da=da, dxi=dxi, dyi=dyi,
-                           layout=layout, chunk=chunk)
+                           layout=layout, chunk=chunk, hop=hop)
 
     @staticmethod
     @once_differentiable
     def backward(ctx, gy):
         x, a, b, xi, yi, y = ctx.saved_tensors
-        layout, chunk, f32_state, toeplitz = ctx.cfg
+        layout, chunk, f32_state, toeplitz, hop = ctx.cfg
         need = ctx.needs_input_grad
         want = [k for k, n in zip(("x", "a", "b", "xi", "yi"), need[:5]) if n]
         if not want:
-            return (None,) * 9
+            return (None,) * 10
         g = _f.filt_backward(gy, x, y, a, b, xi, yi, layout=layout, chunk=chunk,
-                             f32_state=f32_state, toeplitz=toeplitz, want=tuple(want))
+                             f32_state=f32_state, toeplitz=toeplitz, hop=hop, want=tuple(want))
         return (g.get("x"), g.get("a"), g.get("b") if b is not None else None,
                 g.get("xi") if xi is not None else None, g.get("yi") if yi is not None else None,
-                None, None, None, None)
+                None, None, None, None, None)
 
 
 def lfilter(x, a, b=None, xi=None, yi=None, layout="BT", chunk=0, f32_state=False,
-            toeplitz=False):
+            toeplitz=False, hop=1):
     """Differentiable y[n] = sum_k b_k[n] x[n-k] - sum_k a_k[n] y[n-k].
 
-    ``a`` / ``b`` may be per-channel ``[B, K]`` or per-sample (the signal
-    layout plus a trailing tap axis).  Coefficients shared across channels can
-    be passed as ``c.expand(B, K)``; autograd sums the per-channel gradients.
+    ``a`` / ``b`` may be per-channel ``[B, K]``, per-sample (the signal
+    layout plus a trailing tap axis) or, with ``hop >= 2``, frame-held: one
+    row per frame of ``hop`` samples in place of the time axis
+    (``ceil(T / hop)`` rows), whose gradients are summed over each frame.
+    Coefficients shared across channels can be passed as ``c.expand(B, K)``;
+    autograd sums the per-channel gradients.
     """
     if a is not None:
         a = a.contiguous()
@@ -70,4 +73,4 @@ def lfilter(x, a, b=None, xi=None, yi=None, layout="BT", chunk=0, f32_state=Fals
     if yi is not None:
         yi = yi.contiguous()
     return LFilter.apply(x.contiguous(), a, b, xi, yi, layout, int(chunk), bool(f32_state),
-                         bool(toeplitz))
+                         bool(toeplitz), int(hop))

@@ -420,11 +420,11 @@ __device__ __forceinline__ void fwd_apply_quad(const Dims &d, const io_t *__rest
     const int64_t t0 = c * d.L;
     const int64_t e0 = sig_at(d, b, t0);
     const int64_t es = d.layout == FILT_LAYOUT_TB ? d.B : 1;
-    const int64_t as = es * N;
     const int last = CLAMP ? (int)min<int64_t>(d.T - 1 - t0, d.L - 1) : (int)d.L - 1;
     const io_t *xp = x + e0;
-    const io_t *ap = ac + e0 * N;
-    const io_t *gp = HASB ? bc + e0 : xp;  // order-0 FIR part: one tap per row
+    const RowWalk<io_t> aw = row_walk(d, ac, b, c * d.L, N);
+    // order-0 FIR part: one tap per row (b_0)
+    const RowWalk<io_t> bw = row_walk(d, HASB ? bc : x, b, c * d.L, HASB ? 1 : 0);
     io_t *yp = y + e0;
     double w[4];  // w[i] = y[t - 4q - 1 - i], from the entering state
 #pragma unroll
@@ -441,10 +441,10 @@ __device__ __forceinline__ void fwd_apply_quad(const Dims &d, const io_t *__rest
     }
     auto fetch = [&](int rel, QuadRaw<io_t> &r) {
         const int rc = CLAMP ? min(rel, last) : rel;
-        quad_taps<AV>(ap + rc * as, q, N, r.a);
+        quad_taps<AV>(aw.at(rc), q, N, r.a);
         r.s = xp[rc * es];
         if constexpr (HASB)
-            r.g = gp[rc * es];
+            r.g = *bw.at(rc);
     };
     QuadRaw<io_t> buf[P];
     static_for<P>([&](auto I) { fetch(decltype(I)::value, buf[decltype(I)::value]); });
@@ -513,11 +513,10 @@ __device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__rest
     const int64_t t0 = c * d.L;
     const int64_t e0 = sig_at(d, b, t0);
     const int64_t es = d.layout == FILT_LAYOUT_TB ? d.B : 1;
-    const int64_t as = es * N;
     const int last = CLAMP ? (int)min<int64_t>(d.T - 1 - t0, d.L - 1) : (int)d.L - 1;
     const io_t *g0 = gy + e0;
-    const io_t *ap = ac + e0 * N;
-    const io_t *gp = HASB ? bc + e0 : g0;
+    const RowWalk<io_t> aw = row_walk(d, ac, b, c * d.L, N);
+    const RowWalk<io_t> bw = row_walk(d, HASB ? bc : gy, b, c * d.L, HASB ? 1 : 0);
     double st[4];  // st[i] = s_{4q+1+i}
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -540,11 +539,11 @@ __device__ __forceinline__ void bwd_apply_quad(const Dims &d, const io_t *__rest
     }
     auto fetch = [&](int rel, QuadRaw<io_t> &r) {
         const int rc = CLAMP ? min(rel, last) : rel;
-        quad_taps<AV>(ap + rc * as, q, N, r.a);
+        quad_taps<AV>(aw.at(rc), q, N, r.a);
         const io_t g = g0[rc * es];
         r.s = (!CLAMP || rel <= last) ? g : io_t(0);
         if constexpr (HASB)
-            r.g = gp[rc * es];
+            r.g = *bw.at(rc);
         if constexpr (GA)
             r.y = yat(rel - 4 * q - 5);  // enters the window after this step
     };
@@ -635,10 +634,7 @@ k_bwd_apply_quad(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ b
 template <int W, typename io_t, typename acc_t>
 constexpr bool kQuadApply = W == 16 && sizeof(acc_t) == 8;
 
-inline bool quad_apply_eligible(const Dims &d)
-{
-    return d.tv && d.fd.m == 0 && d.M == 0 && d.N > 0;
-}
+inline bool quad_apply_eligible(const Dims &d) { return d.tv && d.M == 0 && d.N > 0; }
 
 template <typename io_t>
 filt_status fwd_apply_quad_run(const Dims &d, const io_t *x, const io_t *bc, const io_t *ac,
@@ -828,11 +824,13 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
     if constexpr (sizeof(io_t) == 4 && sizeof(acc_t) == 8 && W <= 16) {
         // [B, T] all-pole: staged apply writes ybar (gx itself when wanted,
         // since gx = ybar for b = [1]); ga comes from the coalesced pass
-        if (stream_eligible(d) && (ga == nullptr || tv_coef_grads_fits(d))) {
+        if (stream_eligible(d) && (ga == nullptr || d.fd.m != 0 || tv_coef_grads_fits(d))) {
             io_t *yb = gx != nullptr ? gx : (io_t *)(ws + w.yb);
             filt_status s = stream_backward_run<W>(d, gy, ac, states, yb, gyi, st);
             if (s != FILT_OK || ga == nullptr)
                 return s;
+            if (d.fd.m != 0)
+                return frame_coef_grads_run<io_t>(d, yb, x, xi, y, yi, ga, nullptr, st);
             return tv_coef_grads_run(d, yb, x, xi, y, yi, ga, nullptr, st);
         }
     }
@@ -840,17 +838,21 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
     // ybar (into gx itself without b, where gx = ybar), then the coefficient
     // gradients from it in a fully parallel pass.
     if constexpr (kQuadApply<W, io_t, acc_t>) {
-        // ga alone is formed inside the adjoint pass; with gb (an order-0
-        // FIR part) both come from ybar in the coalesced pass
-        if (quad_apply_eligible(d) && gb == nullptr)
+        // per-sample ga alone is formed inside the adjoint pass; with gb (an
+        // order-0 FIR part), or for frame-held rows, the gradients come from
+        // ybar in a separate pass
+        const bool fr = d.fd.m != 0;
+        if (quad_apply_eligible(d) && gb == nullptr && !fr)
             return bwd_apply_quad_run<io_t>(d, gy, bc, ac, states, gx, gyi, nullptr, y, yi, ga,
                                             st);
-        if (quad_apply_eligible(d) && sizeof(io_t) == 4 && tv_coef_grads_fits(d)) {
+        if (quad_apply_eligible(d) && (fr || (sizeof(io_t) == 4 && tv_coef_grads_fits(d)))) {
             io_t *yb = (gx != nullptr && !d.has_b) ? gx : (io_t *)(ws + w.yb);
             filt_status s = bwd_apply_quad_run<io_t>(d, gy, bc, ac, states, gx, gyi, yb, y, yi,
                                                      nullptr, st);
-            if (s != FILT_OK)
+            if (s != FILT_OK || (ga == nullptr && gb == nullptr))
                 return s;
+            if (fr)
+                return frame_coef_grads_run<io_t>(d, yb, x, xi, y, yi, ga, gb, st);
             if constexpr (sizeof(io_t) == 4)
                 return tv_coef_grads_run(d, yb, x, xi, y, yi, ga, gb, st);
         }

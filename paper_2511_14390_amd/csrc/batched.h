@@ -24,6 +24,8 @@ struct SegDesc {
     int64_t summ_off, states_off, agg_off, bstart_off;
     int64_t tile_base, ntile;  // single-pass buckets: first tile record, tiles
     int32_t N, a_vec;
+    int64_t hop;               // samples per coefficient row (1: per sample)
+    FrameDiv fd;               // frame-held rows when fd.m != 0
 };
 
 // One unit of work: a chunk of a segment (and, for the summaries, one of the
@@ -40,8 +42,9 @@ __device__ __forceinline__ Dims seg_dims(const SegDesc &s)
     d.M = 0;
     d.N = s.N;
     d.tv = 1;
-    d.F = s.T;
-    d.hop = 1;
+    d.hop = s.hop;
+    d.fd = s.fd;
+    d.F = s.fd.m != 0 ? (s.T + s.hop - 1) / s.hop : s.T;
     d.layout = FILT_LAYOUT_BT;
     d.has_b = 0;
     d.L = s.L;
@@ -229,7 +232,10 @@ kb_stream_fwd(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
     const int64_t t0 = c * Lc;
     L.osig[i] = act ? sd.x_off + t0 : 0;
     L.oout[i] = L.osig[i];
-    L.ocoef[i] = act ? sd.a_off + t0 * sd.N : 0;
+    L.ocoef[i] = act ? sd.a_off + (sd.fd.m != 0 ? (int64_t)frame_of(sd.fd, (uint32_t)t0) : t0) *
+                               sd.N
+                     : 0;
+    stream_set_rows(L, i, t0, sd.fd);
     L.ln[i] = act ? min(Lc, sd.T - t0) : 0;
     L.lN[i] = act ? sd.N : 0;
     double h0[W];
@@ -266,7 +272,10 @@ kb_stream_bwd(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
     const int64_t t0 = c * Lc;
     L.osig[i] = act ? sd.x_off + t0 : 0;
     L.oout[i] = L.osig[i];
-    L.ocoef[i] = act ? sd.a_off + t0 * sd.N : 0;
+    L.ocoef[i] = act ? sd.a_off + (sd.fd.m != 0 ? (int64_t)frame_of(sd.fd, (uint32_t)t0) : t0) *
+                               sd.N
+                     : 0;
+    stream_set_rows(L, i, t0, sd.fd);
     L.ln[i] = act ? min(Lc, sd.T - t0) : 0;
     L.lN[i] = act ? sd.N : 0;
     double s0[W];
@@ -294,8 +303,8 @@ kb_coef_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
     const Item it = items[blockIdx.x];
     const SegDesc sd = segs[it.seg];
     const int N = sd.N;
-    if (N == 0)
-        return;
+    if (N == 0 || sd.fd.m != 0)
+        return;  // frame-held rows take kb_frame_grads
     const int64_t t0 = (int64_t)it.chunk * Lc;
     const int64_t n = min(Lc, sd.T - t0);
     const int G = (N + 3) / 4;
@@ -330,6 +339,66 @@ kb_coef_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
             for (int jj = 0; jj < 4; ++jj)
                 if (4 * q + jj < N)
                     __builtin_nontemporal_store(r[jj], o + jj);
+        }
+    }
+}
+
+// Frame-held rows: ga of every frame of the bucket's frame-held segments
+// from the stored adjoint, ga_k[f] = -sum_{t in f} ybar[t] y[t-k] (Sec. 3.1
+// Eq. 8 summed over the frame).  One wavefront per frame: lanes take the
+// frame's samples, then the wavefront adds each tap's 64 partial sums.
+// Frame w of the bucket belongs to the segment sid[k] with
+// cum[k] <= w < cum[k + 1] (binary search over the ns segments).
+static __global__ void __launch_bounds__(256)
+kb_frame_grads(const SegDesc *__restrict__ segs, const int64_t *__restrict__ cum,
+               const int *__restrict__ sid, int ns, int64_t nf, const float *__restrict__ ybar,
+               const float *__restrict__ y, const float *__restrict__ yi, float *__restrict__ ga)
+{
+    const int64_t w = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= nf)
+        return;  // whole wavefronts
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cum[mid] <= w)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const SegDesc sd = segs[sid[lo]];
+    const int64_t f = w - cum[lo];
+    const int64_t t0 = f * sd.hop, t1 = min(t0 + sd.hop, sd.T);
+    const int N = sd.N;
+    double acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        acc[j] = 0.0;
+    for (int64_t t = t0 + lane; t < t1; t += 64) {
+        const double yb = (double)ybar[sd.x_off + t];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (j < N) {
+                const int64_t u = t - 1 - j;
+                float v = 0.f;
+                if (u >= 0)
+                    v = y[sd.x_off + u];
+                else if (yi != nullptr)
+                    v = yi[sd.ic_off + (-u - 1)];
+                acc[j] = __builtin_fma(yb, (double)v, acc[j]);
+            }
+        }
+    }
+    float *o = ga + sd.a_off + f * N;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j < N) {
+            double v = acc[j];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1)
+                v += __shfl_xor(v, m, 64);
+            if (lane == 0)
+                o[j] = (float)(-v);
         }
     }
 }
@@ -377,7 +446,7 @@ kb_fwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ i
         float cb[16], xb[16];
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-            cb[s] = rc.p[(int64_t)(L - 16 + s) * rc.stride];
+            cb[s] = *rc.at(L - 16 + s);
             xb[s] = xp[L - 16 + s];
         }
         double acc = 0.0;
@@ -387,7 +456,7 @@ kb_fwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ i
                 const double cf = rc.cvt(cb[s]);
                 const double xv = (double)xb[s];
                 const int nx = max(rel - 16 + s, 0);
-                cb[s] = rc.p[(int64_t)nx * rc.stride];
+                cb[s] = *rc.at(nx);
                 xb[s] = xp[nx];
                 acc = __builtin_fma(ss[(1 - s) & 15], xv, acc);
                 row_bwd_step<s>(cf, ss);
@@ -435,7 +504,7 @@ kb_bwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ i
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             const int r = min(s, valid - 1);
-            cb[s] = rc.p[(int64_t)r * rc.stride];
+            cb[s] = *rc.at(r);
             gb[s] = gp[r];
         }
         double acc = 0.0;
@@ -446,7 +515,7 @@ kb_bwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ i
                 const double cf = in ? rc.cvt(cb[s]) : 0.0;
                 const double gv = in ? (double)gb[s] : 0.0;
                 const int nx = min(rel + 16 + s, valid - 1);
-                cb[s] = rc.p[(int64_t)nx * rc.stride];
+                cb[s] = *rc.at(nx);
                 gb[s] = gp[nx];
                 h[s] = row_fwd_step<s>(cf, h);
                 acc = __builtin_fma(gv, h[s], acc);

@@ -126,6 +126,14 @@ struct filt_plan {
     size_t flags_n = 0;
     int64_t tiles_fwd_off[kBuckets] = {}, tiles_bwd_off[kBuckets] = {}, ntiles[kBuckets] = {};
     int64_t agg_off[kBuckets] = {}, inc_off[kBuckets] = {}, flag_off[kBuckets] = {};
+    // frame-held segments per bucket: cumulative frame counts (ns + 1) and
+    // segment ids, for the per-frame gradient pass; and an adjoint buffer
+    // for backward calls that want ga but no gx
+    int64_t *d_fr_cum = nullptr;
+    int *d_fr_sid = nullptr;
+    int64_t fr_cum_off[kBuckets] = {}, fr_sid_off[kBuckets] = {}, fr_n[kBuckets] = {},
+            fr_total[kBuckets] = {};
+    float *d_ybar = nullptr;
     // captured forward + backward
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -167,6 +175,8 @@ filt_status plan_layout(filt_plan *p)
         d.a_off = s.a_off;
         d.ic_off = s.ic_off;
         d.N = s.N;
+        d.hop = s.hop > 1 ? s.hop : 1;
+        d.fd = frame_div(d.hop);
         d.L = p->chunk[bk];
         d.C = (s.T + d.L - 1) / d.L;
         const int64_t steps = std::max<int64_t>(d.C - 1, 1);
@@ -304,7 +314,32 @@ filt_status plan_layout(filt_plan *p)
         p->cseg_n[b] = (int64_t)items.size() - p->cseg_off[b];
     }
 
+    // frame-held segments of each bucket
+    std::vector<int64_t> fr_cum;
+    std::vector<int> fr_sid;
+    for (int b = 0; b < kBuckets; ++b) {
+        p->fr_cum_off[b] = (int64_t)fr_cum.size();
+        p->fr_sid_off[b] = (int64_t)fr_sid.size();
+        int64_t tot = 0;
+        for (int i = 0; i < nseg; ++i) {
+            if (bucket_of(std::max(p->segs[i].N, 1)) != b || sd[i].fd.m == 0 || sd[i].N == 0)
+                continue;
+            fr_cum.push_back(tot);
+            fr_sid.push_back(i);
+            tot += (sd[i].T + sd[i].hop - 1) / sd[i].hop;
+        }
+        p->fr_n[b] = (int64_t)fr_sid.size() - p->fr_sid_off[b];
+        fr_cum.push_back(tot);
+        p->fr_total[b] = tot;
+    }
+
     filt_status s = to_device(p->d_segs, sd);
+    if (s != FILT_OK)
+        return s;
+    s = to_device(p->d_fr_cum, fr_cum);
+    if (s != FILT_OK)
+        return s;
+    s = to_device(p->d_fr_sid, fr_sid);
     if (s != FILT_OK)
         return s;
     s = to_device(p->d_items, items);
@@ -446,13 +481,36 @@ filt_status bucket_forward(const filt_plan *p, const float *x, const float *a, c
 
 // One bucket's backward: summaries, carry, adjoint apply (+ coefficient
 // gradients).
+// ga of the bucket's frame-held segments from the adjoint ybar.
+filt_status frame_grads_launch(const filt_plan *p, int b, const float *ybar, const float *y,
+                               const float *yi, float *ga, hipStream_t st)
+{
+    if (ga == nullptr || p->fr_total[b] == 0)
+        return FILT_OK;
+    const int64_t threads = p->fr_total[b] * 64;
+    FILT_LAUNCH(FILT_BNAME("batched_frame_grads", kBucketW[b]), kb_frame_grads,
+                dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, p->d_segs,
+                p->d_fr_cum + p->fr_cum_off[b], p->d_fr_sid + p->fr_sid_off[b], (int)p->fr_n[b],
+                p->fr_total[b], ybar, y, yi, ga);
+    return check_launch("batched frame gradients");
+}
+
 template <int W, int B>
 filt_status bucket_backward(const filt_plan *p, const float *gy, const float *y, const float *a,
                             const float *yi, float *gx, float *ga, float *gyi, hipStream_t st)
 {
-    if (p->onepass[B])
-        return onepass_backward<W>(p, B, gy, y, a, yi, gx, ga, gyi, st);
-    filt_status s = batched_bwd_summary<W>(bucket_args(p, B, a), gy, a, p->d_ws, st);
+    // frame-held rows take their gradients from the stored adjoint (gx is
+    // ybar for b = [1]); without gx it goes to the plan's own buffer
+    if (gx == nullptr && ga != nullptr && p->fr_total[B] > 0)
+        gx = p->d_ybar;
+    filt_status s = FILT_OK;
+    if (p->onepass[B]) {
+        s = onepass_backward<W>(p, B, gy, y, a, yi, gx, ga, gyi, st);
+        if (s != FILT_OK)
+            return s;
+        return frame_grads_launch(p, B, gx, y, yi, ga, st);
+    }
+    s = batched_bwd_summary<W>(bucket_args(p, B, a), gy, a, p->d_ws, st);
     if (s == FILT_OK)
         s = carry_launch(p, B, 1, nullptr, st);
     if (s != FILT_OK)
@@ -460,10 +518,14 @@ filt_status bucket_backward(const filt_plan *p, const float *gy, const float *y,
     if (gx == nullptr)
         return batched_bwd_apply<W>(bucket_args(p, B, a), gy, y, a, yi, p->d_ws, gx, ga, gyi, st);
     if constexpr (kStreamBucket<W>)
-        return batched_stream_bwd<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx,
-                                     ga, gyi, st);
-    return batched_bwd_split<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx, ga,
-                                gyi, st);
+        s = batched_stream_bwd<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx,
+                                  ga, gyi, st);
+    else
+        s = batched_bwd_split<W>(bucket_args(p, B, a), p->chunk[B], gy, y, a, yi, p->d_ws, gx,
+                                 ga, gyi, st);
+    if (s != FILT_OK)
+        return s;
+    return frame_grads_launch(p, B, gx, y, yi, ga, st);
 }
 
 // Does the plan have work in bucket b?
@@ -562,6 +624,9 @@ filt_status filt_plan_create(const filt_segment *segs, int32_t nseg, const int32
             return fail(FILT_EINVAL, "segment %d: negative size or offset", i);
         if (s.N < 0 || s.N > 16)
             return fail(s.N < 0 ? FILT_EINVAL : FILT_EUNSUPPORTED, "segment %d: order %d", i, s.N);
+        if (s.hop < 0)
+            return fail(FILT_EINVAL, "segment %d: hop %d (0 or 1: per-sample rows, h >= 2: "
+                        "frame-held rows)", i, (int)s.hop);
         if (s.T > ((int64_t)1 << 31) - 64)
             return fail(FILT_EUNSUPPORTED, "segment %d: T too large for a plan", i);
     }
@@ -587,7 +652,20 @@ filt_status filt_plan_create(const filt_segment *segs, int32_t nseg, const int32
         filt_plan_destroy(p);
         return fail(FILT_EHIP, "creating the plan's bucket streams failed");
     }
-    const filt_status s = plan_layout(p);
+    filt_status s = plan_layout(p);
+    // backward calls that want ga without gx stage the adjoint of the
+    // frame-held segments here
+    bool frames = false;
+    int64_t nybar = 0;
+    for (int i = 0; i < nseg; ++i) {
+        frames = frames || segs[i].hop > 1;
+        nybar = std::max<int64_t>(nybar, segs[i].x_off + segs[i].T);
+    }
+    if (!frames)
+        nybar = 0;
+    if (s == FILT_OK && nybar > 0 &&
+        hipMalloc((void **)&p->d_ybar, (size_t)nybar * sizeof(float)) != hipSuccess)
+        s = fail(FILT_EHIP, "hipMalloc of the plan's adjoint buffer failed");
     if (s != FILT_OK) {
         filt_plan_destroy(p);
         return s;
@@ -611,6 +689,12 @@ void filt_plan_destroy(filt_plan *p)
         hipEventDestroy(p->fork);
     if (p->d_tiles != nullptr)
         hipFree(p->d_tiles);
+    if (p->d_fr_cum != nullptr)
+        hipFree(p->d_fr_cum);
+    if (p->d_fr_sid != nullptr)
+        hipFree(p->d_fr_sid);
+    if (p->d_ybar != nullptr)
+        hipFree(p->d_ybar);
     if (p->d_flags != nullptr)
         hipFree(p->d_flags);
     if (p->d_segs != nullptr)

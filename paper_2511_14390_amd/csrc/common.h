@@ -183,6 +183,37 @@ __device__ __forceinline__ Cursor<T> cursor(const Dims &d, const T *base, int64_
     return c;
 }
 
+// Coefficient rows of channel b seen from chunk start t0: at(r) is the row
+// (K taps) that applies at time t0 + r, r >= -t0 (per-sample rows r steps
+// on; frame-held rows frame(t0 + r) - frame(t0) frames on).
+template <typename T>
+struct RowWalk {
+    const T *p;      // row of time t0
+    int64_t stride;  // elements per step (per frame when frame-held)
+    FrameDiv fd;
+    uint32_t t0, f0;
+
+    __device__ __forceinline__ const T *at(int r) const
+    {
+        if (fd.m == 0)
+            return p + (int64_t)r * stride;
+        return p + (int64_t)((int)frame_of(fd, t0 + (uint32_t)r) - (int)f0) * stride;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ RowWalk<T> row_walk(const Dims &d, const T *base, int64_t b,
+                                               int64_t t0, int K)
+{
+    RowWalk<T> w;
+    w.p = base + row_at(d, b, t0, K);
+    w.stride = (d.layout == FILT_LAYOUT_TB ? d.B : 1) * (int64_t)K;
+    w.fd = d.tv ? d.fd : FrameDiv{0u, 0};
+    w.t0 = (uint32_t)t0;
+    w.f0 = w.fd.m != 0 ? frame_of(w.fd, (uint32_t)t0) : 0u;
+    return w;
+}
+
 // Cursor over the coefficient rows (K taps) of channel b from chunk start
 // t0: per-sample rows as cursor(), frame-held rows one row per frame.
 template <typename T>

@@ -222,15 +222,42 @@ __device__ __forceinline__ void stage_signal(float *xs, const float *__restrict_
     }
 }
 
+// Start of the coefficient row of tile sample r (tile start t0): per-sample
+// rows follow the samples, frame-held rows (fd.m != 0) their frames.
+__device__ __forceinline__ int64_t tile_row(int64_t a_off, int64_t t0, const FrameDiv &fd, int r,
+                                            int N)
+{
+    const int64_t t = t0 + r;
+    return a_off + (fd.m != 0 ? (int64_t)frame_of(fd, (uint32_t)t) : t) * N;
+}
+
 // Stage the tile's coefficient rows [n][N] into LDS as [64 lanes][L][W]
 // (zero taps past N and rows past n); loads first, then the LDS stores.
+// Per-sample rows of order W (>= 4 or whole float4 pieces of several rows)
+// load as vectors; frame-held rows as vectors only when a row is one float4.
 template <int W>
-__device__ __forceinline__ void stage_rows(float *cs, const float *__restrict__ a, int64_t a0,
-                                           int n, int N, int lane)
+__device__ __forceinline__ void stage_rows(float *cs, const float *__restrict__ a, int64_t a_off,
+                                           int64_t t0, const FrameDiv &fd, int n, int N,
+                                           int lane)
 {
     using G = OnePass<W>;
     constexpr int L = G::L;
-    if (N == W && (a0 % 4) == 0 && (W * L) % 4 == 0) {
+    const int64_t a0 = a_off + t0 * N;
+    if (fd.m != 0 && N == 4 && W == 4 && (a_off % 4) == 0) {
+        constexpr int K = G::S / 64;  // one float4 (a row) per sample
+        float4 val[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int r = lane + 64 * i;
+            val[i] = r < n ? *reinterpret_cast<const float4 *>(a + tile_row(a_off, t0, fd, r, 4))
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int r = lane + 64 * i;
+            *reinterpret_cast<float4 *>(cs + (r / L) * G::CS + (r % L) * W) = val[i];
+        }
+    } else if (fd.m == 0 && N == W && (a0 % 4) == 0 && (W * L) % 4 == 0) {
         // whole float4 pieces of rows below n; the rest one float at a time
         constexpr int K = G::S * W / 4 / 64;
         const int nv = (n * W) / 4;
@@ -262,7 +289,7 @@ __device__ __forceinline__ void stage_rows(float *cs, const float *__restrict__ 
         for (int i = 0; i < K; ++i) {
             const int e = lane + 64 * i;
             const int r = e / W, tap = e % W;
-            val[i] = (r < n && tap < N) ? a[a0 + (int64_t)r * N + tap] : 0.f;
+            val[i] = (r < n && tap < N) ? a[tile_row(a_off, t0, fd, r, N) + tap] : 0.f;
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -455,7 +482,7 @@ kb_onepass_fwd(OnePassArgs A, const float *__restrict__ x, const float *__restri
 
         // 1. stage
         stage_signal<G::S, L, G::XS>(xs, x + sd.x_off + t0, n, lane);
-        stage_rows<W>(cs, a, sd.a_off + t0 * N, n, N, lane);
+        stage_rows<W>(cs, a, sd.a_off, t0, sd.fd, n, N, lane);
         __syncthreads();
         const float *xl = xs + lane * G::XS;
         const float *cl = cs + lane * G::CS;
@@ -571,11 +598,14 @@ kb_onepass_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__restr
         const int n = (int)min<int64_t>(G::S, sd.T - t0);
         const int N = sd.N;
         const int64_t rec = sd.tile_base + k;
+        // per-sample ga rows are formed here; frame-held rows get theirs
+        // from the stored adjoint in a separate pass
+        const bool want_ga = ga != nullptr && sd.fd.m == 0;
 
         // 1. stage gy, the rows and y with W samples of history per lane
         stage_signal<G::S, L, G::XS>(gs, gy + sd.x_off + t0, n, lane);
-        stage_rows<W>(cs, a, sd.a_off + t0 * N, n, N, lane);
-        if (ga != nullptr) {
+        stage_rows<W>(cs, a, sd.a_off, t0, sd.fd, n, N, lane);
+        if (want_ga) {
             // positions -W .. S-1 of the tile, K + 1 per lane (the last
             // round only for lanes below W)
             constexpr int K = G::S / 64;
@@ -680,7 +710,7 @@ kb_onepass_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__restr
             for (int i = 0; i < W; ++i)
                 sv[i] = __builtin_fma(-c[i + 1], yb, i + 1 < W ? sv[i + 1] : 0.0);
             gw[s] = (float)yb;
-            if (ga != nullptr) {
+            if (want_ga) {
 #pragma unroll
                 for (int kk = 1; kk <= W; ++kk)
                     cl[s * W + kk - 1] = (float)(-yb * (double)yl[W + s - kk]);
@@ -696,7 +726,7 @@ kb_onepass_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__restr
         if (gx != nullptr)
             for (int e = lane; e < n; e += 64)
                 gx[sd.x_off + t0 + e] = gs[(e / L) * G::XS + (e % L)];
-        if (ga != nullptr) {
+        if (want_ga) {
             const int64_t a0 = sd.a_off + t0 * N;
             if (N == W && (a0 % 4) == 0) {
                 const int nv = (n * W) / 4;

@@ -47,18 +47,20 @@ struct OnePass16 {
 
 // Stage rows [n][N] (N <= 16) as [P][L][16] with the padded sub-chunk
 // stride; every load of the tile is issued before the first LDS store.
-__device__ __forceinline__ void stage_rows16(float *cs, const float *__restrict__ a, int64_t a0,
-                                             int n, int N, int t)
+__device__ __forceinline__ void stage_rows16(float *cs, const float *__restrict__ a,
+                                             int64_t a_off, int64_t t0, const FrameDiv &fd, int n,
+                                             int N, int t)
 {
     using G = OnePass16;
-    if (N == 16 && (a0 % 4) == 0) {
+    if (N == 16 && (a_off % 4) == 0) {
         constexpr int K = G::S * 4 / G::kThreads;
         const int nv = n * 4;  // float4 pieces of the valid rows
         float4 val[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int v = t + G::kThreads * i;
-            val[i] = v < nv ? *reinterpret_cast<const float4 *>(a + a0 + 4 * (int64_t)v)
+            val[i] = v < nv ? *reinterpret_cast<const float4 *>(
+                                  a + tile_row(a_off, t0, fd, v >> 2, 16) + 4 * (v & 3))
                             : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
@@ -75,7 +77,7 @@ __device__ __forceinline__ void stage_rows16(float *cs, const float *__restrict_
         for (int i = 0; i < K; ++i) {
             const int e = t + G::kThreads * i;
             const int r = e >> 4, tap = e & 15;
-            val[i] = (r < n && tap < N) ? a[a0 + (int64_t)r * N + tap] : 0.f;
+            val[i] = (r < n && tap < N) ? a[tile_row(a_off, t0, fd, r, N) + tap] : 0.f;
         }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -271,7 +273,7 @@ kb_onepass16_fwd(OnePassArgs A, const float *__restrict__ x, const float *__rest
 
         // 1. stage
         stage_signal16(xs, x + sd.x_off + t0, n, t);
-        stage_rows16(cs, a, sd.a_off + t0 * N, n, N, t);
+        stage_rows16(cs, a, sd.a_off, t0, sd.fd, n, N, t);
         __syncthreads();
 
         // 2. row summaries: adjoint solve j of sub-chunk `row`, seeded with
@@ -425,11 +427,14 @@ kb_onepass16_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__res
         const int n = (int)min<int64_t>(G::S, sd.T - t0);
         const int N = sd.N;
         const int64_t rec = sd.tile_base + k;
+        // per-sample ga rows are formed here; frame-held rows get theirs
+        // from the stored adjoint in a separate pass
+        const bool want_ga = ga != nullptr && sd.fd.m == 0;
 
         // 1. stage gy, rows, and y with 16 samples of history per sub-chunk
         stage_signal16(gs, gy + sd.x_off + t0, n, t);
-        stage_rows16(cs, a, sd.a_off + t0 * N, n, N, t);
-        if (ga != nullptr) {
+        stage_rows16(cs, a, sd.a_off, t0, sd.fd, n, N, t);
+        if (want_ga) {
             // positions -16 .. S-1 of the tile: K per thread, one more for
             // threads below 16
             constexpr int K = G::S / G::kThreads;
@@ -561,7 +566,7 @@ kb_onepass16_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__res
                 s4[1] = __builtin_fma(-(double)a4.y, yb, s4[2]);
                 s4[2] = __builtin_fma(-(double)a4.z, yb, s4[3]);
                 s4[3] = __builtin_fma(-(double)a4.w, yb, nxt);
-                if (ga != nullptr) {
+                if (want_ga) {
                     float4 g4;
                     g4.x = (float)(-yb * (double)yp[s - 1]);
                     g4.y = (float)(-yb * (double)yp[s - 2]);
@@ -583,7 +588,7 @@ kb_onepass16_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__res
         if (gx != nullptr)
             for (int e = t; e < n; e += G::kThreads)
                 gx[sd.x_off + t0 + e] = gs[(e / L) * G::XS + (e % L)];
-        if (ga != nullptr) {
+        if (want_ga) {
             const int64_t a0 = sd.a_off + t0 * N;
             if (N == 16 && (a0 % 4) == 0) {
                 for (int v = t; v < n * 4; v += G::kThreads) {

@@ -43,7 +43,32 @@ struct StreamLds {
     int64_t osig[64], ocoef[64], oout[64];
     int64_t ln[64];
     int lN[64];  // row width (the order) of each lane's filter
+    // frame-held rows (lfm != 0): ocoef is the row of the chunk start's
+    // frame; local step s takes the row frame(lt0 + s) - lf0 frames on
+    uint32_t lt0[64], lf0[64], lfm[64];
+    int lfsh[64];
 };
+
+// Row offset (in rows) of local step tc of lane i.
+template <int W>
+__device__ __forceinline__ int64_t stream_row_of(const StreamLds<W> &L, int i, int64_t tc)
+{
+    if (L.lfm[i] == 0)
+        return tc;
+    const FrameDiv f{L.lfm[i], L.lfsh[i]};
+    return (int64_t)((int)frame_of(f, L.lt0[i] + (uint32_t)tc) - (int)L.lf0[i]);
+}
+
+// Lane i's row bookkeeping for chunk start t0 (fd.m == 0: per-sample rows).
+template <int W>
+__device__ __forceinline__ void stream_set_rows(StreamLds<W> &L, int i, int64_t t0,
+                                                const FrameDiv &fd)
+{
+    L.lt0[i] = (uint32_t)t0;
+    L.lfm[i] = fd.m;
+    L.lfsh[i] = fd.sh;
+    L.lf0[i] = fd.m != 0 ? frame_of(fd, (uint32_t)t0) : 0u;
+}
 
 // The arrays the lane offsets refer to.
 struct StreamPtrs {
@@ -107,7 +132,8 @@ __device__ __forceinline__ void stream_load(const StreamLds<W> &L, const StreamP
             const int64_t t = lo + s;
             // clamp into the lane's chunk (its first row when it has none)
             const int64_t tc = stream_clamp(t, n);
-            r.c[j] = *reinterpret_cast<const float4 *>(P.coef + L.ocoef[i] + tc * W + (4 * q) % W);
+            r.c[j] = *reinterpret_cast<const float4 *>(P.coef + L.ocoef[i] +
+                                                        stream_row_of(L, i, tc) * W + (4 * q) % W);
             if (j % 32 == 0)
                 r.okc[j / 32] = 0;
             r.okc[j / 32] |= ((t >= 0 && t < n) ? 1u : 0u) << (j % 32);
@@ -123,7 +149,7 @@ __device__ __forceinline__ void stream_load(const StreamLds<W> &L, const StreamP
             const int64_t t = lo + s;
             const int64_t tc = stream_clamp(t, n);
             const int kc = k < Ni ? k : 0;
-            r.c[j] = P.coef[L.ocoef[i] + tc * Ni + kc];
+            r.c[j] = P.coef[L.ocoef[i] + stream_row_of(L, i, tc) * Ni + kc];
             if (j % 32 == 0)
                 r.okc[j / 32] = 0;
             r.okc[j / 32] |= ((k < Ni && t >= 0 && t < n) ? 1u : 0u) << (j % 32);
@@ -337,7 +363,8 @@ k_stream_fwd(Dims d, const float *__restrict__ x, const float *__restrict__ a,
     const int64_t c = act ? idx % d.C : 0, b = act ? idx / d.C : 0;
     const int64_t t0 = c * d.L;
     L.osig[i] = b * d.T + t0;
-    L.ocoef[i] = (b * d.T + t0) * d.N;
+    L.ocoef[i] = row_at(d, b, t0, d.N);
+    stream_set_rows(L, i, t0, d.fd);
     L.oout[i] = b * d.T + t0;
     L.ln[i] = act ? min(d.L, d.T - t0) : 0;
     L.lN[i] = d.N;
@@ -368,7 +395,8 @@ k_stream_bwd(Dims d, const float *__restrict__ gy, const float *__restrict__ a,
     const int64_t c = act ? idx % d.C : 0, b = act ? idx / d.C : 0;
     const int64_t t0 = c * d.L;
     L.osig[i] = b * d.T + t0;
-    L.ocoef[i] = (b * d.T + t0) * d.N;
+    L.ocoef[i] = row_at(d, b, t0, d.N);
+    stream_set_rows(L, i, t0, d.fd);
     L.oout[i] = b * d.T + t0;
     L.ln[i] = act ? min(d.L, d.T - t0) : 0;
     L.lN[i] = d.N;
@@ -390,8 +418,7 @@ k_stream_bwd(Dims d, const float *__restrict__ gy, const float *__restrict__ a,
 // per lane and step, and the direct path keeps more of them in flight).
 inline bool stream_eligible(const Dims &d)
 {
-    return d.tv && d.fd.m == 0 && d.layout == FILT_LAYOUT_BT && !d.has_b && d.M == 0 &&
-           d.N > 0 && d.N <= 8;
+    return d.tv && d.layout == FILT_LAYOUT_BT && !d.has_b && d.M == 0 && d.N > 0 && d.N <= 8;
 }
 
 template <int W>

@@ -420,9 +420,10 @@ __device__ __forceinline__ void row_bwd_step(double c, double (&ss)[16])
 // and the reads stop at its end.
 template <typename io_t, bool FULL>
 struct RowCoef {
-    const io_t *p;   // tap of this lane at the chunk's first step
-    int64_t stride;  // elements per time step
+    RowWalk<io_t> w; // this lane's tap: at(r) is its value's address at step r
     bool live;       // j < N
+
+    __device__ __forceinline__ const io_t *at(int r) const { return w.at(r); }
 
     __device__ __forceinline__ double cvt(io_t raw) const
     {
@@ -439,9 +440,8 @@ __device__ __forceinline__ RowCoef<io_t, FULL> row_coef(const Dims &d, const io_
     RowCoef<io_t, FULL> r;
     const int64_t t0 = c * d.L;
     const int jj = j < d.N ? j : d.N - 1;
-    const bool tb = d.layout == FILT_LAYOUT_TB;
-    r.p = ac + (tb ? t0 * d.B + b : b * d.T + t0) * (int64_t)d.N + jj;
-    r.stride = (tb ? d.B : 1) * (int64_t)d.N;
+    r.w = row_walk(d, ac, b, t0, d.N);
+    r.w.p += jj;
     r.live = j < d.N;
     return r;
 }
@@ -460,14 +460,14 @@ __device__ __forceinline__ void fwd_row_item(const Dims &d, const io_t *__restri
     io_t buf[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s)
-        buf[s] = rc.p[s * rc.stride];
+        buf[s] = *rc.at(s);
     for (int rel = 0; rel < d.L; rel += 16) {
         static_for<16>([&](auto I) {
             constexpr int s = decltype(I)::value;
             const double cf = rc.cvt(buf[s]);
             // step rel + 16 + s; the last block re-reads the chunk's last row
             // (unconditional loads keep the ring free of merges and waits)
-            buf[s] = rc.p[(int64_t)min(rel + 16 + s, (int)d.L - 1) * rc.stride];
+            buf[s] = *rc.at(min(rel + 16 + s, (int)d.L - 1));
             h[s] = row_fwd_step<s>(cf, h);
             __builtin_amdgcn_sched_barrier(0);
         });
@@ -506,16 +506,15 @@ __device__ __forceinline__ void bwd_row_item(const Dims &d, const io_t *__restri
     for (int e = 0; e < 16; ++e)
         ss[e] = (rc.live && e == ((j + 2) & 15)) ? 1.0 : 0.0;
     io_t buf[16];
-    const io_t *top = rc.p + (int64_t)(d.L - 16) * rc.stride;
 #pragma unroll
     for (int s = 0; s < 16; ++s)
-        buf[s] = top[s * rc.stride];
+        buf[s] = *rc.at((int)d.L - 16 + s);
     for (int rel = d.L - 16; rel >= 0; rel -= 16) {
         static_for<16>([&](auto I) {
             constexpr int s = 15 - decltype(I)::value;
             const double cf = rc.cvt(buf[s]);
             // step rel - 16 + s; the last block re-reads the chunk's first row
-            buf[s] = rc.p[(int64_t)max(rel - 16 + s, 0) * rc.stride];
+            buf[s] = *rc.at(max(rel - 16 + s, 0));
             row_bwd_step<s>(cf, ss);
             __builtin_amdgcn_sched_barrier(0);
         });
@@ -584,14 +583,14 @@ __device__ __forceinline__ void fwd_rows_group(const Dims &d, const io_t *__rest
         io_t buf[16];
 #pragma unroll
         for (int s = 0; s < 16; ++s)
-            buf[s] = rc.p[s * rc.stride];
+            buf[s] = *rc.at(s);
         // steps 8 HH .. 8 HH + 7 of the block at rel; raw values to hand[HH]
         auto half = [&](auto HH, int rel) {
             static_for<kHandSteps>([&](auto I) {
                 constexpr int s = decltype(HH)::value * kHandSteps + decltype(I)::value;
                 hand[decltype(HH)::value][decltype(I)::value][row][j] = buf[s];
                 const double cf = rc.cvt(buf[s]);
-                buf[s] = rc.p[(int64_t)min(rel + 16 + s, (int)d.L - 1) * rc.stride];
+                buf[s] = *rc.at(min(rel + 16 + s, (int)d.L - 1));
                 h[s] = row_fwd_step<s>(cf, h);
                 __builtin_amdgcn_sched_barrier(0);
             });
@@ -619,13 +618,14 @@ __device__ __forceinline__ void fwd_rows_group(const Dims &d, const io_t *__rest
     const int64_t e0 = tb ? c * d.L * d.B + b : b * d.T + c * d.L;
     const int64_t es = tb ? d.B : 1;
     const io_t *xp = x + e0;
-    const io_t *gp = HASB ? bc + e0 : xp;  // order-0 FIR part: one tap per row
+    // order-0 FIR part: one tap per row (b_0)
+    const RowWalk<io_t> bw = row_walk(d, HASB ? bc : x, b, c * d.L, HASB ? 1 : 0);
     io_t xb[16], gb[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         xb[s] = xp[s * es];
         if constexpr (HASB)
-            gb[s] = gp[s * es];
+            gb[s] = *bw.at(s);
     }
     double w[4] = {0.0, 0.0, 0.0, 0.0};  // w[i] = y[t - 4q - 1 - i]
     // steps 8 HH .. 8 HH + 7 of the block at rel, taps from hand[HH]
@@ -650,7 +650,7 @@ __device__ __forceinline__ void fwd_rows_group(const Dims &d, const io_t *__rest
             const int nx = min(rel + 16 + s, (int)d.L - 1);
             xb[s] = xp[nx * es];
             if constexpr (HASB)
-                gb[s] = gp[nx * es];
+                gb[s] = *bw.at(nx);
             double p = 0.0;
 #pragma unroll
             for (int i = 3; i >= 0; --i)
@@ -698,11 +698,10 @@ __device__ __forceinline__ void bwd_part_quad(const Dims &d, const io_t *__restr
     const int64_t es = tb ? d.B : 1;
     const int last = CLAMP ? (int)min<int64_t>(d.T - 1 - c * d.L, d.L - 1) : d.L - 1;
     const io_t *gp = gy + e0;
-    const io_t *ap = ac + e0 * N;
-    const int64_t as = es * N;
+    const RowWalk<io_t> aw = row_walk(d, ac, b, c * d.L, N);
     auto fetch = [&](int rel, QuadRaw<io_t> &r) {
         const int rc = CLAMP ? min(rel, last) : rel;
-        quad_taps<AV>(ap + rc * as, q, N, r.a);
+        quad_taps<AV>(aw.at(rc), q, N, r.a);
         const io_t g = gp[rc * es];
         r.s = (!CLAMP || rel <= last) ? g : io_t(0);
     };
@@ -817,7 +816,7 @@ filt_status fwd_summary_fir(const Dims &d, const io_t *x, const io_t *xi, const 
     const int N = d.N;
     const int64_t ncs = d.C - 1;  // chunks with a successor
     if constexpr (W == 16) {
-        if (d.tv && d.fd.m == 0) {
+        if (d.tv) {
             const unsigned gr = (unsigned)((d.B * ncs + kRowGroupChunks - 1) / kRowGroupChunks);
 #define FILT_ROWS(AV, FULL)                                                                        \
     FILT_LAUNCH("fwd_summary", (k_fwd_summary_rows<FIR, AV, FULL, io_t>), dim3(gr),               \
@@ -872,7 +871,7 @@ filt_status bwd_summary_fir(const Dims &d, const io_t *gy, const io_t *bc, const
     const int N = d.N;
     const int64_t ncs = d.C - 1;  // chunks 1..C-1 pass a state to an earlier chunk
     if constexpr (W == 16 && !FIR) {
-        if (d.tv && d.fd.m == 0) {
+        if (d.tv) {
             const unsigned gr = (unsigned)((d.B * ncs + kRowGroupChunks - 1) / kRowGroupChunks);
 #define FILT_ROWS(AV, FULL)                                                                        \
     FILT_LAUNCH("bwd_summary", (k_bwd_summary_rows<AV, FULL, io_t>), dim3(gr),                    \

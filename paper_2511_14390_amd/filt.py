@@ -278,7 +278,7 @@ def profile_read(max_entries: int = 64):
 
 class FiltSegment(ctypes.Structure):
     _fields_ = [("x_off", ctypes.c_int64), ("T", ctypes.c_int64), ("a_off", ctypes.c_int64),
-                ("ic_off", ctypes.c_int64), ("N", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("ic_off", ctypes.c_int64), ("N", ctypes.c_int32), ("hop", ctypes.c_int32)]
 
 
 def _plan_lib():
@@ -307,18 +307,21 @@ def _plan_lib():
 
 
 class BatchedFilter:
-    """Many independent all-pole filters with per-sample coefficients, packed
-    into flat tensors (see filt_segment in include/filt.h): segment i covers
-    x[x_off[i] : x_off[i] + T[i]], its rows a[a_off[i] : a_off[i] + T[i]*N[i]]
-    ([T_i, N_i] row-major) and yi[ic_off[i] : ic_off[i] + N[i]]."""
+    """Many independent all-pole filters with per-sample or frame-held
+    coefficients, packed into flat tensors (see filt_segment in
+    include/filt.h): segment i covers x[x_off[i] : x_off[i] + T[i]], its rows
+    a[a_off[i] : a_off[i] + R_i*N[i]] ([R_i, N_i] row-major, R_i = T[i], or
+    ceil(T[i] / hop) with hop >= 2) and yi[ic_off[i] : ic_off[i] + N[i]].
+    hop is one value for every segment or a sequence of one per segment."""
 
-    def __init__(self, T, N, x_off, a_off, ic_off, chunks=None):
+    def __init__(self, T, N, x_off, a_off, ic_off, chunks=None, hop=1):
         L = _plan_lib()
         n = len(T)
+        hops = [int(hop)] * n if not hasattr(hop, "__len__") else [int(h) for h in hop]
         segs = (FiltSegment * max(n, 1))()
         for i in range(n):
             segs[i] = FiltSegment(int(x_off[i]), int(T[i]), int(a_off[i]), int(ic_off[i]),
-                                  int(N[i]), 0)
+                                  int(N[i]), hops[i])
         ch = None
         if chunks is not None:
             ch = (ctypes.c_int32 * 5)(*[int(c) for c in chunks])

@@ -187,6 +187,8 @@ def test_plan_create_rejects_bad_segments_on_host(L):
     assert L.filt_plan_create(bad_order, 1, None, ctypes.byref(h)) == F.FILT_EUNSUPPORTED
     bad_len = (F.FiltSegment * 1)(F.FiltSegment(0, -1, 0, 0, 2, 0))
     assert L.filt_plan_create(bad_len, 1, None, ctypes.byref(h)) == F.FILT_EINVAL
+    bad_hop = (F.FiltSegment * 1)(F.FiltSegment(0, 100, 0, 0, 2, -3))
+    assert L.filt_plan_create(bad_hop, 1, None, ctypes.byref(h)) == F.FILT_EINVAL
     bad_chunk = (ctypes.c_int32 * 5)(48, 64, 64, 64, 64)
     ok = (F.FiltSegment * 1)(F.FiltSegment(0, 100, 0, 0, 2, 0))
     assert L.filt_plan_create(ok, 1, (ctypes.c_int32 * 5)(-2, 64, 64, 64, 64),
@@ -233,12 +235,12 @@ def test_empty_backward_is_ok_on_host(L):
     assert rc == F.FILT_OK
 
 
-def test_plan_api_is_all_pole_per_sample(L):
-    # the batched plan covers filters with b = [1] (M = 0) and per-sample
-    # coefficients only: its segment descriptor has no FIR order and the plan
-    # calls take no b / xi / gb / gxi
+def test_plan_api_is_all_pole(L):
+    # the batched plan covers filters with b = [1] (M = 0) and per-sample or
+    # frame-held coefficients: its segment descriptor has no FIR order and the
+    # plan calls take no b / xi / gb / gxi
     F._plan_lib()
     fields = [f[0] for f in F.FiltSegment._fields_]
-    assert fields == ["x_off", "T", "a_off", "ic_off", "N", "reserved"]
+    assert fields == ["x_off", "T", "a_off", "ic_off", "N", "hop"]
     assert len(L.filt_plan_forward.argtypes) == 6
     assert len(L.filt_plan_backward.argtypes) == 9
