@@ -14,6 +14,9 @@ graph), and the FP64 CPU oracle on the host's cores.
 The other workloads (``--workload``): the per-sample order-16 filter
 (64 x 48000), the time-invariant M = N = 4 filter on [65536, 1024] and the
 long narrow order-4 filter (2 x 2^22), through the autograd.Function.
+``--frames`` runs the per-sample workloads (batched-ragged, ltv-allpole-n16)
+with their coefficients given as frame rows (one row per hop, the gradients
+of the coefficients per frame) instead of per-sample rows.
 
 Prints one JSON line with the dominant kernel's achieved HBM bandwidth
 (algorithmic bytes per launch / its average duration, timed with HIP events
@@ -55,6 +58,9 @@ def parse():
     ap.add_argument("--f32-state", action="store_true")
     ap.add_argument("--toeplitz", action="store_true",
                     help="time-invariant [B, T] workloads: the opt-in FP32 matrix-core path")
+    ap.add_argument("--frames", action="store_true",
+                    help="batched-ragged: the coefficients as frame rows (one per hop of 128 "
+                         "samples, gradients per frame) instead of per-sample rows")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -63,9 +69,14 @@ def parse():
     return ap.parse_args()
 
 
-def make_problem(name):
+def make_problem(name, frames=False):
     from paper_2511_14390_amd import workloads as W
 
+    if frames:
+        if name != "ltv-allpole-n16":
+            raise SystemExit("--frames applies to the per-sample workloads (ltv-allpole-n16, "
+                             "batched-ragged)")
+        return W.config2(frames=True)
     return {"ltv-allpole-n16": W.config2, "lti-allpole-n2": W.config1,
             "lti-df-m4n4": W.config3, "lti-allpole-n4-long": W.config4}[name]()
 
@@ -89,7 +100,9 @@ def kernel_bytes(p, name):
     are 4 B/sample; per-sample coefficients 4*K B/sample."""
     K_a = p.N
     K_b = (p.M + 1) if p.b is not None else 0
-    coef = 4 * (K_a + K_b) if p.time_varying else 0
+    # per-sample rows, or frame rows (one per hop samples)
+    hop = int(p.meta.get("hop", 1)) if p.meta.get("frames") else 1
+    coef = 4 * (K_a + K_b) / hop if p.time_varying else 0
     fir = 4 if p.M > 0 else 0
     W = 1
     while W < max(p.N, p.M + 1):
@@ -113,6 +126,9 @@ def kernel_bytes(p, name):
         "stream_bwd_apply": 4 + coef + 4,
         # per-sample coefficient gradients: read ybar and y, write the rows
         "coef_grads": 4 + 4 + coef,
+        # frame-held rows: read ybar and y (x too with an FIR part), write
+        # one row per frame
+        "frame_coef_grads": 4 + 4 + fir + coef,
         # backward: read gy, y (+ x for M > 0) and coefficients; write gx and
         # the per-sample coefficient gradients (split: read gy, the row, write
         # gx, the products left to coef_grads)
@@ -172,10 +188,11 @@ def counted_traffic(workload, layout, chunk, kernel):
 
 def batched_kernel_bytes(s, chunks, name):
     """Algorithmic bytes of one launch of a batched kernel (name ends in the
-    order bucket, e.g. ``batched_fwd_apply_w16``): the per-sample bytes of
-    that phase (signals 4 B, coefficient rows 4 N B) summed over the bucket's
-    segments and the samples the phase covers.  None for the carry kernels
-    (they move O(N^2) doubles per chunk, not samples)."""
+    order bucket, e.g. ``batched_fwd_apply_w16``): the bytes of that phase
+    (signals 4 B per sample, coefficient rows 4 N B per row: one row per
+    sample, or per frame of hop samples for frame-held rows) summed over the
+    bucket's segments and the samples the phase covers.  None for the carry
+    kernels (they move O(N^2) doubles per chunk, not samples)."""
     import numpy as np
 
     kind, _, w = name.rpartition("_w")
@@ -183,14 +200,16 @@ def batched_kernel_bytes(s, chunks, name):
         return None
     W = int(w)
     bucket = {1: 0, 2: 1, 4: 2, 8: 3, 16: 4}[W]
-    L = chunks[bucket]
+    L = max(chunks[bucket], 1)
     Wb = np.maximum(1, 2 ** np.ceil(np.log2(np.maximum(s.N, 1)))).astype(np.int64)
     sel = Wb == W
     T = s.T[sel].astype(np.float64)
     N = s.N[sel].astype(np.float64)
+    rows = np.asarray(s.rows, np.float64)[sel] / np.maximum(T, 1)  # rows per sample
     C = np.ceil(T / L)
     # the forward summarises chunks 0..C-2, the adjoint chunks 1..C-1
     summ = np.maximum(T - L, 0) * (C > 1)
+    frames = bool(s.meta.get("frames"))
     per = {
         # read the signal and the coefficient rows
         "batched_fwd_summary": (summ, 4, 4),
@@ -198,17 +217,22 @@ def batched_kernel_bytes(s, chunks, name):
         # read x and the rows, write y
         "batched_fwd_apply": (T, 8, 4),
         "batched_stream_fwd": (T, 8, 4),
+        "batched_onepass_fwd": (T, 8, 4),
         # read gy and the rows, write gx (= ybar for b = [1]); the per-sample
         # products go to coef_grads
         "batched_bwd_apply": (T, 8, 4),
         "batched_stream_bwd": (T, 8, 4),
+        # single pass: read gy and the rows, write gx and (per-sample rows)
+        # the ga rows, reading y for them
+        "batched_onepass_bwd": (T, 8 if frames else 12, 4 if frames else 8),
         # read ybar and y, write the ga rows
         "batched_coef_grads": (T, 8, 4),
+        "batched_frame_grads": (T, 8, 4),
     }.get(kind)
     if per is None:
         return None
     n, sig, coef = per
-    return float((n * (sig + coef * N)).sum())
+    return float((n * (sig + coef * N * rows)).sum())
 
 
 def cpu_model():
@@ -231,10 +255,18 @@ def batched_cpu_baseline(s, seconds):
 
     import oracle
 
+    hop = int(s.meta["hop"]) if s.meta.get("frames") else 1
+
     def one(i):
         x, a, yi, gy = s.segment(i)
         x64, a64, gy64 = (np.asarray(v, np.float64)[None] for v in (x, a, gy))
         yi64 = np.asarray(yi, np.float64)[None] if len(yi) else None
+        if hop > 1:
+            y = oracle.forward_frames(x64, a64, None, None, yi64, hop=hop, layout="BT",
+                                      nthreads=1)
+            oracle.backward_frames(gy64, x64, y, a64, None, None, yi64, hop=hop, layout="BT",
+                                   want=("x", "a", "yi"), nthreads=1)
+            return
         y = oracle.forward(x64, a64, None, None, yi64, layout="BT", nthreads=1)
         oracle.backward(gy64, x64, y, a64, None, None, yi64, layout="BT", want=("x", "a", "yi"),
                         nthreads=1)
@@ -273,7 +305,9 @@ def batched_main(args):
     from paper_2511_14390_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    s = W.config5()
+    s = W.config5(frames=args.frames)
+    hop = int(s.meta["hop"]) if args.frames else 1
+    workload = "batched-ragged-frames" if args.frames else "batched-ragged"
     t = lambda v: torch.from_numpy(v).to(dev)
     x, a, yi, gy = t(s.x), t(s.a), t(s.yi), t(s.gy)
     samples = int(s.T.sum())
@@ -281,10 +315,10 @@ def batched_main(args):
         # fixed chunk lengths (no tuning)
         fixed = ([int(v) for v in args.bucket_chunks.split(",")] if args.bucket_chunks
                  else [args.chunk] * 5)
-        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off, chunks=fixed)
+        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off, chunks=fixed, hop=hop)
         chunks = plan.chunks
     else:
-        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off)
+        plan = F.BatchedFilter(s.T, s.N, s.x_off, s.a_off, s.ic_off, hop=hop)
         chunks = plan.tune(x, a, yi, gy)
     y = torch.empty_like(x)
     gx = torch.empty_like(x)
@@ -359,22 +393,21 @@ def batched_main(args):
             roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4),
-                        "traffic": counted_traffic("batched-ragged", "packed",
-                                                   chunks[4], dom),
+                        "traffic": counted_traffic(workload, "packed", chunks[4], dom),
                         "bytes_per_launch": per_launch, "avg_launch_us": round(avg_us, 2)}
 
     # plain: one dense forward + backward call per filter, eager and captured
-    segs = [(int(s.T[i]), int(s.N[i]), int(s.x_off[i]), int(s.a_off[i]), int(s.ic_off[i]))
-            for i in range(len(s.T))]
+    segs = [(int(s.T[i]), int(s.N[i]), int(s.x_off[i]), int(s.a_off[i]), int(s.ic_off[i]),
+             int(s.rows[i])) for i in range(len(s.T))]
 
     def plain_step():
-        for (tt, n, xo, ao, io) in segs:
+        for (tt, n, xo, ao, io, r) in segs:
             xs = x[xo:xo + tt][None]
-            as_ = a[ao:ao + tt * n].view(1, tt, n)
+            as_ = a[ao:ao + r * n].view(1, r, n)
             yis = yi[io:io + n][None]
-            ys = F.filt_forward(xs, as_, None, None, yis, layout="BT")
+            ys = F.filt_forward(xs, as_, None, None, yis, layout="BT", hop=hop)
             F.filt_backward(gy[xo:xo + tt][None], xs, ys, as_, None, None, yis, layout="BT",
-                            want=("x", "a", "yi"))
+                            hop=hop, want=("x", "a", "yi"))
 
     plain_ms = plain_graph_ms = None
     if args.plain_steps > 0:
@@ -406,7 +439,7 @@ def batched_main(args):
         except Exception as e:  # reported, not fatal
             print(f"plain loop graph capture failed: {e}", file=sys.stderr, flush=True)
 
-    coef = 4 * float((s.T * s.N).sum())
+    coef = 4 * float((np.asarray(s.rows) * s.N).sum())
     # forward: x, y, the rows; backward: gy, y, gx, the rows read, ga written
     algo = 4 * samples * 2 + coef + (4 * samples * 3 + 2 * coef)
     cpu = None if args.no_cpu_baseline else batched_cpu_baseline(s, args.cpu_seconds)
@@ -415,9 +448,11 @@ def batched_main(args):
         "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "batched-ragged", "io": "f32", "segments": len(s.T),
+        "config": {"workload": workload, "io": "f32", "segments": len(s.T),
                    "samples": samples, "T_range": [int(s.T.min()), int(s.T.max())],
                    "orders": sorted(set(int(n) for n in s.N)), "hop": s.meta["hop"],
+                   "coefficients": ("frame rows (one per hop, gradients per frame)"
+                                    if args.frames else "per-sample rows"),
                    "chunks_by_order_bucket": chunks, "timed": "hip graph replay",
                    "parallelism": "single GPU"},
         "roofline": roofline,
@@ -450,7 +485,8 @@ def main():
     from paper_2511_14390_amd import filt as F
 
     dev = torch.device("cuda:0")
-    p = make_problem(args.workload)
+    p = make_problem(args.workload, args.frames)
+    hop = int(p.meta["hop"]) if args.frames else 1
     # the per-sample workload runs channel-interleaved ([T, B]): one wavefront
     # then reads 64 channels' coefficient rows of one time step as one block
     layout = args.layout or ("TB" if args.workload == "ltv-allpole-n16" else p.layout)
@@ -467,7 +503,7 @@ def main():
 
     def step():
         y = AG.lfilter(x, a, b, xi, yi, layout=p.layout, chunk=args.chunk,
-                       f32_state=args.f32_state, toeplitz=args.toeplitz)
+                       f32_state=args.f32_state, toeplitz=args.toeplitz, hop=hop)
         inputs = [v for v in (x, a, b, xi, yi) if v is not None]
         torch.autograd.grad(y, inputs, gy)
 
@@ -515,7 +551,8 @@ def main():
                      "total_ms_per_step": ms / args.steps, "timed_region": True}
 
     roofline = None
-    chunk = F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk, toeplitz=args.toeplitz))
+    chunk = F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk, toeplitz=args.toeplitz,
+                                   hop=hop))
     if dom is not None and kernel_flops(p, dom, chunk) is not None:
         # the dominant kernel is bound by FP64 vector arithmetic (SQ counters:
         # VALU issue), so it is measured against the FP64 vector peak
@@ -524,14 +561,16 @@ def main():
         roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2),
                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(ach / FP64_VALU_PEAK_TFLOPS, 4),
-                    "traffic": counted_traffic(args.workload, p.layout, chunk, dom),
+                    "traffic": counted_traffic(args.workload + ("-frames" if hop > 1 else ""),
+                                               p.layout, chunk, dom),
                     "flops_per_launch": flop, "avg_launch_us": round(kern[dom]["avg_us"], 2)}
     elif dom is not None and kernel_bytes(p, dom) is not None:
         per_launch = kernel_bytes(p, dom) * samples
         ach = per_launch / (kern[dom]["avg_us"] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": counted_traffic(args.workload, p.layout, chunk, dom),
+                    "traffic": counted_traffic(args.workload + ("-frames" if hop > 1 else ""),
+                                               p.layout, chunk, dom),
                     "bytes_per_launch": per_launch,
                     "avg_launch_us": round(kern[dom]["avg_us"], 2)}
 
@@ -545,8 +584,15 @@ def main():
         xs, as_, bs, xis, yis, gys = map(f64, (p.x, p.a, p.b, p.xi, p.yi, p.gy))
         reps, c0 = 0, time.perf_counter()
         while True:
-            yo = oracle.forward(xs, as_, bs, xis, yis, layout=p.layout, nthreads=nthreads)
-            oracle.backward(gys, xs, yo, as_, bs, xis, yis, layout=p.layout, nthreads=nthreads)
+            if hop > 1:
+                yo = oracle.forward_frames(xs, as_, bs, xis, yis, hop=hop, layout=p.layout,
+                                           nthreads=nthreads)
+                oracle.backward_frames(gys, xs, yo, as_, bs, xis, yis, hop=hop, layout=p.layout,
+                                       nthreads=nthreads)
+            else:
+                yo = oracle.forward(xs, as_, bs, xis, yis, layout=p.layout, nthreads=nthreads)
+                oracle.backward(gys, xs, yo, as_, bs, xis, yis, layout=p.layout,
+                                nthreads=nthreads)
             reps += 1
             if time.perf_counter() - c0 >= args.cpu_seconds:
                 break
@@ -563,8 +609,9 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-state" if args.f32_state else ("f32-mfma" if args.toeplitz else "f64"),
         "data": "synthetic",
-        "config": {"workload": p.name, "io": "f32", "B": p.B, "T": p.T, "M": p.M, "N": p.N,
-                   "time_varying": bool(p.time_varying), "layout": p.layout,
+        "config": {"workload": p.name + ("-frames" if hop > 1 else ""), "io": "f32", "B": p.B,
+                   "T": p.T, "M": p.M, "N": p.N,
+                   "time_varying": bool(p.time_varying), "hop": hop, "layout": p.layout,
                    "chunk": chunk,
                    "parallelism": "single GPU"},
         "roofline": roofline,

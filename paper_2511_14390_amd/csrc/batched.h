@@ -343,64 +343,21 @@ kb_coef_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items, 
     }
 }
 
-// Frame-held rows: ga of every frame of the bucket's frame-held segments
-// from the stored adjoint, ga_k[f] = -sum_{t in f} ybar[t] y[t-k] (Sec. 3.1
-// Eq. 8 summed over the frame).  One wavefront per frame: lanes take the
-// frame's samples, then the wavefront adds each tap's 64 partial sums.
-// Frame w of the bucket belongs to the segment sid[k] with
-// cum[k] <= w < cum[k + 1] (binary search over the ns segments).
-static __global__ void __launch_bounds__(256)
-kb_frame_grads(const SegDesc *__restrict__ segs, const int64_t *__restrict__ cum,
-               const int *__restrict__ sid, int ns, int64_t nf, const float *__restrict__ ybar,
-               const float *__restrict__ y, const float *__restrict__ yi, float *__restrict__ ga)
+// Frame-held rows: ga of the bucket's frame-held segments from the stored
+// adjoint, ga_k[f] = -sum_{t in f} ybar[t] y[t-k] (Sec. 3.1 Eq. 8 summed over
+// the frame).  One wavefront (workgroup) per item (segment, first frame,
+// frames <= 64).
+static __global__ void __launch_bounds__(64)
+kb_frame_grads(const SegDesc *__restrict__ segs, const Item *__restrict__ items,
+               const float *__restrict__ ybar, const float *__restrict__ y,
+               const float *__restrict__ yi, float *__restrict__ ga)
 {
-    const int64_t w = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (w >= nf)
-        return;  // whole wavefronts
-    int lo = 0, hi = ns - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (cum[mid] <= w)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const SegDesc sd = segs[sid[lo]];
-    const int64_t f = w - cum[lo];
-    const int64_t t0 = f * sd.hop, t1 = min(t0 + sd.hop, sd.T);
-    const int N = sd.N;
-    double acc[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-        acc[j] = 0.0;
-    for (int64_t t = t0 + lane; t < t1; t += 64) {
-        const double yb = (double)ybar[sd.x_off + t];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            if (j < N) {
-                const int64_t u = t - 1 - j;
-                float v = 0.f;
-                if (u >= 0)
-                    v = y[sd.x_off + u];
-                else if (yi != nullptr)
-                    v = yi[sd.ic_off + (-u - 1)];
-                acc[j] = __builtin_fma(yb, (double)v, acc[j]);
-            }
-        }
-    }
-    float *o = ga + sd.a_off + f * N;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        if (j < N) {
-            double v = acc[j];
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1)
-                v += __shfl_xor(v, m, 64);
-            if (lane == 0)
-                o[j] = (float)(-v);
-        }
-    }
+    __shared__ float lds[kFrameLds];
+    const Item it = items[blockIdx.x];
+    const SegDesc sd = segs[it.seg];
+    frame_sums_wave(ybar + sd.x_off, y + sd.x_off, yi != nullptr ? yi + sd.ic_off : nullptr,
+                    sd.N, 1, sd.N, -1.0, sd.T, sd.hop, (int64_t)it.chunk, it.lane,
+                    ga + sd.a_off, lds, (int)threadIdx.x);
 }
 
 // Launch geometry of a grid-stride kernel over n items.

@@ -126,13 +126,10 @@ struct filt_plan {
     size_t flags_n = 0;
     int64_t tiles_fwd_off[kBuckets] = {}, tiles_bwd_off[kBuckets] = {}, ntiles[kBuckets] = {};
     int64_t agg_off[kBuckets] = {}, inc_off[kBuckets] = {}, flag_off[kBuckets] = {};
-    // frame-held segments per bucket: cumulative frame counts (ns + 1) and
-    // segment ids, for the per-frame gradient pass; and an adjoint buffer
-    // for backward calls that want ga but no gx
-    int64_t *d_fr_cum = nullptr;
-    int *d_fr_sid = nullptr;
-    int64_t fr_cum_off[kBuckets] = {}, fr_sid_off[kBuckets] = {}, fr_n[kBuckets] = {},
-            fr_total[kBuckets] = {};
+    // frame-held segments per bucket: items (segment, first frame, frames)
+    // of the per-frame gradient pass; and an adjoint buffer for backward
+    // calls that want ga but no gx
+    int64_t fr_off[kBuckets] = {}, fr_n[kBuckets] = {};
     float *d_ybar = nullptr;
     // captured forward + backward
     hipGraph_t graph = nullptr;
@@ -314,32 +311,20 @@ filt_status plan_layout(filt_plan *p)
         p->cseg_n[b] = (int64_t)items.size() - p->cseg_off[b];
     }
 
-    // frame-held segments of each bucket
-    std::vector<int64_t> fr_cum;
-    std::vector<int> fr_sid;
+    // per-frame gradient items of each bucket's frame-held segments
     for (int b = 0; b < kBuckets; ++b) {
-        p->fr_cum_off[b] = (int64_t)fr_cum.size();
-        p->fr_sid_off[b] = (int64_t)fr_sid.size();
-        int64_t tot = 0;
+        p->fr_off[b] = (int64_t)items.size();
         for (int i = 0; i < nseg; ++i) {
             if (bucket_of(std::max(p->segs[i].N, 1)) != b || sd[i].fd.m == 0 || sd[i].N == 0)
                 continue;
-            fr_cum.push_back(tot);
-            fr_sid.push_back(i);
-            tot += (sd[i].T + sd[i].hop - 1) / sd[i].hop;
+            const int64_t F = (sd[i].T + sd[i].hop - 1) / sd[i].hop;
+            for (int64_t f0 = 0; f0 < F; f0 += 64)
+                items.push_back(Item{i, (int32_t)f0, (int32_t)std::min<int64_t>(64, F - f0), 0});
         }
-        p->fr_n[b] = (int64_t)fr_sid.size() - p->fr_sid_off[b];
-        fr_cum.push_back(tot);
-        p->fr_total[b] = tot;
+        p->fr_n[b] = (int64_t)items.size() - p->fr_off[b];
     }
 
     filt_status s = to_device(p->d_segs, sd);
-    if (s != FILT_OK)
-        return s;
-    s = to_device(p->d_fr_cum, fr_cum);
-    if (s != FILT_OK)
-        return s;
-    s = to_device(p->d_fr_sid, fr_sid);
     if (s != FILT_OK)
         return s;
     s = to_device(p->d_items, items);
@@ -485,13 +470,11 @@ filt_status bucket_forward(const filt_plan *p, const float *x, const float *a, c
 filt_status frame_grads_launch(const filt_plan *p, int b, const float *ybar, const float *y,
                                const float *yi, float *ga, hipStream_t st)
 {
-    if (ga == nullptr || p->fr_total[b] == 0)
+    if (ga == nullptr || p->fr_n[b] == 0)
         return FILT_OK;
-    const int64_t threads = p->fr_total[b] * 64;
     FILT_LAUNCH(FILT_BNAME("batched_frame_grads", kBucketW[b]), kb_frame_grads,
-                dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, p->d_segs,
-                p->d_fr_cum + p->fr_cum_off[b], p->d_fr_sid + p->fr_sid_off[b], (int)p->fr_n[b],
-                p->fr_total[b], ybar, y, yi, ga);
+                dim3((unsigned)p->fr_n[b]), dim3(64), 0, st, p->d_segs,
+                p->d_items + p->fr_off[b], ybar, y, yi, ga);
     return check_launch("batched frame gradients");
 }
 
@@ -501,7 +484,7 @@ filt_status bucket_backward(const filt_plan *p, const float *gy, const float *y,
 {
     // frame-held rows take their gradients from the stored adjoint (gx is
     // ybar for b = [1]); without gx it goes to the plan's own buffer
-    if (gx == nullptr && ga != nullptr && p->fr_total[B] > 0)
+    if (gx == nullptr && ga != nullptr && p->fr_n[B] > 0)
         gx = p->d_ybar;
     filt_status s = FILT_OK;
     if (p->onepass[B]) {
@@ -689,10 +672,6 @@ void filt_plan_destroy(filt_plan *p)
         hipEventDestroy(p->fork);
     if (p->d_tiles != nullptr)
         hipFree(p->d_tiles);
-    if (p->d_fr_cum != nullptr)
-        hipFree(p->d_fr_cum);
-    if (p->d_fr_sid != nullptr)
-        hipFree(p->d_fr_sid);
     if (p->d_ybar != nullptr)
         hipFree(p->d_ybar);
     if (p->d_flags != nullptr)

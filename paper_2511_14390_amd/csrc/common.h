@@ -549,6 +549,90 @@ filt_status fir_states_run(const Dims &d, const double *summ, double *states, hi
 filt_status reduce_lti_run(const Dims &d, const double *part, void *ga, void *gb, bool f64,
                            hipStream_t st);
 
+// Frame-held coefficients, per-frame gradient products of one contiguous
+// signal of T samples (a channel of a [B, T] problem, or a batched segment):
+//   out[f K + j] = sign * sum_{t in frame f} ybar[t] s(t - k0 - j),  j < K,
+// with s(u) = hist[-u - 1] for u < 0 (nh values, zero past them).
+//
+// One wavefront takes 64 consecutive frames f0 .. f0 + 63 (lane i frame
+// f0 + i, lanes past nf idle) of hop samples.  Each lane keeps its K sums and
+// a shift register of the K signal values its taps read, so a step needs
+// only ybar[t] and s(t + 1 - k0).  The wavefront stages both for every lane
+// through LDS in slices of kFrameSlice samples, loaded as runs of contiguous
+// samples (each half wavefront one frame's slice), so the global loads are
+// coalesced although every lane walks its own frame.  FP64 sums.
+constexpr int kFrameSlice = 32;
+constexpr int kFrameLds = 2 * 64 * (kFrameSlice + 1);  // elements per wavefront
+
+template <typename io_t>
+__device__ __forceinline__ void frame_sums_wave(const io_t *ybar, const io_t *s,
+                                                const io_t *hist, int nh, int k0, int K,
+                                                double sign, int64_t T, int64_t hop, int64_t f0,
+                                                int nf, io_t *out, io_t *lds, int lane)
+{
+    constexpr int SL = kFrameSlice, SP = kFrameSlice + 1;
+    static_assert(SL == 32, "the staging loop covers two frames' slices per load");
+    constexpr int KM = kMaxOrder + 1;
+    io_t *ly = lds, *ls = lds + 64 * SP;
+    auto sval = [&](int64_t u) -> double {
+        if (u >= 0)
+            return u < T ? (double)s[u] : 0.0;
+        return (hist != nullptr && -u <= nh) ? (double)hist[-u - 1] : 0.0;
+    };
+    const int64_t f = f0 + lane;
+    const bool act = lane < nf;
+    const int64_t t0 = f * hop;
+    const int64_t len = act ? min(hop, T - t0) : 0;  // samples of this lane's frame
+    double acc[KM], w[KM];  // w[j] = s(t - k0 - j) for the step t about to run
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        acc[j] = 0.0;
+        w[j] = (act && j < K) ? sval(t0 - k0 - j) : 0.0;
+    }
+    for (int64_t r0 = 0; r0 < hop; r0 += SL) {
+        // stage: for frame i of the wavefront, samples t = t0_i + r0 + e
+        // (e < SL) of ybar and the values s(t + 1 - k0) >= 0 entering the
+        // register after step t; every load issued before the LDS stores
+        io_t vy[32], vs[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const int i = 2 * k + (lane >> 5), e = lane & 31;
+            const int64_t t = (f0 + i) * hop + r0 + e;
+            const bool ok = i < nf && r0 + e < hop && t < T;
+            const int64_t u = t + 1 - k0;
+            vy[k] = ok ? ybar[t] : io_t(0);
+            vs[k] = (ok && r0 + e + 1 < hop && u < T) ? s[u] : io_t(0);
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            const int i = 2 * k + (lane >> 5), e = lane & 31;
+            ly[i * SP + e] = vy[k];
+            ls[i * SP + e] = vs[k];
+        }
+        __builtin_amdgcn_s_waitcnt(0xC07F);
+        __builtin_amdgcn_wave_barrier();
+        const int n = (int)min<int64_t>(SL, len - r0);
+        for (int e = 0; e < n; ++e) {
+            const double yb = (double)ly[lane * SP + e];
+            const double nx = (double)ls[lane * SP + e];
+#pragma unroll
+            for (int j = 0; j < KM; ++j)
+                acc[j] = __builtin_fma(yb, w[j], acc[j]);
+#pragma unroll
+            for (int j = KM - 1; j > 0; --j)
+                w[j] = w[j - 1];
+            w[0] = nx;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < KM; ++j)
+            if (j < K)
+                out[f * K + j] = (io_t)(sign * acc[j]);
+    }
+}
+
 // Frame rows of a problem: time_varying = 0 (per channel), 1 (per sample)
 // or h >= 2 (per frame of h samples).
 inline void set_rows(Dims &d, int64_t time_varying)

@@ -97,76 +97,74 @@ __device__ __forceinline__ double sig_hist(const Dims &d, const io_t *s, const i
     return (hist != nullptr && -t <= nh) ? (double)hist[b * nh + (-t - 1)] : 0.0;
 }
 
-// [B, T]: one wavefront per (channel, frame); lanes take the frame's samples
-// (coalesced), each lane sums its products for every tap, and the wavefront
-// adds the 64 partial sums of each tap.
+// [B, T]: one wavefront (workgroup) per (channel, 64 consecutive frames).
 template <typename io_t>
-__global__ void __launch_bounds__(kGradThreads)
+__global__ void __launch_bounds__(64)
 k_frame_grads_bt(Dims d, const io_t *__restrict__ ybar, const io_t *__restrict__ s,
                  const io_t *__restrict__ hist, int nh, int k0, int K, double sign,
                  io_t *__restrict__ out)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * kGradThreads + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (wave >= d.B * d.F)
-        return;  // whole wavefronts
-    const int64_t b = wave / d.F, f = wave % d.F;
-    const int64_t t0 = f * d.hop, t1 = min(t0 + d.hop, d.T);
-    double acc[kMaxOrder + 1];
-#pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j)
-        acc[j] = 0.0;
-    for (int64_t t = t0 + lane; t < t1; t += 64) {
-        const double yb = (double)ybar[sig_at(d, b, t)];
-#pragma unroll
-        for (int j = 0; j <= kMaxOrder; ++j)
-            if (j < K)
-                acc[j] += yb * sig_hist(d, s, hist, nh, b, t - k0 - j);
-    }
-    io_t *o = out + row_at(d, b, t0, K);
-#pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j) {
-        if (j < K) {
-            double v = acc[j];
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1)
-                v += __shfl_xor(v, m, 64);
-            if (lane == 0)
-                o[j] = (io_t)(sign * v);
-        }
-    }
+    __shared__ io_t lds[kFrameLds];
+    const int64_t nfb = (d.F + 63) / 64;
+    const int64_t b = blockIdx.x / nfb, f0 = (blockIdx.x % nfb) * 64;
+    frame_sums_wave(ybar + b * d.T, s + b * d.T, hist != nullptr ? hist + b * nh : nullptr, nh,
+                    k0, K, sign, d.T, d.hop, f0, (int)min<int64_t>(64, d.F - f0),
+                    out + b * d.F * K, lds, (int)threadIdx.x);
 }
 
-// [T, B]: one lane per (channel, frame), neighbouring lanes neighbouring
-// channels (every load of a wavefront is one contiguous run); the lane walks
-// its frame and keeps the K sums.
+// [T, B]: one lane per (channel, frame, group of four taps), neighbouring
+// lanes neighbouring channels (every load of a wavefront is one contiguous
+// run).  The lane walks its frame with the four signal values its taps read
+// in a shift register: two loads and four FMAs per sample, the loads of 16
+// samples issued together.
 template <typename io_t>
 __global__ void __launch_bounds__(kGradThreads)
 k_frame_grads_tb(Dims d, const io_t *__restrict__ ybar, const io_t *__restrict__ s,
                  const io_t *__restrict__ hist, int nh, int k0, int K, double sign,
                  io_t *__restrict__ out)
 {
+    const int G = (K + 3) / 4;
     const int64_t g = (int64_t)blockIdx.x * kGradThreads + threadIdx.x;
-    if (g >= d.B * d.F)
+    if (g >= d.B * d.F * G)
         return;
-    const int64_t b = g % d.B, f = g / d.B;
+    const int64_t b = g % d.B, rest = g / d.B;
+    const int q = (int)(rest % G);
+    const int64_t f = rest / G;
     const int64_t t0 = f * d.hop, t1 = min(t0 + d.hop, d.T);
-    double acc[kMaxOrder + 1];
+    const int kq = k0 + 4 * q;  // first tap of this lane
+    double acc[4], w[4];        // w[i] = s(t - kq - i) for the step t about to run
 #pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j)
-        acc[j] = 0.0;
-    for (int64_t t = t0; t < t1; ++t) {
-        const double yb = (double)ybar[sig_at(d, b, t)];
-#pragma unroll
-        for (int j = 0; j <= kMaxOrder; ++j)
-            if (j < K)
-                acc[j] += yb * sig_hist(d, s, hist, nh, b, t - k0 - j);
+    for (int i = 0; i < 4; ++i) {
+        acc[i] = 0.0;
+        w[i] = sig_hist(d, s, hist, nh, b, t0 - kq - i);
     }
-    io_t *o = out + row_at(d, b, t0, K);
+    constexpr int P = 16;
+    for (int64_t tb = t0; tb < t1; tb += P) {
+        io_t yv[P], nv[P];
 #pragma unroll
-    for (int j = 0; j <= kMaxOrder; ++j)
-        if (j < K)
-            o[j] = (io_t)(sign * acc[j]);
+        for (int r = 0; r < P; ++r) {
+            const int64_t t = tb + r;
+            const int64_t u = t + 1 - kq;  // enters the register after step t
+            yv[r] = t < t1 ? ybar[t * d.B + b] : io_t(0);
+            nv[r] = (t + 1 < t1) ? (io_t)sig_hist(d, s, hist, nh, b, u) : io_t(0);
+        }
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const double yb = (double)yv[r];  // zero past the frame
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                acc[i] = __builtin_fma(yb, w[i], acc[i]);
+            w[3] = w[2];
+            w[2] = w[1];
+            w[1] = w[0];
+            w[0] = (double)nv[r];
+        }
+    }
+    io_t *o = out + row_at(d, b, t0, K) + 4 * q;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (4 * q + i < K)
+            o[i] = (io_t)(sign * acc[i]);
 }
 
 }  // namespace
@@ -181,12 +179,11 @@ filt_status frame_coef_grads_run(const Dims &d, const io_t *ybar, const io_t *x,
     auto launch = [&](const io_t *sig, const io_t *hist, int nh, int k0, int K, double sign,
                       io_t *o) {
         if (d.layout == FILT_LAYOUT_BT) {
-            const int64_t threads = d.B * d.F * 64;
             FILT_LAUNCH("frame_coef_grads", k_frame_grads_bt<io_t>,
-                        dim3((unsigned)((threads + kGradThreads - 1) / kGradThreads)),
-                        dim3(kGradThreads), 0, st, d, ybar, sig, hist, nh, k0, K, sign, o);
+                        dim3((unsigned)(d.B * ((d.F + 63) / 64))), dim3(64), 0, st, d, ybar, sig,
+                        hist, nh, k0, K, sign, o);
         } else {
-            const int64_t threads = d.B * d.F;
+            const int64_t threads = d.B * d.F * ((K + 3) / 4);
             FILT_LAUNCH("frame_coef_grads", k_frame_grads_tb<io_t>,
                         dim3((unsigned)((threads + kGradThreads - 1) / kGradThreads)),
                         dim3(kGradThreads), 0, st, d, ybar, sig, hist, nh, k0, K, sign, o);
