@@ -191,3 +191,122 @@ def backward_frames(gy, x, y, a, b=None, xi=None, yi=None, hop=1, layout="BT", n
         if k in g:
             g[k] = frame_reduce(g[k], hop, layout)
     return g
+
+
+# ---------------------------------------------------------------------------
+# State-space filter and the transposed direct form (Sec. 2 Eqs. 4-5; the
+# backward of Sec. 3.1 Eqs. 6-9 and App. A), time-invariant.
+#
+# State-space filter, per channel: v(n+1) = A v(n) + B x(n),
+# y(n) = C . v(n) + D x(n), with the initial state v(0).  Shapes: x [B, T]
+# ("BT") or [T, B] ("TB"); A [B, K, K]; Bv, C [B, K]; D [B]; v0 [B, K].
+#
+# Transposed direct form II (SciPy's lfilter with its zi state): with
+# K = max(M, N), b_j = 0 past M and a_j = 0 past N, the state after sample n
+# is z(n), y(n) = b_0 x(n) + z_0(n-1) and
+# z_i(n) = b_{i+1} x(n) - a_{i+1} y(n) + z_{i+1}(n-1).  As a state-space
+# filter with v(n) = z(n-1) (so v(0) = zi): A[i][0] = -a_{i+1},
+# A[i][i+1] = 1, B_i = b_{i+1} - a_{i+1} b_0, C = e_0, D = b_0 -- the
+# transpose of the direct form's companion realisation with B and C swapped
+# (Sec. 2).
+
+
+def _chan_first(v, layout):
+    return v if layout == "BT" else v.T
+
+
+def ss_forward(x, A, Bv, C, D, v0=None, layout="BT"):
+    """y of the state-space filter (FP64), every channel at once."""
+    x = _chan_first(_f64(x), layout)
+    A, Bv, C, D = map(_f64, (A, Bv, C, D))
+    Bn, T = x.shape
+    K = A.shape[-1]
+    v = np.zeros((Bn, K)) if v0 is None else _f64(v0).copy()
+    y = np.zeros((Bn, T))
+    for n in range(T):
+        y[:, n] = np.einsum("bk,bk->b", C, v) + D * x[:, n]
+        v = np.einsum("bij,bj->bi", A, v) + Bv * x[:, n, None]
+    return y if layout == "BT" else y.T
+
+
+def ss_backward(gy, x, A, Bv, C, D, v0=None, layout="BT"):
+    """Gradients of L = <gy, y> for the state-space filter by the paper's
+    reverse recursion: gz(n) = A^T gz(n+1) + C gy(n+1) from gz(T-1) = 0
+    (Eq. 7 with dL/dv(n) = gy(n) C, Eq. 6), gx(n) = B . gz(n) + D gy(n)
+    (Eq. 8), gv0 = gz(-1), gB = sum_n gz(n) x(n), gA_ij = sum_n gz_i(n) v_j(n)
+    (Eq. 9, the chain-rule orientation), gC = sum_n gy(n) v(n),
+    gD = sum_n gy(n) x(n) (Eq. 6).  Returns a dict x, A, B, C, D, v0."""
+    x = _chan_first(_f64(x), layout)
+    gy = _chan_first(_f64(gy), layout)
+    A, Bv, C, D = map(_f64, (A, Bv, C, D))
+    Bn, T = x.shape
+    K = A.shape[-1]
+    # the states v(0) .. v(T-1) of the forward
+    vs = np.zeros((T, Bn, K))
+    v = np.zeros((Bn, K)) if v0 is None else _f64(v0).copy()
+    for n in range(T):
+        vs[n] = v
+        v = np.einsum("bij,bj->bi", A, v) + Bv * x[:, n, None]
+    gx = np.zeros((Bn, T))
+    gA = np.zeros_like(A)
+    gB = np.zeros_like(Bv)
+    gC = np.zeros_like(C)
+    gD = np.zeros(Bn)
+    gz = np.zeros((Bn, K))  # gz(T-1)
+    for n in range(T - 1, -1, -1):
+        if n < T - 1:
+            gz = np.einsum("bji,bj->bi", A, gz) + C * gy[:, n + 1, None]
+        gx[:, n] = np.einsum("bk,bk->b", Bv, gz) + D * gy[:, n]
+        gB += gz * x[:, n, None]
+        gA += gz[:, :, None] * vs[n][:, None, :]
+        gC += gy[:, n, None] * vs[n]
+        gD += gy[:, n] * x[:, n]
+    gv0 = np.einsum("bji,bj->bi", A, gz) + C * gy[:, 0, None] if T > 0 else np.zeros((Bn, K))
+    return {"x": gx if layout == "BT" else gx.T, "A": gA, "B": gB, "C": gC, "D": gD,
+            "v0": gv0}
+
+
+def tdf_matrices(b, a):
+    """(A, B, C, D) of the transposed direct form II for b [B, M+1], a [B, N]
+    (a_0 = 1 implicit), K = max(M, N) (at least 1)."""
+    b, a = _f64(b), _f64(a)
+    Bn = b.shape[0]
+    M, N = b.shape[1] - 1, a.shape[1]
+    K = max(M, N, 1)
+    bb = np.zeros((Bn, K + 1))
+    bb[:, :M + 1] = b
+    aa = np.zeros((Bn, K + 1))
+    aa[:, 1:N + 1] = a
+    A = np.zeros((Bn, K, K))
+    A[:, :, 0] = -aa[:, 1:]
+    for i in range(K - 1):
+        A[:, i, i + 1] = 1.0
+    Bv = bb[:, 1:] - aa[:, 1:] * bb[:, :1]
+    C = np.zeros((Bn, K))
+    C[:, 0] = 1.0
+    return A, Bv, C, bb[:, 0].copy()
+
+
+def tdf_forward(x, b, a, zi=None, layout="BT"):
+    """Transposed direct form II with initial state zi [B, max(M, N)]
+    (SciPy's lfilter semantics), time-invariant."""
+    A, Bv, C, D = tdf_matrices(b, a)
+    return ss_forward(x, A, Bv, C, D, zi, layout)
+
+
+def tdf_backward(gy, x, b, a, zi=None, layout="BT"):
+    """Gradients of the transposed direct form with respect to x, b, a and
+    zi: the state-space gradients mapped through tdf_matrices by the chain
+    rule (B_i = b_{i+1} - a_{i+1} b_0, A[i][0] = -a_{i+1}, D = b_0)."""
+    b, a = _f64(b), _f64(a)
+    M, N = b.shape[1] - 1, a.shape[1]
+    A, Bv, C, D = tdf_matrices(b, a)
+    K = A.shape[-1]
+    g = ss_backward(gy, x, A, Bv, C, D, zi, layout)
+    aa = np.zeros((b.shape[0], K))
+    aa[:, :N] = a
+    gb = np.zeros_like(b)
+    gb[:, 0] = g["D"] - (g["B"] * aa).sum(axis=1)
+    gb[:, 1:] = g["B"][:, :M]
+    ga = -g["A"][:, :N, 0] - b[:, :1] * g["B"][:, :N]
+    return {"x": g["x"], "b": gb, "a": ga, "zi": g["v0"]}
