@@ -155,6 +155,29 @@ filt_status filt_jvp(const filt_problem *p, const float *x, const float *y, cons
                      const float *db, const float *da, const float *dxi, const float *dyi,
                      float *dy, void *ws, size_t ws_bytes, void *stream);
 
+/* Transposed direct form II with an initial state (Sec. 2: the state-space
+ * form of Eqs. 4-5 with the companion matrix transposed and B, C swapped;
+ * SciPy's lfilter(b, a, x, zi)), time-invariant coefficients only
+ * (p->time_varying must be 0; FILT_EUNSUPPORTED otherwise).  With
+ * K = max(M, N) (at least 1), b_j = 0 past M and a_j = 0 past N:
+ *   y(n) = b_0 x(n) + z_0(n-1),
+ *   z_i(n) = b_{i+1} x(n) - a_{i+1} y(n) + z_{i+1}(n-1),  z(-1) = zi,
+ * x and y zero before time 0.  b [B][M+1] is required (b = [1] is a row of
+ * one 1), a [B][N] may be NULL only when N == 0, zi [B][K] may be NULL
+ * (zero state).  Signals in p->layout.  The backward (Sec. 3.1 Eqs. 6-9 for
+ * this realisation) writes gx [layout], gb [B][M+1], ga [B][N] (needs y and
+ * N > 0), gzi [B][K]; each may be NULL.  x is read only for gb.  T == 0 with
+ * B > 0 zero-fills the per-channel gradients it was given.  ws: at least
+ * filt_tdf_workspace_bytes(p) bytes. */
+filt_status filt_tdf_workspace_bytes(const filt_problem *p, size_t *bytes);
+filt_status filt_tdf_forward(const filt_problem *p, const float *x, const float *b,
+                             const float *a, const float *zi, float *y, void *ws, size_t ws_bytes,
+                             void *stream);
+filt_status filt_tdf_backward(const filt_problem *p, const float *gy, const float *x,
+                              const float *y, const float *b, const float *a, const float *zi,
+                              float *gx, float *gb, float *ga, float *gzi, void *ws,
+                              size_t ws_bytes, void *stream);
+
 /* The same two operations on FP64 data, computed in FP64 (for numerical
  * gradient checks).  Arguments as above with double in place of float. */
 filt_status filt_forward_f64(const filt_problem *p, const double *x, const double *b,

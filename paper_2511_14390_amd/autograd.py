@@ -74,3 +74,38 @@ def lfilter(x, a, b=None, xi=None, yi=None, layout="BT", chunk=0, f32_state=Fals
         yi = yi.contiguous()
     return LFilter.apply(x.contiguous(), a, b, xi, yi, layout, int(chunk), bool(f32_state),
                          bool(toeplitz), int(hop))
+
+
+class TDFilter(torch.autograd.Function):
+    """Transposed direct form II with an initial state (SciPy's lfilter with
+    zi), time-invariant: forward filt_tdf_forward, backward filt_tdf_backward
+    for the inputs that need gradients.  Saves the inputs and y."""
+
+    @staticmethod
+    def forward(ctx, x, b, a, zi, layout, chunk):
+        y = _f.filt_tdf_forward(x, b, a, zi, layout=layout, chunk=chunk)
+        ctx.save_for_backward(x, b, a, zi, y)
+        ctx.cfg = (layout, chunk)
+        return y
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, gy):
+        x, b, a, zi, y = ctx.saved_tensors
+        layout, chunk = ctx.cfg
+        need = ctx.needs_input_grad
+        want = [k for k, n in zip(("x", "b", "a", "zi"), need[:4]) if n]
+        if not want:
+            return (None,) * 6
+        g = _f.filt_tdf_backward(gy, x, y, b, a, zi, layout=layout, chunk=chunk,
+                                 want=tuple(want))
+        return (g.get("x"), g.get("b"), g.get("a") if a is not None else None,
+                g.get("zi") if zi is not None else None, None, None)
+
+
+def lfilter_tdf(x, b, a, zi=None, layout="BT", chunk=0):
+    """Differentiable transposed direct form II: SciPy's
+    ``lfilter(b, a, x, zi=zi)`` per channel, b ``[B, M+1]``, a ``[B, N]``
+    (a_0 = 1 implied), zi ``[B, max(M, N)]`` or None."""
+    return TDFilter.apply(x.contiguous(), b.contiguous(), None if a is None else a.contiguous(),
+                          None if zi is None else zi.contiguous(), layout, int(chunk))

@@ -240,6 +240,77 @@ def filt_jvp(x, y, a, b=None, xi=None, yi=None, *, dx=None, db=None, da=None, dx
     return dy
 
 
+def _tdf_lib():
+    L = lib()
+    if not getattr(L, "_tdf_ready", False):
+        PP, P = ctypes.POINTER(FiltProblem), ctypes.c_void_p
+        L.filt_tdf_workspace_bytes.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+        L.filt_tdf_workspace_bytes.restype = ctypes.c_int
+        L.filt_tdf_forward.argtypes = [PP] + [P] * 6 + [ctypes.c_size_t, P]
+        L.filt_tdf_forward.restype = ctypes.c_int
+        L.filt_tdf_backward.argtypes = [PP] + [P] * 11 + [ctypes.c_size_t, P]
+        L.filt_tdf_backward.restype = ctypes.c_int
+        L._tdf_ready = True
+    return L
+
+
+def _tdf_prep(x, b, a, zi, layout, chunk):
+    dev = x.device
+    if dev.type != "cuda":
+        raise ValueError("the transposed form runs on the GPU only")
+    if x.dtype != torch.float32:
+        raise ValueError("the transposed form takes float32 tensors")
+    if b is None or b.dim() != 2:
+        raise ValueError("b must be [B, M+1] (time-invariant)")
+    if a is not None and a.dim() != 2:
+        raise ValueError("a must be [B, N] (time-invariant)")
+    b, a, zi = (_prep(t, torch.float32, dev, n) for t, n in ((b, "b"), (a, "a"), (zi, "zi")))
+    p = problem(x, a, b, layout, chunk)
+    K = max(p.M, p.N, 1)
+    if zi is not None and tuple(zi.shape) != (p.B, K):
+        raise ValueError(f"zi must be [{p.B}, {K}], got {tuple(zi.shape)}")
+    n = ctypes.c_size_t(0)
+    _check(_tdf_lib().filt_tdf_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return p, b, a, zi, K, n.value
+
+
+def filt_tdf_forward(x, b, a, zi=None, *, layout="BT", chunk=0, ws=None, stream=None):
+    """Transposed direct form II with initial state zi [B, max(M, N)]
+    (SciPy's lfilter(b, a, x, zi) semantics; see filt_tdf_forward in
+    include/filt.h).  Returns y."""
+    x = x.contiguous()
+    p, b, a, zi, K, need = _tdf_prep(x, b, a, zi, layout, chunk)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    y = torch.empty_like(x)
+    _check(_tdf_lib().filt_tdf_forward(ctypes.byref(p), _ptr(x), _ptr(b), _ptr(a), _ptr(zi),
+                                       _ptr(y), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                       _stream(x.device, stream)))
+    return y
+
+
+def filt_tdf_backward(gy, x, y, b, a, zi=None, *, layout="BT", chunk=0,
+                      want=("x", "b", "a", "zi"), ws=None, stream=None):
+    """Gradients of the transposed direct form with respect to x, b, a, zi
+    (the requested keys; a only with N > 0)."""
+    gy = gy.contiguous()
+    x = _prep(x, torch.float32, gy.device, "x")
+    y = _prep(y, torch.float32, gy.device, "y")
+    p, b, a, zi, K, need = _tdf_prep(gy, b, a, zi, layout, chunk)
+    dev = gy.device
+    gx = torch.empty_like(gy) if "x" in want else None
+    gb = torch.empty_like(b) if "b" in want else None
+    ga = torch.empty_like(a) if ("a" in want and a is not None and p.N > 0) else None
+    gzi = torch.empty((p.B, K), dtype=torch.float32, device=dev) if "zi" in want else None
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(_tdf_lib().filt_tdf_backward(ctypes.byref(p), _ptr(gy), _ptr(x), _ptr(y), _ptr(b),
+                                        _ptr(a), _ptr(zi), _ptr(gx), _ptr(gb), _ptr(ga),
+                                        _ptr(gzi), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                        _stream(dev, stream)))
+    return {k: v for k, v in (("x", gx), ("b", gb), ("a", ga), ("zi", gzi)) if v is not None}
+
+
 def profile_enable(on: bool):
     """Start (True) or stop (False) per-kernel event timing inside the library."""
     L = lib()
