@@ -310,3 +310,38 @@ def tdf_backward(gy, x, b, a, zi=None, layout="BT"):
     gb[:, 1:] = g["B"][:, :M]
     ga = -g["A"][:, :N, 0] - b[:, :1] * g["B"][:, :N]
     return {"x": g["x"], "b": gb, "a": ga, "zi": g["v0"]}
+
+
+# ---------------------------------------------------------------------------
+# Second-order sections (the cascade of biquads the paper's experiments
+# motivate for higher orders, Sec. 4; SciPy's sosfilt): section s filters the
+# previous section's output with b [S, B, 3], a [S, B, 2] (a_0 = 1 implied)
+# in the transposed direct form with its own initial state zi [S, B, 2].
+
+
+def sos_forward(x, b, a, zi=None, layout="BT"):
+    """Cascade output: every section's transposed-form filter in turn."""
+    y = _f64(x)
+    for s in range(b.shape[0]):
+        y = tdf_forward(y, b[s], a[s], None if zi is None else zi[s], layout)
+    return y
+
+
+def sos_backward(gy, x, b, a, zi=None, layout="BT"):
+    """Gradients of the cascade: the sections' inputs from a forward pass,
+    then each section's transposed-form gradients from the last section to
+    the first, the input gradient of one section being the output gradient
+    of the one before it (chain rule)."""
+    S = b.shape[0]
+    ins = [_f64(x)]
+    for s in range(S - 1):
+        ins.append(tdf_forward(ins[-1], b[s], a[s], None if zi is None else zi[s], layout))
+    g = _f64(gy)
+    gb = np.zeros(b.shape)
+    ga = np.zeros(a.shape)
+    gzi = np.zeros((S,) + a.shape[1:])
+    for s in range(S - 1, -1, -1):
+        r = tdf_backward(g, ins[s], b[s], a[s], None if zi is None else zi[s], layout)
+        gb[s], ga[s], gzi[s] = r["b"], r["a"], r["zi"]
+        g = r["x"]
+    return {"x": g, "b": gb, "a": ga, "zi": gzi}
