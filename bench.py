@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--frames", action="store_true",
                     help="batched-ragged: the coefficients as frame rows (one per hop of 128 "
                          "samples, gradients per frame) instead of per-sample rows")
+    ap.add_argument("--tdf", action="store_true",
+                    help="lti-df-m4n4: the transposed direct form II with an initial state "
+                         "(zi drawn like the workload's initial conditions) instead of the "
+                         "direct form with input / output histories")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -137,6 +141,13 @@ def kernel_bytes(p, name):
         # chunk summaries read their phase's inputs once
         "fwd_summary": 4 + coef,
         "bwd_summary": 4 + coef,
+        # transposed form: the feed-forward input (read x, write u), the
+        # feed-forward adjoint (read ybar, write gx; in [T, B] it also reads x
+        # for the gb partial sums) and the separate gb partial sums of [B, T]
+        # (read ybar and x)
+        "tdf_input": 8,
+        "tdf_fir_adjoint": 12 if p.layout == "TB" else 8,
+        "tdf_gb_partial": 8,
     }
     return table.get(name)
 
@@ -501,7 +512,18 @@ def main():
     gy = t(p.gy)
     samples = p.B * p.T
 
+    if args.tdf:
+        if args.workload != "lti-df-m4n4":
+            raise SystemExit("--tdf applies to lti-df-m4n4")
+        # the transposed form's state zi [B, max(M, N)] from the same draw as
+        # the workload's output history
+        zi = t(p.yi, True)
+
     def step():
+        if args.tdf:
+            y = AG.lfilter_tdf(x, b, a, zi, layout=p.layout, chunk=args.chunk)
+            torch.autograd.grad(y, [x, b, a, zi], gy)
+            return
         y = AG.lfilter(x, a, b, xi, yi, layout=p.layout, chunk=args.chunk,
                        f32_state=args.f32_state, toeplitz=args.toeplitz, hop=hop)
         inputs = [v for v in (x, a, b, xi, yi) if v is not None]
@@ -553,10 +575,16 @@ def main():
     roofline = None
     chunk = F.auto_chunk(F.problem(x, a, b, p.layout, args.chunk, toeplitz=args.toeplitz,
                                    hop=hop))
-    if dom is not None and kernel_flops(p, dom, chunk) is not None:
+    pk = p  # the problem whose per-sample bytes the library's kernels move
+    if args.tdf:
+        # the transposed form runs the all-pole kernels on the formed input
+        from paper_2511_14390_amd import workloads as W
+
+        pk = W.Problem(p.name, p.layout, p.x, p.a, None, None, None, p.gy, dict(p.meta))
+    if dom is not None and kernel_flops(pk, dom, chunk) is not None:
         # the dominant kernel is bound by FP64 vector arithmetic (SQ counters:
         # VALU issue), so it is measured against the FP64 vector peak
-        flop = kernel_flops(p, dom, chunk) * samples
+        flop = kernel_flops(pk, dom, chunk) * samples
         ach = flop / (kern[dom]["avg_us"] * 1e-6) / 1e12
         roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2),
                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -564,8 +592,8 @@ def main():
                     "traffic": counted_traffic(args.workload + ("-frames" if hop > 1 else ""),
                                                p.layout, chunk, dom),
                     "flops_per_launch": flop, "avg_launch_us": round(kern[dom]["avg_us"], 2)}
-    elif dom is not None and kernel_bytes(p, dom) is not None:
-        per_launch = kernel_bytes(p, dom) * samples
+    elif dom is not None and kernel_bytes(pk, dom) is not None:
+        per_launch = kernel_bytes(pk, dom) * samples
         ach = per_launch / (kern[dom]["avg_us"] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
@@ -582,9 +610,20 @@ def main():
         nthreads = max(1, min(cores, p.B))
         f64 = lambda v: None if v is None else np.ascontiguousarray(v, dtype=np.float64)
         xs, as_, bs, xis, yis, gys = map(f64, (p.x, p.a, p.b, p.xi, p.yi, p.gy))
+        sub = None
+        if args.tdf:
+            # the transposed form's oracle is a NumPy loop over time: a
+            # bounded sample of 16 channels
+            sub = np.arange(16)
+            pick = (lambda v: v[:, sub]) if p.layout == "TB" else (lambda v: v[sub])
+            xs, gys = pick(xs), pick(gys)
+            bs, as_, zis = bs[sub], as_[sub], f64(p.yi)[sub]
         reps, c0 = 0, time.perf_counter()
         while True:
-            if hop > 1:
+            if args.tdf:
+                yo = oracle.tdf_forward(xs, bs, as_, zis, layout=p.layout)
+                oracle.tdf_backward(gys, xs, bs, as_, zis, layout=p.layout)
+            elif hop > 1:
                 yo = oracle.forward_frames(xs, as_, bs, xis, yis, hop=hop, layout=p.layout,
                                            nthreads=nthreads)
                 oracle.backward_frames(gys, xs, yo, as_, bs, xis, yis, hop=hop, layout=p.layout,
@@ -597,10 +636,17 @@ def main():
             if time.perf_counter() - c0 >= args.cpu_seconds:
                 break
         dt = time.perf_counter() - c0
-        cpu = {"value": round(samples * reps / dt / 1e9, 6), "unit": "Gsamples/s", "cores": nthreads,
-               "kind": "oracle",
-               "sample": f"the whole workload (fwd+bwd, all {p.B} channels) repeated {reps}x, "
-                         f"FP64, {nthreads} threads over channels, {dt:.1f} s"}
+        if sub is not None:
+            cpu = {"value": round(len(sub) * p.T * reps / dt / 1e9, 6), "unit": "Gsamples/s",
+                   "cores": 1, "kind": "oracle",
+                   "sample": f"{len(sub)} of the {p.B} channels (fwd+bwd of the transposed "
+                             f"form, FP64 NumPy state-space loop, 1 thread) repeated {reps}x, "
+                             f"{dt:.1f} s"}
+        else:
+            cpu = {"value": round(samples * reps / dt / 1e9, 6), "unit": "Gsamples/s",
+                   "cores": nthreads, "kind": "oracle",
+                   "sample": f"the whole workload (fwd+bwd, all {p.B} channels) repeated "
+                             f"{reps}x, FP64, {nthreads} threads over channels, {dt:.1f} s"}
 
     rec = {
         "metric": "fwd+bwd Gsamples/s & % HBM roofline, batched vs plain, rel err <=1e-4 vs FP64",
@@ -609,7 +655,9 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-state" if args.f32_state else ("f32-mfma" if args.toeplitz else "f64"),
         "data": "synthetic",
-        "config": {"workload": p.name + ("-frames" if hop > 1 else ""), "io": "f32", "B": p.B,
+        "config": {"workload": p.name + ("-frames" if hop > 1 else "") + ("-tdf" if args.tdf
+                                                                          else ""),
+                   "io": "f32", "B": p.B,
                    "T": p.T, "M": p.M, "N": p.N,
                    "time_varying": bool(p.time_varying), "hop": hop, "layout": p.layout,
                    "chunk": chunk,

@@ -178,6 +178,26 @@ filt_status filt_tdf_backward(const filt_problem *p, const float *gy, const floa
                               float *gx, float *gb, float *ga, float *gzi, void *ws,
                               size_t ws_bytes, void *stream);
 
+/* Cascades of nsec second-order sections (biquads; the structure used for
+ * higher orders to keep rounding errors small, Sec. 4), SciPy's sosfilt
+ * semantics: section k filters section k-1's output (x for k = 0) in the
+ * transposed direct form II above with its own initial state.  p->M and
+ * p->N must be 2 and p->time_varying 0; coefficients are section-major:
+ * b [nsec][B][3] (b_0 b_1 b_2), a [nsec][B][2] (a_1 a_2, a_0 = 1 implied),
+ * zi [nsec][B][2] or NULL (zero states).  The backward writes gx [layout]
+ * and gb, ga, gzi in the shapes of b, a, zi (each may be NULL); it needs x
+ * and y (the forward's output) and recomputes the sections' inputs.
+ * ws: at least filt_sos_workspace_bytes(p, nsec) bytes (nsec + 1 signals
+ * plus one section's workspace). */
+filt_status filt_sos_workspace_bytes(const filt_problem *p, int32_t nsec, size_t *bytes);
+filt_status filt_sos_forward(const filt_problem *p, int32_t nsec, const float *x, const float *b,
+                             const float *a, const float *zi, float *y, void *ws, size_t ws_bytes,
+                             void *stream);
+filt_status filt_sos_backward(const filt_problem *p, int32_t nsec, const float *gy,
+                              const float *x, const float *y, const float *b, const float *a,
+                              const float *zi, float *gx, float *gb, float *ga, float *gzi,
+                              void *ws, size_t ws_bytes, void *stream);
+
 /* The same two operations on FP64 data, computed in FP64 (for numerical
  * gradient checks).  Arguments as above with double in place of float. */
 filt_status filt_forward_f64(const filt_problem *p, const double *x, const double *b,

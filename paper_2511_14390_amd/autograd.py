@@ -109,3 +109,38 @@ def lfilter_tdf(x, b, a, zi=None, layout="BT", chunk=0):
     (a_0 = 1 implied), zi ``[B, max(M, N)]`` or None."""
     return TDFilter.apply(x.contiguous(), b.contiguous(), None if a is None else a.contiguous(),
                           None if zi is None else zi.contiguous(), layout, int(chunk))
+
+
+class SOSFilter(torch.autograd.Function):
+    """Cascade of second-order sections (SciPy's sosfilt with per-section
+    initial states), time-invariant: forward filt_sos_forward, backward
+    filt_sos_backward.  Saves the inputs and y."""
+
+    @staticmethod
+    def forward(ctx, x, b, a, zi, layout, chunk):
+        y = _f.filt_sos_forward(x, b, a, zi, layout=layout, chunk=chunk)
+        ctx.save_for_backward(x, b, a, zi, y)
+        ctx.cfg = (layout, chunk)
+        return y
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, gy):
+        x, b, a, zi, y = ctx.saved_tensors
+        layout, chunk = ctx.cfg
+        need = ctx.needs_input_grad
+        want = [k for k, n in zip(("x", "b", "a", "zi"), need[:4]) if n]
+        if not want:
+            return (None,) * 6
+        g = _f.filt_sos_backward(gy, x, y, b, a, zi, layout=layout, chunk=chunk,
+                                 want=tuple(want))
+        return (g.get("x"), g.get("b"), g.get("a"), g.get("zi") if zi is not None else None,
+                None, None)
+
+
+def sosfilt(x, b, a, zi=None, layout="BT", chunk=0):
+    """Differentiable cascade of second-order sections: b ``[S, B, 3]``,
+    a ``[S, B, 2]`` (a_0 = 1 implied), zi ``[S, B, 2]`` or None; per
+    channel SciPy's ``sosfilt``."""
+    return SOSFilter.apply(x.contiguous(), b.contiguous(), a.contiguous(),
+                           None if zi is None else zi.contiguous(), layout, int(chunk))

@@ -311,6 +311,73 @@ def filt_tdf_backward(gy, x, y, b, a, zi=None, *, layout="BT", chunk=0,
     return {k: v for k, v in (("x", gx), ("b", gb), ("a", ga), ("zi", gzi)) if v is not None}
 
 
+def _sos_lib():
+    L = lib()
+    if not getattr(L, "_sos_ready", False):
+        PP, P, I = ctypes.POINTER(FiltProblem), ctypes.c_void_p, ctypes.c_int32
+        L.filt_sos_workspace_bytes.argtypes = [PP, I, ctypes.POINTER(ctypes.c_size_t)]
+        L.filt_sos_workspace_bytes.restype = ctypes.c_int
+        L.filt_sos_forward.argtypes = [PP, I] + [P] * 6 + [ctypes.c_size_t, P]
+        L.filt_sos_forward.restype = ctypes.c_int
+        L.filt_sos_backward.argtypes = [PP, I] + [P] * 11 + [ctypes.c_size_t, P]
+        L.filt_sos_backward.restype = ctypes.c_int
+        L._sos_ready = True
+    return L
+
+
+def _sos_prep(x, b, a, zi, layout, chunk):
+    dev = x.device
+    if dev.type != "cuda":
+        raise ValueError("the section cascade runs on the GPU only")
+    if x.dtype != torch.float32:
+        raise ValueError("the section cascade takes float32 tensors")
+    if b.dim() != 3 or b.shape[-1] != 3 or a.dim() != 3 or a.shape[-1] != 2:
+        raise ValueError("b must be [S, B, 3] and a [S, B, 2]")
+    b, a, zi = (_prep(t, torch.float32, dev, n) for t, n in ((b, "b"), (a, "a"), (zi, "zi")))
+    S = b.shape[0]
+    p = problem(x, a[0], b[0], layout, chunk)
+    if tuple(a.shape) != (S, p.B, 2) or (zi is not None and tuple(zi.shape) != (S, p.B, 2)):
+        raise ValueError("a and zi must be [S, B, 2]")
+    n = ctypes.c_size_t(0)
+    _check(_sos_lib().filt_sos_workspace_bytes(ctypes.byref(p), S, ctypes.byref(n)))
+    return p, S, b, a, zi, n.value
+
+
+def filt_sos_forward(x, b, a, zi=None, *, layout="BT", chunk=0, ws=None, stream=None):
+    """Cascade of second-order sections (SciPy's sosfilt per channel):
+    b [S, B, 3], a [S, B, 2], zi [S, B, 2] or None.  Returns y."""
+    x = x.contiguous()
+    p, S, b, a, zi, need = _sos_prep(x, b, a, zi, layout, chunk)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    y = torch.empty_like(x)
+    _check(_sos_lib().filt_sos_forward(ctypes.byref(p), S, _ptr(x), _ptr(b), _ptr(a), _ptr(zi),
+                                       _ptr(y), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                       _stream(x.device, stream)))
+    return y
+
+
+def filt_sos_backward(gy, x, y, b, a, zi=None, *, layout="BT", chunk=0,
+                      want=("x", "b", "a", "zi"), ws=None, stream=None):
+    """Gradients of the section cascade with respect to x, b, a, zi."""
+    gy = gy.contiguous()
+    x = _prep(x, torch.float32, gy.device, "x")
+    y = _prep(y, torch.float32, gy.device, "y")
+    p, S, b, a, zi, need = _sos_prep(gy, b, a, zi, layout, chunk)
+    dev = gy.device
+    gx = torch.empty_like(gy) if "x" in want else None
+    gb = torch.empty_like(b) if "b" in want else None
+    ga = torch.empty_like(a) if "a" in want else None
+    gzi = torch.empty((S, p.B, 2), dtype=torch.float32, device=dev) if "zi" in want else None
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(_sos_lib().filt_sos_backward(ctypes.byref(p), S, _ptr(gy), _ptr(x), _ptr(y), _ptr(b),
+                                        _ptr(a), _ptr(zi), _ptr(gx), _ptr(gb), _ptr(ga),
+                                        _ptr(gzi), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                        _stream(dev, stream)))
+    return {k: v for k, v in (("x", gx), ("b", gb), ("a", ga), ("zi", gzi)) if v is not None}
+
+
 def profile_enable(on: bool):
     """Start (True) or stop (False) per-kernel event timing inside the library."""
     L = lib()
