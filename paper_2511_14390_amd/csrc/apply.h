@@ -17,7 +17,9 @@ namespace filt_detail {
 
 // ---------------------------------------------------------------- forward
 
-template <int W, bool TV, bool FIR, bool AV, typename io_t, typename acc_t>
+// KT bounds the taps the loops visit (a_1..a_KT, b_0..b_KT): the bucket width
+// by default, max(N, M) for narrower time-invariant filters (lti_tap_bound).
+template <int W, bool TV, bool FIR, bool AV, typename io_t, typename acc_t, int KT = W>
 __device__ __forceinline__ void fwd_apply_item(const Dims &d, const io_t *__restrict__ x,
                                                const io_t *__restrict__ xi,
                                                const io_t *__restrict__ bc,
@@ -96,6 +98,8 @@ __device__ __forceinline__ void fwd_apply_item(const Dims &d, const io_t *__rest
             if constexpr (FIR) {
 #pragma unroll
                 for (int k = W - 1; k >= 0; --k) {
+                    if (k > KT)
+                        continue;
                     if (k & 1)
                         p1 += cb[k] * hx[(s - k) & m];
                     else
@@ -107,6 +111,8 @@ __device__ __forceinline__ void fwd_apply_item(const Dims &d, const io_t *__rest
             // oldest taps first; the newest output is the last dependency
 #pragma unroll
             for (int k = W; k >= 2; --k) {
+                if (k > KT)
+                    continue;
                 if (k & 1)
                     p1 -= ca[k] * hy[(s - k) & m];
                 else
@@ -121,7 +127,7 @@ __device__ __forceinline__ void fwd_apply_item(const Dims &d, const io_t *__rest
     }
 }
 
-template <int W, bool TV, bool FIR, bool AV, typename io_t, typename acc_t>
+template <int W, bool TV, bool FIR, bool AV, typename io_t, typename acc_t, int KT = W>
 __global__ void __launch_bounds__(kThreads)
 k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
             const io_t *__restrict__ bc, const io_t *__restrict__ ac,
@@ -132,7 +138,7 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
         return;
     int64_t b, c, jj;
     decode(d, idx, d.C, b, c, jj);
-    fwd_apply_item<W, TV, FIR, AV, io_t, acc_t>(d, x, xi, bc, ac, yi, hin, y, b, c);
+    fwd_apply_item<W, TV, FIR, AV, io_t, acc_t, KT>(d, x, xi, bc, ac, yi, hin, y, b, c);
 }
 
 // ---------------------------------------------------------------- backward
@@ -145,7 +151,8 @@ k_fwd_apply(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
 // from windows wx[t mod W] = x[t], wy[t mod W] = y[t] that slide down in time.
 // Time-invariant filters write per-(b, c) FP64 partial sums to
 // part[(b*C + c)*(N+M+1)] = (ga_1..ga_N, gb_0..gb_M).  Chunk 0 writes gyi / gxi.
-template <int W, bool TV, bool FIR, bool GA, bool GB, bool AV, typename io_t, typename acc_t>
+template <int W, bool TV, bool FIR, bool GA, bool GB, bool AV, typename io_t, typename acc_t,
+          int KT = W>
 __device__ __forceinline__ void bwd_apply_item(
     const Dims &d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
     const io_t *__restrict__ xi, const io_t *__restrict__ y, const io_t *__restrict__ yi,
@@ -276,15 +283,17 @@ __device__ __forceinline__ void bwd_apply_item(
                     gxv += rs[(1 - s) & m];
                 gxrow[(t - t0) * sstride] = (io_t)gxv;
             }
-            ss[(1 - s) & m] = -ca[W] * yb;
+            ss[(1 - s) & m] = KT < W ? acc_t(0) : -ca[W] * yb;
 #pragma unroll
             for (int k = 1; k < W; ++k)
-                ss[(k + 1 - s) & m] -= ca[k] * yb;
+                if (k <= KT)
+                    ss[(k + 1 - s) & m] -= ca[k] * yb;
             if constexpr (FIR) {
                 rs[(1 - s) & m] = acc_t(0);
 #pragma unroll
                 for (int k = 1; k < W; ++k)
-                    rs[(k + 1 - s) & m] += cb[k] * yb;
+                    if (k <= KT)
+                        rs[(k + 1 - s) & m] += cb[k] * yb;
             }
             if constexpr (COEF) {
                 // only chunk 0's first block reaches times before 0
@@ -305,7 +314,8 @@ __device__ __forceinline__ void bwd_apply_item(
                     } else {
 #pragma unroll
                         for (int k = 0; k < W; ++k)
-                            sgb[k] += (double)(yb * wx[(s - k) & m]);
+                            if (k <= KT)
+                                sgb[k] += (double)(yb * wx[(s - k) & m]);
                     }
                 }
                 if constexpr (want_ga) {
@@ -343,7 +353,8 @@ __device__ __forceinline__ void bwd_apply_item(
                     } else {
 #pragma unroll
                         for (int k = 1; k <= W; ++k)
-                            sga[k] -= (double)(yb * wy[(s - k) & m]);
+                            if (k <= KT)
+                                sga[k] -= (double)(yb * wy[(s - k) & m]);
                     }
                 }
             }
@@ -372,7 +383,8 @@ __device__ __forceinline__ void bwd_apply_item(
     }
 }
 
-template <int W, bool TV, bool FIR, bool GA, bool GB, bool AV, typename io_t, typename acc_t>
+template <int W, bool TV, bool FIR, bool GA, bool GB, bool AV, typename io_t, typename acc_t,
+          int KT = W>
 __global__ void __launch_bounds__(kThreads)
 k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
             const io_t *__restrict__ xi, const io_t *__restrict__ y,
@@ -386,8 +398,8 @@ k_bwd_apply(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ x,
         return;
     int64_t b, c, jj;
     decode(d, idx, d.C, b, c, jj);
-    bwd_apply_item<W, TV, FIR, GA, GB, AV, io_t, acc_t>(d, gy, x, xi, y, yi, bc, ac, gin, gx, gb,
-                                                        ga, gxi, gyi, part, ybo, b, c);
+    bwd_apply_item<W, TV, FIR, GA, GB, AV, io_t, acc_t, KT>(d, gy, x, xi, y, yi, bc, ac, gin, gx,
+                                                            gb, ga, gxi, gyi, part, ybo, b, c);
 }
 
 // ---------------------------------------------------------------- drivers
@@ -708,9 +720,12 @@ filt_status fwd_apply(const Dims &d, const io_t *x, const io_t *bc, const io_t *
                     dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, x, xi, bc, ac, yi,
                     states, y);
     else
-        FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, false, FIR, false, io_t, acc_t>),
-                    dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, x, xi, bc, ac, yi,
-                    states, y);
+        lti_tap_bound<W, FIR, io_t, acc_t>(d, [&](auto kt) {
+            constexpr int KT = decltype(kt)::value;
+            FILT_LAUNCH("fwd_apply", (k_fwd_apply<W, false, FIR, false, io_t, acc_t, KT>),
+                        dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, x, xi,
+                        bc, ac, yi, states, y);
+        });
     return check_launch("forward apply");
 }
 
@@ -762,9 +777,12 @@ filt_status bwd_apply(const Dims &d, const io_t *gy, const io_t *x, const io_t *
                       double *part, io_t *ybo, hipStream_t st)
 {
 #define FILT_BWD_APPLY(TVV, GAV, GBV, AVV)                                                         \
-    FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, GAV, GBV, AVV, io_t, acc_t>),               \
-                dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, gy, x, xi, y, yi, bc, ac,     \
-                states, gx, gb, ga, gxi, gyi, part, ybo)
+    lti_tap_bound<W, FIR && !TVV, io_t, acc_t>(d, [&](auto kt) {                                   \
+        constexpr int KT = decltype(kt)::value;                                                    \
+        FILT_LAUNCH("bwd_apply", (k_bwd_apply<W, TVV, FIR, GAV, GBV, AVV, io_t, acc_t, KT>),       \
+                    dim3(blocks_for(d.B * d.C)), dim3(block_for(d.B * d.C)), 0, st, d, gy, x, xi,  \
+                    y, yi, bc, ac, states, gx, gb, ga, gxi, gyi, part, ybo);                       \
+    })
 #define FILT_BWD_APPLY_G(TVV, AVV)                                                                 \
     do {                                                                                           \
         if (ga != nullptr && gb != nullptr)                                                        \

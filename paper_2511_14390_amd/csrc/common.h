@@ -302,6 +302,37 @@ __device__ __forceinline__ void ld_row_lti(const Dims &d, const io_t *bc, const 
     cvt_row<W, FIR>(ra, rb, ca, cb);
 }
 
+// Time-invariant problems with an FIR part in the order-8 bucket (FP32 I/O,
+// FP64 state) run their tap loops up to the highest tap max(N, M) instead of
+// the bucket width, a compile-time bound: an M = N = 4 filter then issues
+// about half the FMAs of the width-8 loops (its other taps are zero).  Calls
+// f(std::integral_constant<int, KT>) with that bound, or with W.
+template <int W, bool FIR, typename io_t, typename acc_t, typename F>
+void lti_tap_bound(const Dims &d, F &&f)
+{
+    if constexpr (W == 8 && FIR && sizeof(io_t) == 4 && sizeof(acc_t) == 8) {
+        if (!d.tv) {
+            switch (d.N > d.M ? d.N : d.M) {
+            case 4:
+                f(std::integral_constant<int, 4>{});
+                return;
+            case 5:
+                f(std::integral_constant<int, 5>{});
+                return;
+            case 6:
+                f(std::integral_constant<int, 6>{});
+                return;
+            case 7:
+                f(std::integral_constant<int, 7>{});
+                return;
+            default:
+                break;
+            }
+        }
+    }
+    f(std::integral_constant<int, W>{});
+}
+
 // f(std::integral_constant<int, i>) for i = 0..n-1, in order.
 template <typename F, int... I>
 __device__ __forceinline__ void static_for_seq(F &&f, std::integer_sequence<int, I...>)

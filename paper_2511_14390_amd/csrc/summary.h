@@ -29,7 +29,10 @@ namespace filt_detail {
 
 // S forward recursions over [t0, t0 + L).  h[q][t mod W] = y_q[t]; hx[t mod
 // W] = x[t].  Slot q is driven by wgt[q] * (b * x)[t] (XIN) and its history.
-template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t>
+// KT bounds the taps the loops visit (a_1..a_KT, b_0..b_KT): the bucket width
+// W by default, the problem's max(N, M) for time-invariant coefficients of a
+// narrower order than the bucket (the other taps are zero).
+template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t, int KT = W>
 __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t t0, const Cursor<io_t> &xc,
                                            const Cursor<io_t> &acur, const Cursor<io_t> &bcur,
                                            double (&h)[S][W], double (&hx)[W],
@@ -76,7 +79,8 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t t0, const Curs
                 if constexpr (FIR) {
 #pragma unroll
                     for (int k = W - 1; k >= 0; --k)
-                        u += cb[k] * hx[(s - k) & m];
+                        if (k <= KT)
+                            u += cb[k] * hx[(s - k) & m];
                 } else {
                     u = cb[0] * hx[s & m];
                 }
@@ -86,6 +90,8 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t t0, const Curs
                 double p0 = XIN ? wgt[q] * u : 0.0, p1 = 0.0;
 #pragma unroll
                 for (int k = W; k >= 2; --k) {
+                    if (k > KT)
+                        continue;
                     if (k & 1)
                         p1 -= ca[k] * h[q][(s - k) & m];
                     else
@@ -107,7 +113,7 @@ __device__ __forceinline__ void fwd_solves(const Dims &d, int64_t t0, const Curs
 //   summ[(b*C + c)*(N*N + N) + i*N + j] = Phi_c[i][j] (per-sample coefficients)
 //   phi[b*N*N + i*N + j]                = Phi[i][j]   (time-invariant)
 //   summ[(b*C + c)*(N*N + N) + N*N + i] = s_c[i]
-template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t>
+template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t, int KT = W>
 __device__ __forceinline__ void fwd_summary_item(const Dims &d, const io_t *__restrict__ x,
                                                  const io_t *__restrict__ xi,
                                                  const io_t *__restrict__ bc,
@@ -143,7 +149,7 @@ __device__ __forceinline__ void fwd_summary_item(const Dims &d, const io_t *__re
         for (int k = 1; k < W; ++k)
             hx[(-k) & m] = ld_x<io_t, double>(d, x, xi, b, t0 - k);
     }
-    fwd_solves<W, S, TV, FIR, XIN, AV>(d, t0, xc, acur, bcur, h, hx, wgt, la, lb);
+    fwd_solves<W, S, TV, FIR, XIN, AV, io_t, KT>(d, t0, xc, acur, bcur, h, hx, wgt, la, lb);
     const int64_t SS = (int64_t)N * N + N;
 #pragma unroll
     for (int q = 0; q < S; ++q) {
@@ -166,7 +172,7 @@ __device__ __forceinline__ void fwd_summary_item(const Dims &d, const io_t *__re
     }
 }
 
-template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t>
+template <int W, int S, bool TV, bool FIR, bool XIN, bool AV, typename io_t, int KT = W>
 __global__ void __launch_bounds__(kThreads)
 k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
               const io_t *__restrict__ bc, const io_t *__restrict__ ac, int64_t c_first,
@@ -180,8 +186,8 @@ k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
     int64_t b, cc;
     int r;
     decode_lanes(d, idx, ncs, nl, b, cc, r);
-    fwd_summary_item<W, S, TV, FIR, XIN, AV>(d, x, xi, bc, ac, j_first, nj, summ, phi, b,
-                                             c_first + cc, r);
+    fwd_summary_item<W, S, TV, FIR, XIN, AV, io_t, KT>(d, x, xi, bc, ac, j_first, nj, summ, phi,
+                                                       b, c_first + cc, r);
 }
 
 // ---------------------------------------------------------------- backward
@@ -193,7 +199,8 @@ k_fwd_summary(Dims d, const io_t *__restrict__ x, const io_t *__restrict__ xi,
 // rs[q][(k - t) mod W].  Per step:
 //   ybar = wgt[q] gy[t] + s_1,  s_k <- s_{k+1} - a_k[t] ybar,
 //   r_k <- r_{k+1} + b_k[t] ybar.
-template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t>
+// KT bounds the taps as in fwd_solves (s_k, r_k for k > KT stay zero).
+template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t, int KT = W>
 __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t t0, const Cursor<io_t> &gc,
                                            const Cursor<io_t> &acur, const Cursor<io_t> &bcur,
                                            double (&ss)[S][W], double (&rs)[S][W],
@@ -242,15 +249,17 @@ __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t t0, const Curs
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 const double yb = (GIN ? wgt[q] * g : 0.0) + ss[q][(1 - s) & m];
-                ss[q][(1 - s) & m] = -ca[W] * yb;
+                ss[q][(1 - s) & m] = KT < W ? 0.0 : -ca[W] * yb;
 #pragma unroll
                 for (int k = 1; k < W; ++k)
-                    ss[q][(k + 1 - s) & m] -= ca[k] * yb;
+                    if (k <= KT)
+                        ss[q][(k + 1 - s) & m] -= ca[k] * yb;
                 if constexpr (FIR) {
                     rs[q][(1 - s) & m] = 0.0;
 #pragma unroll
                     for (int k = 1; k < W; ++k)
-                        rs[q][(k + 1 - s) & m] += cb[k] * yb;
+                        if (k <= KT)
+                            rs[q][(k + 1 - s) & m] += cb[k] * yb;
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -268,7 +277,7 @@ __device__ __forceinline__ void bwd_solves(const Dims &d, int64_t t0, const Curs
 // Time-invariant Phi' and R go to phi[b*(N*N + M*N) + ...].
 // Before the first (highest) time and after the last, s_k sits in slot
 // (k + 1) mod W.
-template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t>
+template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t, int KT = W>
 __device__ __forceinline__ void bwd_summary_item(const Dims &d, const io_t *__restrict__ gy,
                                                  const io_t *__restrict__ bc,
                                                  const io_t *__restrict__ ac, int j_first, int nj,
@@ -296,7 +305,7 @@ __device__ __forceinline__ void bwd_summary_item(const Dims &d, const io_t *__re
             rs[q][e] = 0.0;
         }
     }
-    bwd_solves<W, S, TV, FIR, GIN, AV>(d, t0, gc, acur, bcur, ss, rs, wgt, la, lb);
+    bwd_solves<W, S, TV, FIR, GIN, AV, io_t, KT>(d, t0, gc, acur, bcur, ss, rs, wgt, la, lb);
     const int64_t SB = (int64_t)(N + 1) * (N + M);
     double *base = summ + (b * d.C + c) * SB;
 #pragma unroll
@@ -326,7 +335,7 @@ __device__ __forceinline__ void bwd_summary_item(const Dims &d, const io_t *__re
     }
 }
 
-template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t>
+template <int W, int S, bool TV, bool FIR, bool GIN, bool AV, typename io_t, int KT = W>
 __global__ void __launch_bounds__(kThreads)
 k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
               const io_t *__restrict__ ac, int64_t c_first, int64_t ncs, int j_first, int nj,
@@ -339,8 +348,8 @@ k_bwd_summary(Dims d, const io_t *__restrict__ gy, const io_t *__restrict__ bc,
     int64_t b, cc;
     int r;
     decode_lanes(d, idx, ncs, nl, b, cc, r);
-    bwd_summary_item<W, S, TV, FIR, GIN, AV>(d, gy, bc, ac, j_first, nj, summ, phi, b,
-                                             c_first + cc, r);
+    bwd_summary_item<W, S, TV, FIR, GIN, AV, io_t, KT>(d, gy, bc, ac, j_first, nj, summ, phi, b,
+                                                       c_first + cc, r);
 }
 
 // ---------------------------------------------------------------- row solves
@@ -845,9 +854,12 @@ filt_status fwd_summary_fir(const Dims &d, const io_t *x, const io_t *xi, const 
                         dim3(blocks_for(d.B * ncs * nl)), dim3(block_for(d.B * ncs * nl)), 0, st, d, x, xi, bc, ac,
                         (int64_t)0, ncs, 0, N + 1, summ, phi);
     } else {
-        FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, 1, false, FIR, true, false, io_t>),
-                    dim3(blocks_for(d.B * ncs)), dim3(block_for(d.B * ncs)), 0, st, d, x, xi, bc, ac,
-                    (int64_t)0, ncs, N, 1, summ, phi);
+        lti_tap_bound<W, FIR, io_t, double>(d, [&](auto kt) {
+            constexpr int KT = decltype(kt)::value;
+            FILT_LAUNCH("fwd_summary", (k_fwd_summary<W, 1, false, FIR, true, false, io_t, KT>),
+                        dim3(blocks_for(d.B * ncs)), dim3(block_for(d.B * ncs)), 0, st, d, x, xi,
+                        bc, ac, (int64_t)0, ncs, N, 1, summ, phi);
+        });
         FILT_LAUNCH("fwd_summary_phi", (k_fwd_summary<W, 1, false, false, false, false, io_t>),
                     dim3(blocks_for(d.B * N)), dim3(block_for(d.B * N)), 0, st, d, x, xi, bc, ac, (int64_t)0,
                     (int64_t)1, 0, N, summ, phi);
@@ -900,9 +912,12 @@ filt_status bwd_summary_fir(const Dims &d, const io_t *gy, const io_t *bc, const
                         dim3(blocks_for(d.B * ncs * nl)), dim3(block_for(d.B * ncs * nl)), 0, st, d, gy, bc, ac,
                         (int64_t)1, ncs, 0, N + 1, summ, phi);
     } else {
-        FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, 1, false, FIR, true, false, io_t>),
-                    dim3(blocks_for(d.B * ncs)), dim3(block_for(d.B * ncs)), 0, st, d, gy, bc, ac, (int64_t)1,
-                    ncs, N, 1, summ, phi);
+        lti_tap_bound<W, FIR, io_t, double>(d, [&](auto kt) {
+            constexpr int KT = decltype(kt)::value;
+            FILT_LAUNCH("bwd_summary", (k_bwd_summary<W, 1, false, FIR, true, false, io_t, KT>),
+                        dim3(blocks_for(d.B * ncs)), dim3(block_for(d.B * ncs)), 0, st, d, gy, bc,
+                        ac, (int64_t)1, ncs, N, 1, summ, phi);
+        });
         if (N > 0)
             FILT_LAUNCH("bwd_summary_phi", (k_bwd_summary<W, 1, false, FIR, false, false, io_t>),
                         dim3(blocks_for(d.B * N)), dim3(block_for(d.B * N)), 0, st, d, gy, bc, ac,

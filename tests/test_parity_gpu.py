@@ -66,6 +66,11 @@ CASES = [
     (2, 2, False, "BT", 777, 64),
     (4, 4, False, "TB", 1500, 128),
     (3, 5, False, "BT", 999, 96),
+    # time-invariant filters narrower than their register bucket (tap loops
+    # bounded at max(N, M) = 5, 6, 7)
+    (5, 2, False, "BT", 800, 32),
+    (6, 3, False, "TB", 1300, 64),
+    (7, 7, False, "BT", 1100, 96),
     (0, 16, False, "BT", 2000, 256),
     (0, 2, True, "BT", 1000, 64),
     (2, 3, True, "TB", 901, 64),
