@@ -14,9 +14,11 @@ Array conventions (numpy, any real dtype; converted to float64 here):
 * ``b``: same with ``M + 1`` taps ``b_0..b_M``; ``None`` means ``b = [1]``.
 * ``xi``: ``[B, M]`` with ``xi[:, j-1] = x[-j]``; ``yi``: ``[B, N]``.
 
-Parity status: every function here is pinned by tests under
-``tests/test_oracle_pins.py`` (closed forms, SciPy, dense solves, finite
-differences, adjoint identity); none is "parity unpinned".
+Parity status: every function here is pinned by tests under ``tests/``
+(``test_oracle_pins.py``, ``test_oracle_frames.py``, ``test_oracle_tdf.py``,
+``test_oracle_sos.py``, ``test_oracle_backward2.py``: closed forms, SciPy,
+dense solves, finite differences, adjoint and pairing identities, Hessian
+symmetry); none is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -345,3 +347,184 @@ def sos_backward(gy, x, b, a, zi=None, layout="BT"):
         gb[s], ga[s], gzi[s] = r["b"], r["a"], r["zi"]
         g = r["x"]
     return {"x": g, "b": gb, "a": ga, "zi": gzi}
+
+
+# ---------------------------------------------------------------------------
+# Forward-mode derivative and the derivative of the backward pass (the
+# paper's closing remarks: forward-mode differentiation follows the same way
+# and serves second-order optimisation).  Plain FP64 loops over time,
+# channels vectorised; coefficients are taken as per-sample rows (time-
+# invariant ones repeated over time, their gradients summed over time).
+
+
+def _chan(v, layout):
+    """Signal as [B, T] (channel first)."""
+    return None if v is None else _chan_first(_f64(v), layout)
+
+
+def _rows(c, B, T, layout):
+    """Coefficients as per-sample rows [B, T, K] (channel first)."""
+    if c is None:
+        return None
+    c = _f64(c)
+    if c.ndim == 2:
+        return np.broadcast_to(c[:, None, :], (B, T, c.shape[1]))
+    return c if layout == "BT" else c.transpose(1, 0, 2)
+
+
+def _back(v, vi, n):
+    """v[:, n] for n >= 0, else the history vi[:, -n - 1] (zero past its end
+    or when vi is None)."""
+    if n >= 0:
+        return v[:, n]
+    j = -n
+    if vi is None or j > vi.shape[1]:
+        return 0.0
+    return vi[:, j - 1]
+
+
+def _out_sig(v, layout):
+    return v if layout == "BT" else v.T.copy()
+
+
+def _out_rows(g, tv, layout):
+    """Per-sample gradient rows [B, T, K] to the coefficient layout; summed
+    over time for time-invariant coefficients."""
+    if not tv:
+        return g.sum(axis=1)
+    return g if layout == "BT" else g.transpose(1, 0, 2).copy()
+
+
+def jvp(x, y, a, b=None, xi=None, yi=None, dx=None, da=None, db=None, dxi=None, dyi=None,
+        layout="BT"):
+    """Tangent of y = forward(x, a, b, xi, yi) along (dx, da, db, dxi, dyi)
+    (None = zero).  Eq. 1 differentiated term by term:
+        dy[n] = sum_k b_k[n] dx[n-k] + sum_k db_k[n] x[n-k]
+                - sum_k da_k[n] y[n-k] - sum_k a_k[n] dy[n-k],
+    with the histories xi, yi, dxi, dyi before time 0.  y is the forward's
+    output."""
+    xc, yc = _chan(x, layout), _chan(y, layout)
+    B, T = xc.shape
+    M = 0 if b is None else _f64(b).shape[-1] - 1
+    N = 0 if a is None else _f64(a).shape[-1]
+    ar, br = _rows(a, B, T, layout), _rows(b, B, T, layout)
+    dar, dbr = _rows(da, B, T, layout), _rows(db, B, T, layout)
+    dxc = _chan(dx, layout)
+    xi, yi, dxi, dyi = map(_f64, (xi, yi, dxi, dyi))
+    dy = np.zeros((B, T))
+    for n in range(T):
+        acc = np.zeros(B)
+        if dxc is not None or dxi is not None:
+            src = dxc if dxc is not None else np.zeros((B, T))
+            for k in range(M + 1):
+                bk = br[:, n, k] if br is not None else 1.0
+                acc += bk * _back(src, dxi, n - k)
+        if dbr is not None:
+            for k in range(M + 1):
+                acc += dbr[:, n, k] * _back(xc, xi, n - k)
+        if dar is not None:
+            for k in range(1, N + 1):
+                acc -= dar[:, n, k - 1] * _back(yc, yi, n - k)
+        for k in range(1, N + 1):
+            acc -= ar[:, n, k - 1] * _back(dy, dyi, n - k)
+        dy[:, n] = acc
+    return _out_sig(dy, layout)
+
+
+def backward2(gy, x, y, a, b=None, xi=None, yi=None, vx=None, va=None, vb=None, vxi=None,
+              vyi=None, layout="BT"):
+    """Derivative of the backward pass.  backward() maps (gy, x, y, a, b, xi,
+    yi) -- y taken as an input of its own -- to the gradients (gx, ga, gb,
+    gxi, gyi); for cotangents (vx, va, vb, vxi, vyi) of those (None = zero)
+    this returns the gradient of
+        Q = <vx, gx> + <va, ga> + <vb, gb> + <vxi, gxi> + <vyi, gyi>
+    with respect to every input, keys gy, x, y, a, b, xi, yi (b, xi only
+    when b is given, a / yi only when N > 0).
+
+    The gradients are the transposed Jacobian of the forward applied to gy,
+    so Q = <gy, dy> with dy the tangent jvp() gives along the cotangents, and
+    (ybar the adjoint, ybar[n] = gy[n] - sum_k a_k[n+k] ybar[n+k]) Q is the
+    pairing of ybar with dy's input terms plus the initial-condition terms.
+    Term by term:
+        d/dgy       = dy
+        d/dx[m]     = sum_{k=0..M} vb_k[m+k] ybar[m+k]
+        d/dxi_j     = sum_{k=j..M} vb_k[k-j] ybar[k-j]
+        d/dy[m]     = -sum_{k=1..N} va_k[m+k] ybar[m+k]
+        d/dyi_j     = -sum_{k=j..N} va_k[k-j] ybar[k-j]
+        d/db_k[n]   = ybar[n] vx[n-k]       (vx's history vxi)
+        d/da_k[n]   = -ybar[n] dy[n-k]      (dy's history vyi)
+    (time-invariant coefficients: the last two summed over n)."""
+    gyc, xc, yc = _chan(gy, layout), _chan(x, layout), _chan(y, layout)
+    B, T = gyc.shape
+    M = 0 if b is None else _f64(b).shape[-1] - 1
+    N = 0 if a is None else _f64(a).shape[-1]
+    tv = int((a is not None and _f64(a).ndim == 3) or (b is not None and _f64(b).ndim == 3))
+    ar = _rows(a, B, T, layout)
+    var, vbr = _rows(va, B, T, layout), _rows(vb, B, T, layout)
+    vxc = _chan(vx, layout)
+    vxi, vyi = _f64(vxi), _f64(vyi)
+    # adjoint of gy (the all-pole part of the backward)
+    yb = np.zeros((B, T))
+    for n in range(T - 1, -1, -1):
+        acc = gyc[:, n].copy()
+        for k in range(1, N + 1):
+            if n + k < T:
+                acc -= ar[:, n + k, k - 1] * yb[:, n + k]
+        yb[:, n] = acc
+    dy = _chan(jvp(x, y, a, b, xi, yi, dx=vx, da=va, db=vb, dxi=vxi, dyi=vyi,
+                   layout=layout), layout)
+    out = {"gy": _out_sig(dy, layout)}
+    gx = np.zeros((B, T))
+    gyo = np.zeros((B, T))
+    for m in range(T):
+        for k in range(M + 1):
+            if vbr is not None and m + k < T:
+                gx[:, m] += vbr[:, m + k, k] * yb[:, m + k]
+        for k in range(1, N + 1):
+            if var is not None and m + k < T:
+                gyo[:, m] -= var[:, m + k, k - 1] * yb[:, m + k]
+    out["x"] = _out_sig(gx, layout)
+    out["y"] = _out_sig(gyo, layout)
+    if b is not None:
+        gxi = np.zeros((B, M))
+        gb = np.zeros((B, T, M + 1))
+        for j in range(1, M + 1):
+            for k in range(j, M + 1):
+                if vbr is not None and k - j < T:
+                    gxi[:, j - 1] += vbr[:, k - j, k] * yb[:, k - j]
+        zeros = np.zeros((B, T))
+        for n in range(T):
+            for k in range(M + 1):
+                gb[:, n, k] = yb[:, n] * _back(vxc if vxc is not None else zeros, vxi, n - k)
+        out["b"] = _out_rows(gb, tv, layout)
+        out["xi"] = gxi
+    if N > 0:
+        gyi = np.zeros((B, N))
+        ga = np.zeros((B, T, N))
+        for j in range(1, N + 1):
+            for k in range(j, N + 1):
+                if var is not None and k - j < T:
+                    gyi[:, j - 1] -= var[:, k - j, k - 1] * yb[:, k - j]
+        for n in range(T):
+            for k in range(1, N + 1):
+                ga[:, n, k - 1] = -yb[:, n] * _back(dy, vyi, n - k)
+        out["a"] = _out_rows(ga, tv, layout)
+        out["yi"] = gyi
+    return out
+
+
+def backward2_frames(gy, x, y, a, b=None, xi=None, yi=None, vx=None, va=None, vb=None,
+                     vxi=None, vyi=None, hop=1, layout="BT"):
+    """backward2 with frame-held a, b (and their cotangents va, vb, one row
+    per frame): a frame's gradient row is the sum of its samples' rows, so
+    its cotangent applies to every sample of the frame; the a / b outputs
+    are summed per frame."""
+    x = _f64(x)
+    T = x.shape[0] if layout == "TB" else x.shape[1]
+    ex = lambda c: None if c is None else frame_expand(c, T, hop, layout)
+    g = backward2(gy, x, y, ex(a), ex(b), xi, yi, vx=vx, va=ex(va), vb=ex(vb), vxi=vxi, vyi=vyi,
+                  layout=layout)
+    for k in ("a", "b"):
+        if k in g:
+            g[k] = frame_reduce(g[k], hop, layout)
+    return g
