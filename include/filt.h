@@ -155,6 +155,34 @@ filt_status filt_jvp(const filt_problem *p, const float *x, const float *y, cons
                      const float *db, const float *da, const float *dxi, const float *dyi,
                      float *dy, void *ws, size_t ws_bytes, void *stream);
 
+/* Derivative of the backward pass (reverse over reverse: Hessian-vector
+ * products for the second-order optimisation the paper's closing remarks
+ * point to).  filt_backward maps (gy, x, y, a, b, xi, yi), y taken as an
+ * input of its own, to (gx, gb, ga, gxi, gyi); for cotangents vx, vb, va,
+ * vxi, vyi of those outputs (shapes of gx, gb, ga, gxi, gyi; each may be
+ * NULL = zero) this writes the gradients of
+ *   Q = <vx, gx> + <vb, gb> + <va, ga> + <vxi, gxi> + <vyi, gyi>:
+ *   wgy = dy, the forward-mode tangent along the cotangents (filt_jvp),
+ *   wx[m]     = sum_{k=0..M} vb_k[m+k] ybar[m+k],   wxi likewise,
+ *   wb_k[n]   = ybar[n] vx[n-k]   (history vxi),
+ *   wy[m]     = -sum_{k=1..N} va_k[m+k] ybar[m+k],  wyi likewise,
+ *   wa_k[n]   = -ybar[n] dy[n-k]  (history vyi),
+ * ybar the adjoint of gy; time-invariant wb / wa summed over n, frame-held
+ * ones over each frame.  Shapes: wgy, wx, wy [layout]; wb, wa, wxi, wyi as
+ * b, a, xi, yi.  Every output may be NULL (not computed).  b == NULL (b =
+ * [1]) needs M == 0 and vb, wb NULL; N == 0 needs va, wa NULL; vb needs x,
+ * va needs y.  T == 0 with B > 0 zero-fills the per-channel outputs given.
+ * FP32 entry point; async on stream, no allocation.  ws: at least
+ * filt_backward2_workspace_bytes(p) bytes (three signals, three coefficient
+ * arrays and the largest workspace of the passes it runs). */
+filt_status filt_backward2_workspace_bytes(const filt_problem *p, size_t *bytes);
+filt_status filt_backward2(const filt_problem *p, const float *gy, const float *x,
+                           const float *y, const float *b, const float *a, const float *xi,
+                           const float *yi, const float *vx, const float *vb, const float *va,
+                           const float *vxi, const float *vyi, float *wgy, float *wx, float *wy,
+                           float *wb, float *wa, float *wxi, float *wyi, void *ws,
+                           size_t ws_bytes, void *stream);
+
 /* Transposed direct form II with an initial state (Sec. 2: the state-space
  * form of Eqs. 4-5 with the companion matrix transposed and B, C swapped;
  * SciPy's lfilter(b, a, x, zi)), time-invariant coefficients only

@@ -8,7 +8,9 @@ direct form the filter state at any chunk boundary is a slice of ``y``
 (the last N outputs) and of ``x``, so nothing else needs to be stored and the
 backward recomputes everything else from them.  Gradients are requested only
 for the inputs that need them (``ctx.needs_input_grad``).  The backward is
-not itself differentiable (second derivatives through it raise).
+itself differentiable (``LFilterGrad``, FP32): its backward is
+``filt_backward2``, so ``create_graph=True`` gives Hessian-vector products
+by reverse over reverse.
 """
 from __future__ import annotations
 
@@ -38,19 +40,58 @@ class LFilter(torch.autograd.Function):
                            layout=layout, chunk=chunk, hop=hop)
 
     @staticmethod
-    @once_differentiable
     def backward(ctx, gy):
         x, a, b, xi, yi, y = ctx.saved_tensors
-        layout, chunk, f32_state, toeplitz, hop = ctx.cfg
         need = ctx.needs_input_grad
-        want = [k for k, n in zip(("x", "a", "b", "xi", "yi"), need[:5]) if n]
+        want = tuple(k for k, n in zip(("x", "a", "b", "xi", "yi"), need[:5]) if n)
         if not want:
             return (None,) * 10
+        # a differentiable call: under create_graph its backward is
+        # filt_backward2 (and y's gradient flows on through this filter)
+        gx, ga, gb, gxi, gyi = LFilterGrad.apply(gy, x, y, a, b, xi, yi, ctx.cfg, want)
+        return (gx, ga, gb if b is not None else None, gxi if xi is not None else None,
+                gyi if yi is not None else None, None, None, None, None, None)
+
+
+class LFilterGrad(torch.autograd.Function):
+    """The backward of LFilter as a function of (gy, x, y, a, b, xi, yi):
+    forward filt_backward, backward filt_backward2 (FP32)."""
+
+    @staticmethod
+    def forward(ctx, gy, x, y, a, b, xi, yi, cfg, want):
+        layout, chunk, f32_state, toeplitz, hop = cfg
         g = _f.filt_backward(gy, x, y, a, b, xi, yi, layout=layout, chunk=chunk,
-                             f32_state=f32_state, toeplitz=toeplitz, hop=hop, want=tuple(want))
-        return (g.get("x"), g.get("a"), g.get("b") if b is not None else None,
-                g.get("xi") if xi is not None else None, g.get("yi") if yi is not None else None,
-                None, None, None, None, None)
+                             f32_state=f32_state, toeplitz=toeplitz, hop=hop, want=want)
+        ctx.save_for_backward(gy, x, y, a, b, xi, yi)
+        ctx.cfg = cfg
+        ctx.set_materialize_grads(False)
+        return tuple(g.get(k) for k in ("x", "a", "b", "xi", "yi"))
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, vx, va, vb, vxi, vyi):
+        gy, x, y, a, b, xi, yi = ctx.saved_tensors
+        layout, chunk, f32_state, toeplitz, hop = ctx.cfg
+        names = ("gy", "x", "y", "a", "b", "xi", "yi")
+        want = tuple(k for k, n in zip(names, ctx.needs_input_grad[:7]) if n)
+        if not want or all(v is None for v in (vx, va, vb, vxi, vyi)):
+            return (None,) * 9
+        if gy.dtype != torch.float32:
+            raise NotImplementedError("second derivatives run in FP32 only")
+        N = 0 if a is None else a.shape[-1]
+        M = 0 if b is None else b.shape[-1] - 1
+        # cotangents of outputs that are empty carry nothing
+        vxi = vxi if (vxi is not None and M > 0) else None
+        vyi = vyi if (vyi is not None and N > 0) else None
+        w = _f.filt_backward2(gy, x, y, a, b, xi, yi, vx=vx, va=va, vb=vb, vxi=vxi, vyi=vyi,
+                              layout=layout, chunk=chunk, f32_state=f32_state,
+                              toeplitz=toeplitz, hop=hop, want=want)
+        out = [w.get(k) for k in names]
+        # inputs that were not given (None) get no gradient
+        for i, t in enumerate((gy, x, y, a, b, xi, yi)):
+            if t is None:
+                out[i] = None
+        return tuple(out) + (None, None)
 
 
 def lfilter(x, a, b=None, xi=None, yi=None, layout="BT", chunk=0, f32_state=False,

@@ -240,6 +240,63 @@ def filt_jvp(x, y, a, b=None, xi=None, yi=None, *, dx=None, db=None, da=None, dx
     return dy
 
 
+def filt_backward2(gy, x, y, a, b=None, xi=None, yi=None, *, vx=None, va=None, vb=None,
+                   vxi=None, vyi=None, layout="BT", chunk=0, f32_state=False, toeplitz=False,
+                   hop=1, want=("gy", "x", "y", "a", "b", "xi", "yi"), ws=None, stream=None):
+    """Derivative of filt_backward (see filt_backward2 in include/filt.h):
+    the gradients of sum_k <v_k, filt_backward(...)_k> for the cotangents
+    vx, va, vb, vxi, vyi (None = zero).  Returns a dict with the requested
+    keys among gy, x, y, a, b, xi, yi (b, xi only with b; a, yi only with
+    N > 0)."""
+    dev = gy.device
+    if dev.type != "cuda":
+        raise ValueError("filt_backward2 runs on the GPU only")
+    if gy.dtype != torch.float32:
+        raise ValueError("filt_backward2 takes float32 tensors")
+    L = lib()
+    if not getattr(L, "_b2_ready", False):
+        PP, P = ctypes.POINTER(FiltProblem), ctypes.c_void_p
+        L.filt_backward2_workspace_bytes.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+        L.filt_backward2_workspace_bytes.restype = ctypes.c_int
+        L.filt_backward2.argtypes = [PP] + [P] * 19 + [P, ctypes.c_size_t, P]
+        L.filt_backward2.restype = ctypes.c_int
+        L._b2_ready = True
+    gy = gy.contiguous()
+    x, y, a, b, xi, yi, vx, va, vb, vxi, vyi = (
+        _prep(t, torch.float32, dev, n) for t, n in
+        ((x, "x"), (y, "y"), (a, "a"), (b, "b"), (xi, "xi"), (yi, "yi"), (vx, "vx"),
+         (va, "va"), (vb, "vb"), (vxi, "vxi"), (vyi, "vyi")))
+    p = problem(gy, a, b, layout, chunk, f32_state, False, toeplitz, hop)
+    B, M, N = p.B, p.M, p.N
+    out = {}
+    if "gy" in want:
+        out["gy"] = torch.empty_like(gy)
+    if "x" in want:
+        out["x"] = torch.empty_like(gy)
+    if "y" in want:
+        out["y"] = torch.empty_like(gy)
+    if "b" in want and b is not None:
+        out["b"] = torch.empty_like(b)
+    if "a" in want and a is not None and N > 0:
+        out["a"] = torch.empty_like(a)
+    if "xi" in want and b is not None:
+        out["xi"] = torch.empty((B, M), dtype=gy.dtype, device=dev)
+    if "yi" in want and N > 0:
+        out["yi"] = torch.empty((B, N), dtype=gy.dtype, device=dev)
+    n = ctypes.c_size_t(0)
+    _check(L.filt_backward2_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    if ws is None or ws.numel() < n.value:
+        ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=dev)
+    g = out.get
+    _check(L.filt_backward2(ctypes.byref(p), _ptr(gy), _ptr(x), _ptr(y), _ptr(b), _ptr(a),
+                            _ptr(xi), _ptr(yi), _ptr(vx), _ptr(vb), _ptr(va), _ptr(vxi),
+                            _ptr(vyi), _ptr(g("gy")), _ptr(g("x")), _ptr(g("y")), _ptr(g("b")),
+                            _ptr(g("a")), _ptr(g("xi") if M > 0 else None),
+                            _ptr(g("yi") if N > 0 else None), _ptr(ws),
+                            ctypes.c_size_t(ws.numel()), _stream(dev, stream)))
+    return out
+
+
 def _tdf_lib():
     L = lib()
     if not getattr(L, "_tdf_ready", False):

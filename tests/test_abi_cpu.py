@@ -244,3 +244,40 @@ def test_plan_api_is_all_pole(L):
     assert fields == ["x_off", "T", "a_off", "ic_off", "N", "hop"]
     assert len(L.filt_plan_forward.argtypes) == 6
     assert len(L.filt_plan_backward.argtypes) == 9
+
+
+def test_backward2_checks_arguments_on_host(L):
+    L.filt_backward2_workspace_bytes.argtypes = [ctypes.POINTER(F.FiltProblem),
+                                                 ctypes.POINTER(ctypes.c_size_t)]
+    L.filt_backward2.argtypes = ([ctypes.POINTER(F.FiltProblem)] + [ctypes.c_void_p] * 19
+                                 + [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p])
+    n = ctypes.c_size_t(7)
+    assert L.filt_backward2_workspace_bytes(ctypes.byref(_prob(T=0)), ctypes.byref(n)) == 0
+    assert n.value == 0
+    # the workspace holds the passes' own workspaces and three signals
+    p = _prob(B=4, T=1000, M=2, N=3)
+    assert L.filt_backward2_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
+    wf = ctypes.c_size_t(0)
+    assert L.filt_workspace_bytes(ctypes.byref(p), ctypes.byref(wf)) == 0
+    assert n.value >= 3 * 4 * 1000 * 4
+    fake = ctypes.c_void_p(0x1000)  # rejected before any access
+
+    def call(p, **given):
+        names = ("gy", "x", "y", "b", "a", "xi", "yi", "vx", "vb", "va", "vxi", "vyi", "wgy",
+                 "wx", "wy", "wb", "wa", "wxi", "wyi")
+        args = [given.get(k) for k in names]
+        return L.filt_backward2(ctypes.byref(p), *args, None, ctypes.c_size_t(0), None)
+
+    # b = [1] (NULL) with a cotangent or gradient for b
+    q = _prob(M=0, N=2)
+    assert call(q, gy=fake, a=fake, vb=fake) == F.FILT_EINVAL
+    assert call(q, gy=fake, a=fake, wb=fake) == F.FILT_EINVAL
+    # no feedback part but va / wa given
+    q = _prob(M=1, N=0)
+    assert call(q, gy=fake, b=fake, va=fake) == F.FILT_EINVAL
+    # a missing with N > 0
+    assert call(_prob(M=0, N=2), gy=fake) == F.FILT_EINVAL
+    # B == 0: nothing to do
+    assert call(_prob(B=0, M=0, N=2), gy=fake, a=fake, wgy=fake) == F.FILT_OK
+    # workspace too small
+    assert call(_prob(M=0, N=2), gy=fake, a=fake, wgy=fake) == F.FILT_EWORKSPACE
