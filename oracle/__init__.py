@@ -16,7 +16,8 @@ Array conventions (numpy, any real dtype; converted to float64 here):
 
 Parity status: every function here is pinned by tests under ``tests/``
 (``test_oracle_pins.py``, ``test_oracle_frames.py``, ``test_oracle_tdf.py``,
-``test_oracle_sos.py``, ``test_oracle_backward2.py``: closed forms, SciPy,
+``test_oracle_sos.py``, ``test_oracle_backward2.py``, ``test_oracle_mr.py``:
+closed forms, SciPy,
 dense solves, finite differences, adjoint and pairing identities, Hessian
 symmetry); none is "parity unpinned".
 """
@@ -528,3 +529,51 @@ def backward2_frames(gy, x, y, a, b=None, xi=None, yi=None, vx=None, va=None, vb
         if k in g:
             g[k] = frame_reduce(g[k], hop, layout)
     return g
+
+
+# ---------------------------------------------------------------------------
+# Matrix recurrence: the state-space recursion of Sec. 2 Eq. 4 with the input
+# already in state space, the operator of App. B, batched over channels:
+#   v(n+1) = A v(n) + z(n),  n = 0 .. T-1,  v(0) = v0,
+# output v(1) .. v(T).  Backward (Sec. 3.1 Eqs. 7 and 9 for this operator):
+# the adjoint of the input runs the same recursion with A transposed in
+# reverse time, gz(n) = gv(n) + A^T gz(n+1) with gz(T) = 0; then
+# gv0 = A^T gz(0) and gA = sum_n gz(n) v(n)^T (v(0) = v0).
+#
+# Shapes: A [B, K, K] (v_i(n+1) = sum_j A[b, i, j] v_j(n) + z_i(n)); v0 [B, K]
+# or None (zero); z, v, gv, gz [B, T, K] (layout "BT") or [T, B, K] ("TB").
+
+
+def _mr_chan(s, layout):
+    return s if layout == "BT" else s.transpose(1, 0, 2)
+
+
+def mr_forward(A, v0, z, layout="BT"):
+    """v(1..T) of the matrix recurrence (FP64)."""
+    A, z = _f64(A), _mr_chan(_f64(z), layout)
+    B, T, K = z.shape
+    v = np.zeros((B, T, K))
+    cur = np.zeros((B, K)) if v0 is None else _f64(v0).copy()
+    for n in range(T):
+        cur = np.einsum("bij,bj->bi", A, cur) + z[:, n]
+        v[:, n] = cur
+    return np.ascontiguousarray(_mr_chan(v, layout))
+
+
+def mr_backward(gv, A, v0, v, layout="BT"):
+    """Gradients {z, A, v0} of <gv, v> for the matrix recurrence; v is the
+    forward's output."""
+    A, gv, v = _f64(A), _mr_chan(_f64(gv), layout), _mr_chan(_f64(v), layout)
+    B, T, K = gv.shape
+    v0 = np.zeros((B, K)) if v0 is None else _f64(v0)
+    gz = np.zeros((B, T, K))
+    acc = np.zeros((B, K))
+    for n in range(T - 1, -1, -1):
+        acc = gv[:, n] + np.einsum("bji,bj->bi", A, acc)
+        gz[:, n] = acc
+    gA = np.zeros((B, K, K))
+    for n in range(T):
+        prev = v0 if n == 0 else v[:, n - 1]
+        gA += gz[:, n, :, None] * prev[:, None, :]
+    gv0 = np.einsum("bji,bj->bi", A, gz[:, 0]) if T > 0 else np.zeros((B, K))
+    return {"z": np.ascontiguousarray(_mr_chan(gz, layout)), "A": gA, "v0": gv0}
