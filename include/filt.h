@@ -183,6 +183,27 @@ filt_status filt_backward2(const filt_problem *p, const float *gy, const float *
                            float *wb, float *wa, float *wxi, float *wyi, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* Matrix recurrence (the state-space recursion of Sec. 2 Eq. 4 with the
+ * input already in state space; the operator of App. B), per channel b:
+ *   v(n+1) = A v(n) + z(n),  n = 0 .. T-1,  v(0) = v0,
+ * output v(1) .. v(T).  The problem takes p->N = K, the state size
+ * (1 <= K <= 16), p->M = 0, p->time_varying = 0; p->chunk as for the filters.
+ * A [B][K][K] row-major (v_i(n+1) = sum_j A[b][i][j] v_j(n) + z_i(n)),
+ * v0 [B][K] or NULL (zero); z, v [B][T][K] (FILT_LAYOUT_BT) or [T][B][K]
+ * (FILT_LAYOUT_TB), v[.., n, ..] = v(n+1).  The state runs in FP64.
+ * Backward (Sec. 3.1 Eqs. 7 and 9 for this operator), given gv = dL/dv:
+ *   gz(n) = gv(n) + A^T gz(n+1) (gz(T) = 0),  gv0 = A^T gz(0),
+ *   gA = sum_n gz(n) v(n)^T  (v(0) = v0),
+ * gz [layout] required, gA [B][K][K] and gv0 [B][K] may be NULL; v is
+ * filt_mr_forward's output.  T == 0 with B > 0: the backward zero-fills gA
+ * and gv0.  ws: at least filt_mr_workspace_bytes(p) bytes. */
+filt_status filt_mr_workspace_bytes(const filt_problem *p, size_t *bytes);
+filt_status filt_mr_forward(const filt_problem *p, const float *A, const float *v0,
+                            const float *z, float *v, void *ws, size_t ws_bytes, void *stream);
+filt_status filt_mr_backward(const filt_problem *p, const float *A, const float *v0,
+                             const float *v, const float *gv, float *gz, float *gA, float *gv0,
+                             void *ws, size_t ws_bytes, void *stream);
+
 /* Transposed direct form II with an initial state (Sec. 2: the state-space
  * form of Eqs. 4-5 with the companion matrix transposed and B, C swapped;
  * SciPy's lfilter(b, a, x, zi)), time-invariant coefficients only

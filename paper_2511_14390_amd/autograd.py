@@ -185,3 +185,37 @@ def sosfilt(x, b, a, zi=None, layout="BT", chunk=0):
     channel SciPy's ``sosfilt``."""
     return SOSFilter.apply(x.contiguous(), b.contiguous(), a.contiguous(),
                            None if zi is None else zi.contiguous(), layout, int(chunk))
+
+
+class MatrixRecurrence(torch.autograd.Function):
+    """v(n+1) = A v(n) + z(n) per channel (the operator of App. B): forward
+    filt_mr_forward, backward filt_mr_backward (the same recursion with A
+    transposed in reverse time, then gA and gv0).  Saves A, v0 and v."""
+
+    @staticmethod
+    def forward(ctx, A, v0, z, layout, chunk):
+        v = _f.filt_mr_forward(A, z, v0, layout=layout, chunk=chunk)
+        ctx.save_for_backward(A, v0, v)
+        ctx.cfg = (layout, chunk)
+        return v
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, gv):
+        A, v0, v = ctx.saved_tensors
+        layout, chunk = ctx.cfg
+        need = ctx.needs_input_grad
+        if not any(need[:3]):
+            return (None,) * 5
+        want = tuple(k for k, n in zip(("A", "v0"), need[:2]) if n)
+        g = _f.filt_mr_backward(gv, A, v, v0, layout=layout, chunk=chunk, want=want)
+        return (g.get("A"), g.get("v0") if v0 is not None else None,
+                g["z"] if need[2] else None, None, None)
+
+
+def matrix_recurrence(A, z, v0=None, layout="BT", chunk=0):
+    """Differentiable v(1..T) of v(n+1) = A v(n) + z(n), v(0) = v0, per
+    channel: A [B, K, K], z [B, T, K] ("BT") or [T, B, K] ("TB"),
+    v0 [B, K] or None; 1 <= K <= 16."""
+    return MatrixRecurrence.apply(A.contiguous(), None if v0 is None else v0.contiguous(),
+                                  z.contiguous(), layout, int(chunk))

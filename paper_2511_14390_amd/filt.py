@@ -297,6 +297,80 @@ def filt_backward2(gy, x, y, a, b=None, xi=None, yi=None, *, vx=None, va=None, v
     return out
 
 
+def _mr_lib():
+    L = lib()
+    if not getattr(L, "_mr_ready", False):
+        PP, P = ctypes.POINTER(FiltProblem), ctypes.c_void_p
+        L.filt_mr_workspace_bytes.argtypes = [PP, ctypes.POINTER(ctypes.c_size_t)]
+        L.filt_mr_workspace_bytes.restype = ctypes.c_int
+        L.filt_mr_forward.argtypes = [PP] + [P] * 4 + [P, ctypes.c_size_t, P]
+        L.filt_mr_forward.restype = ctypes.c_int
+        L.filt_mr_backward.argtypes = [PP] + [P] * 7 + [P, ctypes.c_size_t, P]
+        L.filt_mr_backward.restype = ctypes.c_int
+        L._mr_ready = True
+    return L
+
+
+def _mr_prep(A, z, layout, chunk):
+    if z.dim() != 3:
+        raise ValueError("z must be [B, T, K] or [T, B, K]")
+    T, B = (z.shape[0], z.shape[1]) if layout == "TB" else (z.shape[1], z.shape[0])
+    K = z.shape[2]
+    if tuple(A.shape) != (B, K, K):
+        raise ValueError(f"A must be {(B, K, K)}, got {tuple(A.shape)}")
+    p = FiltProblem(B, T, 0, K, 0, _layout_code(layout), 0, int(chunk))
+    L = _mr_lib()
+    n = ctypes.c_size_t(0)
+    _check(L.filt_mr_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return p, L, n.value
+
+
+def filt_mr_forward(A, z, v0=None, *, layout="BT", chunk=0, ws=None, stream=None):
+    """Matrix recurrence v(n+1) = A v(n) + z(n) per channel (see
+    filt_mr_forward in include/filt.h).  A [B, K, K]; z [B, T, K] ("BT") or
+    [T, B, K] ("TB"); v0 [B, K] or None.  Returns v (the shape of z)."""
+    dev = z.device
+    if dev.type != "cuda" or z.dtype != torch.float32:
+        raise ValueError("filt_mr_forward takes float32 tensors on the GPU")
+    z = z.contiguous()
+    A, v0 = (_prep(t, torch.float32, dev, n) for t, n in ((A, "A"), (v0, "v0")))
+    p, L, need = _mr_prep(A, z, layout, chunk)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    v = torch.empty_like(z)
+    _check(L.filt_mr_forward(ctypes.byref(p), _ptr(A), _ptr(v0), _ptr(z), _ptr(v), _ptr(ws),
+                             ctypes.c_size_t(ws.numel()), _stream(dev, stream)))
+    return v
+
+
+def filt_mr_backward(gv, A, v, v0=None, *, layout="BT", chunk=0, want=("z", "A", "v0"),
+                     ws=None, stream=None):
+    """Gradients of the matrix recurrence for dL/dv = gv; v is the forward's
+    output.  Returns a dict with z (always), and A / v0 if requested (v0
+    only when v0 was given)."""
+    dev = gv.device
+    if dev.type != "cuda" or gv.dtype != torch.float32:
+        raise ValueError("filt_mr_backward takes float32 tensors on the GPU")
+    gv = gv.contiguous()
+    A, v, v0 = (_prep(t, torch.float32, dev, n) for t, n in ((A, "A"), (v, "v"), (v0, "v0")))
+    p, L, need = _mr_prep(A, gv, layout, chunk)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    gz = torch.empty_like(gv)
+    gA = torch.empty_like(A) if "A" in want else None
+    gv0 = torch.empty((p.B, p.N), dtype=gv.dtype, device=dev) \
+        if ("v0" in want and v0 is not None) else None
+    _check(L.filt_mr_backward(ctypes.byref(p), _ptr(A), _ptr(v0), _ptr(v), _ptr(gv), _ptr(gz),
+                              _ptr(gA), _ptr(gv0), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                              _stream(dev, stream)))
+    out = {"z": gz}
+    if gA is not None:
+        out["A"] = gA
+    if gv0 is not None:
+        out["v0"] = gv0
+    return out
+
+
 def _tdf_lib():
     L = lib()
     if not getattr(L, "_tdf_ready", False):
