@@ -65,6 +65,11 @@ def parse():
                     help="lti-df-m4n4: the transposed direct form II with an initial state "
                          "(zi drawn like the workload's initial conditions) instead of the "
                          "direct form with input / output histories")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="the paper's own benchmark: the state-space recursion "
+                         "v(n+1) = A v(n) + z(n) with a 2-dimensional state, one signal of "
+                         "T = 2^14 .. 2^20 samples, forward and forward + backward times, "
+                         "beside the same lengths of the order-2 all-pole direct form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -481,12 +486,84 @@ def batched_main(args):
     print(json.dumps(rec), flush=True)
 
 
+# The paper's Figure 1 (RTX 5060 Ti, FP32, batch unstated): its custom
+# operator's forward and "backprop" runtimes in microseconds at
+# T = 2^14, 2^16, 2^18, 2^20.
+PAPER_FIG1_GPU_US = {"fwd": [135.0, 141.0, 155.3, 213.6], "backprop": [451.5, 463.0, 709.6,
+                                                                          2394.9]}
+
+
+def paper_sweep_main(args):
+    """The state-space recursion of the paper's benchmark (2-dimensional
+    state, time-invariant, one signal) through the autograd functions:
+    median forward and forward + backward times over the timed repeats,
+    each bracketed by events on the current stream."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2511_14390_amd import autograd as AG
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(2024)
+    # a stable 2 x 2 transition with complex poles (radius 0.95, angle 0.3)
+    r, th = 0.95, 0.3
+    A = np.array([[[r * math.cos(th), -r * math.sin(th)], [r * math.sin(th), r * math.cos(th)]]],
+                 np.float32)
+    rows = []
+    for e, T in enumerate((1 << 14, 1 << 16, 1 << 18, 1 << 20)):
+        z = torch.from_numpy(rng.standard_normal((1, T, 2)).astype(np.float32)).to(dev)
+        gv = torch.from_numpy(rng.standard_normal((1, T, 2)).astype(np.float32)).to(dev)
+        At = torch.from_numpy(A).to(dev)
+        x = torch.from_numpy(rng.standard_normal((1, T)).astype(np.float32)).to(dev)
+        gy = torch.from_numpy(rng.standard_normal((1, T)).astype(np.float32)).to(dev)
+        a = torch.tensor([[-2 * r * math.cos(th), r * r]], dtype=torch.float32, device=dev)
+
+        def timed(fn):
+            for _ in range(args.warmup):
+                fn()
+            ts = []
+            for _ in range(args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e3)
+            return float(np.median(ts))
+
+        zr, Ar, xr, ar = (v.clone().requires_grad_(True) for v in (z, At, x, a))
+        mr_f = timed(lambda: AG.matrix_recurrence(At, z))
+        mr_fb = timed(lambda: torch.autograd.grad(AG.matrix_recurrence(Ar, zr), [Ar, zr], gv))
+        df_f = timed(lambda: AG.lfilter(x, a))
+        df_fb = timed(lambda: torch.autograd.grad(AG.lfilter(xr, ar), [xr, ar], gy))
+        rows.append({"T": T, "mr_fwd_us": round(mr_f, 1), "mr_fwd_bwd_us": round(mr_fb, 1),
+                     "df_fwd_us": round(df_f, 1), "df_fwd_bwd_us": round(df_fb, 1),
+                     "paper_fwd_us": PAPER_FIG1_GPU_US["fwd"][e],
+                     "paper_backprop_us": PAPER_FIG1_GPU_US["backprop"][e]})
+    last = rows[-1]
+    rec = {"metric": "the paper's Figure 1 workload: state-space recursion (2-dim state), "
+                     "forward + backward time at T = 2^20",
+           "value": last["mr_fwd_bwd_us"], "unit": "us", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(last["mr_fwd_bwd_us"] * 1e-3, 4),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "paper-fig1-state-space-m2", "io": "f32", "B": 1,
+                      "K": 2, "parallelism": "single GPU",
+                      "paper_hardware": "RTX 5060 Ti (the paper's; context only)"},
+           "sweep": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.paper_sweep:
+        return paper_sweep_main(args)
     if args.workload == "batched-ragged":
         return batched_main(args)
     import numpy as np

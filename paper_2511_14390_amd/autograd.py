@@ -46,9 +46,15 @@ class LFilter(torch.autograd.Function):
         want = tuple(k for k, n in zip(("x", "a", "b", "xi", "yi"), need[:5]) if n)
         if not want:
             return (None,) * 10
-        # a differentiable call: under create_graph its backward is
-        # filt_backward2 (and y's gradient flows on through this filter)
-        gx, ga, gb, gxi, gyi = LFilterGrad.apply(gy, x, y, a, b, xi, yi, ctx.cfg, want)
+        if torch.is_grad_enabled():
+            # create_graph: a differentiable call whose backward is
+            # filt_backward2 (y's gradient flows on through this filter)
+            gx, ga, gb, gxi, gyi = LFilterGrad.apply(gy, x, y, a, b, xi, yi, ctx.cfg, want)
+        else:
+            layout, chunk, f32_state, toeplitz, hop = ctx.cfg
+            g = _f.filt_backward(gy, x, y, a, b, xi, yi, layout=layout, chunk=chunk,
+                                 f32_state=f32_state, toeplitz=toeplitz, hop=hop, want=want)
+            gx, ga, gb, gxi, gyi = (g.get(k) for k in ("x", "a", "b", "xi", "yi"))
         return (gx, ga, gb if b is not None else None, gxi if xi is not None else None,
                 gyi if yi is not None else None, None, None, None, None, None)
 

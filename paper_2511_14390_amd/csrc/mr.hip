@@ -296,19 +296,26 @@ k_mr_apply(MrDims d, const float *__restrict__ A, int trans, const float *__rest
     }
 }
 
-// gA[b][i][j] = sum over chunks of the partials (FP64, in chunk order).
+// gA[b][i][j] = sum over chunks of the partials: one workgroup per element,
+// strided FP64 partial sums and a fixed-shape tree in LDS (deterministic).
 __global__ void __launch_bounds__(256)
 k_mr_reduce(MrDims d, const double *__restrict__ part, float *__restrict__ gA)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double red[256];
     const int64_t KK = (int64_t)d.K * d.K;
-    if (g >= d.B * KK)
-        return;
-    const int64_t b = g / KK, e = g % KK;
+    const int64_t b = blockIdx.x / KK, e = blockIdx.x % KK;
     double s = 0.0;
-    for (int64_t c = 0; c < d.C; ++c)
+    for (int64_t c = threadIdx.x; c < d.C; c += blockDim.x)
         s += part[(b * d.C + c) * KK + e];
-    gA[g] = (float)s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        gA[blockIdx.x] = (float)red[0];
 }
 
 __global__ void __launch_bounds__(256) k_mr_zero(float *__restrict__ p, int64_t n)
@@ -431,9 +438,8 @@ filt_status mr_run(const MrDims &d, const float *A, const float *in, const float
     filt_status s = check_launch("matrix recurrence apply");
     if (s != FILT_OK || !REV || gA == nullptr)
         return s;
-    const int64_t n = d.B * d.K * d.K;
-    FILT_LAUNCH("mr_reduce", k_mr_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d,
-                part, gA);
+    FILT_LAUNCH("mr_reduce", k_mr_reduce, dim3((unsigned)(d.B * d.K * d.K)), dim3(256), 0, st,
+                d, part, gA);
     return check_launch("matrix recurrence gA");
 }
 
