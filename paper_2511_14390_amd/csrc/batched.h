@@ -34,6 +34,13 @@ struct Item {
     int32_t seg, chunk, lane, pad;
 };
 
+}  // namespace filt_detail
+
+// staged order-16 applies: need SegDesc and Item
+#include "quadstage.h"
+
+namespace filt_detail {
+
 __device__ __forceinline__ Dims seg_dims(const SegDesc &s)
 {
     Dims d{};
@@ -579,9 +586,10 @@ filt_status batched_fwd_apply(const BucketArgs &b, const float *x, const float *
         return FILT_OK;
     if constexpr (W == 16) {
         const dim3 grid((unsigned)((b.app_n * 4 + kThreads - 1) / kThreads));
+        const dim3 sgrid((unsigned)((b.app_n + kQuadChains - 1) / kQuadChains));
         if (b.av)
-            FILT_LAUNCH(FILT_BNAME("batched_fwd_apply", W), kb_fwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
-                        b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
+            FILT_LAUNCH(FILT_BNAME("batched_fwd_apply", W), kb_fwd_apply_quad_staged, sgrid,
+                        dim3(64), 0, st, b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
         else
             FILT_LAUNCH(FILT_BNAME("batched_fwd_apply", W), kb_fwd_apply_quad<false>, grid, dim3(kThreads), 0,
                         st, b.segs, b.app_items, b.app_n, x, a, yi, ws, y);
@@ -677,9 +685,10 @@ filt_status batched_bwd_split(const BucketArgs &b, int64_t Lc, const float *gy, 
         return s;
     if constexpr (W == 16) {
         const dim3 grid((unsigned)((b.app_n * 4 + kThreads - 1) / kThreads));
+        const dim3 sgrid((unsigned)((b.app_n + kQuadChains - 1) / kQuadChains));
         if (b.av)
-            FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad<true>, grid, dim3(kThreads), 0, st,
-                        b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad_staged, sgrid,
+                        dim3(64), 0, st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);
         else
             FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad<false>, grid, dim3(kThreads), 0,
                         st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);

@@ -1,0 +1,266 @@
+// quadstage.h -- staged quad applies for the batched order-16 bucket.
+//
+// The quad applies (apply.h) run each (segment, chunk) chain on a lane quad,
+// lane q owning taps 4q+1 .. 4q+4.  In the batched plan a segment's rows are
+// contiguous in time, so the 16 chains of a wavefront read 16 rows that lie
+// a chunk length apart at every step: each load instruction touches 16
+// separate 64-byte pieces, and the same quad apply on channel-interleaved
+// data (where a wavefront's rows of one step are one 1 KB block) moves twice
+// the bytes per microsecond.  Here the wavefront loads the next run of
+// kQuadRun steps of all 16 chains together -- half a wavefront reads one
+// chain's run of rows, 512 contiguous bytes -- parks it in LDS, and each
+// quad then reads its taps from LDS; outputs are gathered in LDS and stored
+// as contiguous runs.  The run after the one being computed is in flight in
+// registers meanwhile.  Same arithmetic as fwd_apply_quad / bwd_apply_quad
+// (FP64 state, quad butterfly), full-width rows only (every filter of the
+// bucket of order 16 with 16-byte aligned rows); per-sample or frame-held.
+//
+// One wavefront per workgroup; wavefront w serves items 16w .. 16w + 15.
+#pragma once
+
+#include "common.h"
+
+namespace filt_detail {
+
+constexpr int kQuadRun = 8;        // steps per staged run
+constexpr int kQuadChains = 16;    // chains (quads) per wavefront
+
+struct QuadStageLds {
+    float coef[kQuadChains][kQuadRun * 16 + 4];  // the run's rows (padded)
+    float sig[kQuadChains][kQuadRun + 1];
+    float out[kQuadChains][kQuadRun + 1];
+    // per chain: element offsets of the chunk's first row / sample, valid
+    // steps, and the frame bookkeeping (lfm == 0: per-sample rows)
+    int64_t ocoef[kQuadChains], osig[kQuadChains], ln[kQuadChains];
+    uint32_t lt0[kQuadChains], lf0[kQuadChains], lfm[kQuadChains];
+    int lfsh[kQuadChains];
+};
+
+struct QuadStageRegs {
+    float4 c[kQuadRun * kQuadChains * 4 / 64];  // 8 float4 pieces per lane
+    float s[kQuadRun * kQuadChains / 64];       // 2 samples per lane
+    uint32_t okc, oks;
+};
+
+__device__ __forceinline__ int64_t qs_row_of(const QuadStageLds &L, int i, int64_t tc)
+{
+    if (L.lfm[i] == 0)
+        return tc;
+    const FrameDiv f{L.lfm[i], L.lfsh[i]};
+    return (int64_t)((int)frame_of(f, L.lt0[i] + (uint32_t)tc) - (int)L.lf0[i]);
+}
+
+// Chain i's bookkeeping for chunk c of segment sd (ln = 0: no chain).
+__device__ __forceinline__ void qs_set_chain(QuadStageLds &L, int i, const SegDesc &sd,
+                                             int64_t c, bool valid)
+{
+    const int64_t t0 = c * sd.L;
+    const int64_t n = valid ? (sd.T - t0 < sd.L ? sd.T - t0 : sd.L) : 0;
+    L.ln[i] = n;
+    L.osig[i] = valid ? sd.x_off + t0 : 0;
+    L.lt0[i] = (uint32_t)t0;
+    L.lfm[i] = valid ? sd.fd.m : 0u;
+    L.lfsh[i] = sd.fd.sh;
+    const uint32_t f0 = (valid && sd.fd.m != 0) ? frame_of(sd.fd, (uint32_t)t0) : 0u;
+    L.lf0[i] = f0;
+    L.ocoef[i] = valid ? sd.a_off + (sd.fd.m != 0 ? (int64_t)f0 : t0) * 16 : 0;
+}
+
+// Load run `lo` (chunk-local steps [lo, lo + kQuadRun)) of all chains:
+// g = lane + 64 j; coefficient piece g -> chain g / 32, step (g % 32) / 4,
+// quarter g % 4 (half a wavefront per chain run: contiguous per-sample rows);
+// sample g -> chain g / 8, step g % 8.  Steps outside [0, n) read the
+// chain's first or last row and are zeroed at commit.
+__device__ __forceinline__ void qs_load(const QuadStageLds &L, const float *__restrict__ coef,
+                                        const float *__restrict__ sig, int64_t lo,
+                                        QuadStageRegs &r)
+{
+    const int l = threadIdx.x;
+    r.okc = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int g = l + 64 * j;
+        const int i = g >> 5, s = (g & 31) >> 2, qq = g & 3;
+        const int64_t n = L.ln[i];
+        const int64_t t = lo + s;
+        const int64_t tc = t < 0 ? 0 : (t < n ? t : (n > 0 ? n - 1 : 0));
+        r.c[j] = *reinterpret_cast<const float4 *>(coef + L.ocoef[i] + qs_row_of(L, i, tc) * 16 +
+                                                   4 * qq);
+        r.okc |= ((t >= 0 && t < n) ? 1u : 0u) << j;
+    }
+    r.oks = 0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int g = l + 64 * j;
+        const int i = g >> 3, s = g & 7;
+        const int64_t n = L.ln[i];
+        const int64_t t = lo + s;
+        const int64_t tc = t < 0 ? 0 : (t < n ? t : (n > 0 ? n - 1 : 0));
+        r.s[j] = sig[L.osig[i] + tc];
+        r.oks |= ((t >= 0 && t < n) ? 1u : 0u) << j;
+    }
+}
+
+__device__ __forceinline__ void qs_commit(QuadStageLds &L, const QuadStageRegs &r)
+{
+    const int l = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int g = l + 64 * j;
+        const int i = g >> 5, s = (g & 31) >> 2, qq = g & 3;
+        *reinterpret_cast<float4 *>(&L.coef[i][s * 16 + 4 * qq]) =
+            ((r.okc >> j) & 1u) ? r.c[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int g = l + 64 * j;
+        L.sig[g >> 3][g & 7] = ((r.oks >> j) & 1u) ? r.s[j] : 0.f;
+    }
+}
+
+// Store run `lo` of every chain's outputs from LDS.
+__device__ __forceinline__ void qs_flush(const QuadStageLds &L, float *__restrict__ out,
+                                         int64_t lo)
+{
+    const int l = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int g = l + 64 * j;
+        const int i = g >> 3, s = g & 7;
+        if (lo + s < L.ln[i])
+            out[L.osig[i] + lo + s] = L.out[i][s];
+    }
+}
+
+// The wavefront's own LDS traffic finished (workgroups are one wavefront).
+__device__ __forceinline__ void qs_sync()
+{
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Forward: y[t] = x[t] - sum_k a_k[t] y[t-k] for each chain from its
+// entering state (yi for chunk 0, else the carry's state).
+static __global__ void __launch_bounds__(64)
+kb_fwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restrict__ items,
+                         int64_t n, const float *__restrict__ x, const float *__restrict__ a,
+                         const float *__restrict__ yi, const double *__restrict__ ws,
+                         float *__restrict__ y)
+{
+    __shared__ QuadStageLds L;
+    const int l = threadIdx.x;
+    const int k = l >> 2, q = l & 3;  // this lane's chain and tap group
+    const int64_t item = (int64_t)blockIdx.x * kQuadChains + k;
+    const bool valid = item < n;
+    const Item it = items[valid ? item : 0];
+    const SegDesc sd = segs[it.seg];
+    const int64_t Lc = sd.L;  // the bucket's chunk length (every segment)
+    if (q == 0)
+        qs_set_chain(L, k, sd, it.chunk, valid);
+    double w[4];  // w[i] = y[t - 4q - 1 - i]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int kk = 4 * q + i;
+        double v = 0.0;
+        if (valid) {
+            if (it.chunk == 0)
+                v = yi != nullptr ? (double)yi[sd.ic_off + kk] : 0.0;
+            else
+                v = ws[sd.states_off + (int64_t)it.chunk * 16 + kk];
+        }
+        w[i] = v;
+    }
+    qs_sync();
+    QuadStageRegs r;
+    qs_load(L, a, x, 0, r);
+    qs_commit(L, r);
+    qs_sync();
+    for (int64_t lo = 0; lo < Lc; lo += kQuadRun) {
+        if (lo + kQuadRun < Lc)
+            qs_load(L, a, x, lo + kQuadRun, r);
+#pragma unroll
+        for (int s = 0; s < kQuadRun; ++s) {
+            const float4 c4 = *reinterpret_cast<const float4 *>(&L.coef[k][s * 16 + 4 * q]);
+            const double ca[4] = {-(double)c4.x, -(double)c4.y, -(double)c4.z, -(double)c4.w};
+            double p = 0.0;
+#pragma unroll
+            for (int i = 3; i >= 0; --i)
+                p = __builtin_fma(ca[i], w[i], p);
+            double tot = p + quad_dpp<kQuadXor1>(p);
+            tot = tot + quad_dpp<kQuadXor2>(tot);
+            const double v = (double)L.sig[k][s] + tot;
+            if (q == 0)
+                L.out[k][s] = (float)v;
+            const double prev = quad_dpp<kQuadFromPrev>(w[3]);
+            w[3] = w[2];
+            w[2] = w[1];
+            w[1] = w[0];
+            w[0] = q == 0 ? v : prev;
+        }
+        qs_sync();
+        qs_flush(L, y, lo);
+        if (lo + kQuadRun < Lc)
+            qs_commit(L, r);
+        qs_sync();
+    }
+}
+
+// Backward (transposed adjoint, decreasing time) from the state entering
+// from the next chunk; writes ybar (= gx without b) and gyi from chunk 0.
+static __global__ void __launch_bounds__(64)
+kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restrict__ items,
+                         int64_t n, const float *__restrict__ gy, const float *__restrict__ a,
+                         const double *__restrict__ ws, float *__restrict__ gx,
+                         float *__restrict__ gyi)
+{
+    __shared__ QuadStageLds L;
+    const int l = threadIdx.x;
+    const int k = l >> 2, q = l & 3;
+    const int64_t item = (int64_t)blockIdx.x * kQuadChains + k;
+    const bool valid = item < n;
+    const Item it = items[valid ? item : 0];
+    const SegDesc sd = segs[it.seg];
+    const int64_t Lc = sd.L;
+    if (q == 0)
+        qs_set_chain(L, k, sd, it.chunk, valid);
+    double st[4];  // st[i] = s_{4q+1+i}
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int kk = 4 * q + i;
+        st[i] = (valid && it.chunk + 1 < sd.C) ? ws[sd.states_off + (int64_t)it.chunk * 16 + kk]
+                                                : 0.0;
+    }
+    qs_sync();
+    QuadStageRegs r;
+    qs_load(L, a, gy, Lc - kQuadRun, r);
+    qs_commit(L, r);
+    qs_sync();
+    for (int64_t lo = Lc - kQuadRun; lo >= 0; lo -= kQuadRun) {
+        if (lo > 0)
+            qs_load(L, a, gy, lo - kQuadRun, r);
+#pragma unroll
+        for (int s = kQuadRun - 1; s >= 0; --s) {
+            const float4 c4 = *reinterpret_cast<const float4 *>(&L.coef[k][s * 16 + 4 * q]);
+            const double yb = (double)L.sig[k][s] + quad_dpp<kQuadLane0>(st[0]);
+            if (q == 0)
+                L.out[k][s] = (float)yb;
+            const double nx = quad_dpp<kQuadFromNext>(st[0]);
+            st[0] = __builtin_fma(-(double)c4.x, yb, st[1]);
+            st[1] = __builtin_fma(-(double)c4.y, yb, st[2]);
+            st[2] = __builtin_fma(-(double)c4.z, yb, st[3]);
+            st[3] = __builtin_fma(-(double)c4.w, yb, q == 3 ? 0.0 : nx);
+        }
+        qs_sync();
+        qs_flush(L, gx, lo);
+        if (lo > 0)
+            qs_commit(L, r);
+        qs_sync();
+    }
+    if (valid && it.chunk == 0 && gyi != nullptr) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            gyi[sd.ic_off + 4 * q + i] = (float)st[i];
+    }
+}
+
+}  // namespace filt_detail
