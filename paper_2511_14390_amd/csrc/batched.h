@@ -673,8 +673,9 @@ filt_status batched_stream_bwd(const BucketArgs &b, int64_t Lc, const float *gy,
     return check_launch("batched staged backward apply");
 }
 
-// Order-16 bucket backward: the apply (quads) writes only gx (= ybar) and
-// the per-item pass forms ga.
+// Order-16 bucket backward: the apply (quads) writes gx (= ybar); with
+// full-width rows the staged adjoint also forms the per-sample ga rows,
+// otherwise the per-item pass forms them from gx.
 template <int W>
 filt_status batched_bwd_split(const BucketArgs &b, int64_t Lc, const float *gy, const float *y,
                               const float *a, const float *yi, const double *ws, float *gx,
@@ -686,9 +687,19 @@ filt_status batched_bwd_split(const BucketArgs &b, int64_t Lc, const float *gy, 
     if constexpr (W == 16) {
         const dim3 grid((unsigned)((b.app_n * 4 + kThreads - 1) / kThreads));
         const dim3 sgrid((unsigned)((b.app_n + kQuadChains - 1) / kQuadChains));
+        // full-width rows: the staged adjoint, forming the per-sample ga rows
+        // itself when their base is 16-byte aligned
+        const bool fused = ga != nullptr && (uintptr_t)ga % 16 == 0;
+        if (b.av && fused) {
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad_staged<true>, sgrid,
+                        dim3(64), 0, st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi, y, yi,
+                        ga);
+            return check_launch("batched backward apply");
+        }
         if (b.av)
-            FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad_staged, sgrid,
-                        dim3(64), 0, st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);
+            FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad_staged<false>, sgrid,
+                        dim3(64), 0, st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi,
+                        (const float *)nullptr, (const float *)nullptr, (float *)nullptr);
         else
             FILT_LAUNCH(FILT_BNAME("batched_bwd_apply", W), kb_bwd_apply_quad<false>, grid, dim3(kThreads), 0,
                         st, b.segs, b.app_items, b.app_n, gy, a, ws, gx, gyi);

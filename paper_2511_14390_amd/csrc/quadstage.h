@@ -24,14 +24,19 @@ namespace filt_detail {
 
 constexpr int kQuadRun = 8;        // steps per staged run
 constexpr int kQuadChains = 16;    // chains (quads) per wavefront
+constexpr int kQuadYWin = 24;      // y samples staged per run for ga (run + 16 back, rounded)
 
 struct QuadStageLds {
     float coef[kQuadChains][kQuadRun * 16 + 4];  // the run's rows (padded)
     float sig[kQuadChains][kQuadRun + 1];
     float out[kQuadChains][kQuadRun + 1];
+    // adjoint with ga: y at chunk-relative times [lo - 17, lo + 7) of the run
+    float yw[kQuadChains][kQuadYWin + 1];
     // per chain: element offsets of the chunk's first row / sample, valid
     // steps, and the frame bookkeeping (lfm == 0: per-sample rows)
     int64_t ocoef[kQuadChains], osig[kQuadChains], ln[kQuadChains];
+    int64_t lyT[kQuadChains];  // T - 1 - t0: y past it is clamped (no output uses it)
+    int64_t lic[kQuadChains];  // initial-condition offset, -1 without yi
     uint32_t lt0[kQuadChains], lf0[kQuadChains], lfm[kQuadChains];
     int lfsh[kQuadChains];
 };
@@ -39,6 +44,7 @@ struct QuadStageLds {
 struct QuadStageRegs {
     float4 c[kQuadRun * kQuadChains * 4 / 64];  // 8 float4 pieces per lane
     float s[kQuadRun * kQuadChains / 64];       // 2 samples per lane
+    float y[kQuadYWin * kQuadChains / 64];      // 6 y samples per lane (ga only)
     uint32_t okc, oks;
 };
 
@@ -52,11 +58,13 @@ __device__ __forceinline__ int64_t qs_row_of(const QuadStageLds &L, int i, int64
 
 // Chain i's bookkeeping for chunk c of segment sd (ln = 0: no chain).
 __device__ __forceinline__ void qs_set_chain(QuadStageLds &L, int i, const SegDesc &sd,
-                                             int64_t c, bool valid)
+                                             int64_t c, bool valid, bool has_yi = false)
 {
     const int64_t t0 = c * sd.L;
     const int64_t n = valid ? (sd.T - t0 < sd.L ? sd.T - t0 : sd.L) : 0;
     L.ln[i] = n;
+    L.lyT[i] = valid ? sd.T - 1 - t0 : 0;
+    L.lic[i] = (valid && has_yi) ? sd.ic_off : -1;
     L.osig[i] = valid ? sd.x_off + t0 : 0;
     L.lt0[i] = (uint32_t)t0;
     L.lfm[i] = valid ? sd.fd.m : 0u;
@@ -115,6 +123,61 @@ __device__ __forceinline__ void qs_commit(QuadStageLds &L, const QuadStageRegs &
     for (int j = 0; j < 2; ++j) {
         const int g = l + 64 * j;
         L.sig[g >> 3][g & 7] = ((r.oks >> j) & 1u) ? r.s[j] : 0.f;
+    }
+}
+
+// ga only: y at chunk-relative times lo - 17 + j, j < kQuadYWin, of every
+// chain (sample g -> chain g / 24, j = g % 24): before time 0 from the
+// initial conditions (zero past 16 or without them), clamped below T.
+__device__ __forceinline__ void qs_load_y(const QuadStageLds &L, const float *__restrict__ y,
+                                          const float *__restrict__ yi, int64_t lo,
+                                          QuadStageRegs &r)
+{
+    const int l = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kQuadYWin * kQuadChains / 64; ++j) {
+        const int g = l + 64 * j;
+        const int i = g / kQuadYWin, e = g % kQuadYWin;
+        const int64_t tt = lo - 17 + e;          // chunk-relative
+        const int64_t ta = (int64_t)L.lt0[i] + tt;  // absolute in the segment
+        float v = 0.f;
+        if (ta >= 0) {
+            v = y[L.osig[i] + (tt < L.lyT[i] ? tt : L.lyT[i])];
+        } else if (L.lic[i] >= 0 && -ta <= 16) {
+            v = yi[L.lic[i] + (-ta - 1)];
+        }
+        r.y[j] = v;
+    }
+}
+
+__device__ __forceinline__ void qs_commit_y(QuadStageLds &L, const QuadStageRegs &r)
+{
+    const int l = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kQuadYWin * kQuadChains / 64; ++j) {
+        const int g = l + 64 * j;
+        L.yw[g / kQuadYWin][g % kQuadYWin] = r.y[j];
+    }
+}
+
+// ga only: store run `lo` of the per-sample gradient rows of every chain
+// from LDS (written over the run's coefficient rows), per-sample chains only
+// (frame-held rows take the per-frame pass), as non-temporal float4 runs.
+__device__ __forceinline__ void qs_flush_ga(const QuadStageLds &L, float *__restrict__ ga,
+                                            int64_t lo)
+{
+    const int l = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int g = l + 64 * j;
+        const int i = g >> 5, s = (g & 31) >> 2, qq = g & 3;
+        if (L.lfm[i] == 0 && lo + s < L.ln[i]) {
+            using f4 = float __attribute__((ext_vector_type(4)));
+            const float4 v = *reinterpret_cast<const float4 *>(&L.coef[i][s * 16 + 4 * qq]);
+            const f4 v4 = {v.x, v.y, v.z, v.w};
+            __builtin_nontemporal_store(
+                v4, reinterpret_cast<f4 *>(ga + L.ocoef[i] + (lo + s) * 16 + 4 * qq));
+        }
     }
 }
 
@@ -207,11 +270,18 @@ kb_fwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restric
 
 // Backward (transposed adjoint, decreasing time) from the state entering
 // from the next chunk; writes ybar (= gx without b) and gyi from chunk 0.
-static __global__ void __launch_bounds__(64)
+// GA: also the per-sample gradient rows ga_k[t] = -ybar[t] y[t-k] (Sec. 3.1
+// Eq. 8 per sample) of per-sample chains, lane q its taps 4q+1 .. 4q+4 from
+// a window wy[i] = y[t - 4q - 1 - i] sliding down one sample per step; the
+// run's ga rows overwrite its coefficient rows in LDS (each lane its own
+// slot, after reading it) and leave as contiguous runs.
+template <bool GA>
+__global__ void __launch_bounds__(64)
 kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restrict__ items,
                          int64_t n, const float *__restrict__ gy, const float *__restrict__ a,
                          const double *__restrict__ ws, float *__restrict__ gx,
-                         float *__restrict__ gyi)
+                         float *__restrict__ gyi, const float *__restrict__ y,
+                         const float *__restrict__ yi, float *__restrict__ ga)
 {
     __shared__ QuadStageLds L;
     const int l = threadIdx.x;
@@ -222,7 +292,7 @@ kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restric
     const SegDesc sd = segs[it.seg];
     const int64_t Lc = sd.L;
     if (q == 0)
-        qs_set_chain(L, k, sd, it.chunk, valid);
+        qs_set_chain(L, k, sd, it.chunk, valid, yi != nullptr);
     double st[4];  // st[i] = s_{4q+1+i}
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -233,17 +303,42 @@ kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restric
     qs_sync();
     QuadStageRegs r;
     qs_load(L, a, gy, Lc - kQuadRun, r);
+    if constexpr (GA)
+        qs_load_y(L, y, yi, Lc - kQuadRun, r);
     qs_commit(L, r);
+    if constexpr (GA)
+        qs_commit_y(L, r);
     qs_sync();
+    // wy[i] = y[t - 4q - 1 - i] for the chunk's last step t = Lc - 1: window
+    // index (Lc - 1 - 4q - 1 - i) - (Lc - kQuadRun - 17)
+    float wy[4];
+    if constexpr (GA) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            wy[i] = L.yw[k][kQuadRun + 15 - 4 * q - i];
+    }
     for (int64_t lo = Lc - kQuadRun; lo >= 0; lo -= kQuadRun) {
-        if (lo > 0)
+        if (lo > 0) {
             qs_load(L, a, gy, lo - kQuadRun, r);
+            if constexpr (GA)
+                qs_load_y(L, y, yi, lo - kQuadRun, r);
+        }
 #pragma unroll
         for (int s = kQuadRun - 1; s >= 0; --s) {
             const float4 c4 = *reinterpret_cast<const float4 *>(&L.coef[k][s * 16 + 4 * q]);
             const double yb = (double)L.sig[k][s] + quad_dpp<kQuadLane0>(st[0]);
             if (q == 0)
                 L.out[k][s] = (float)yb;
+            if constexpr (GA) {
+                const float nyb = -(float)yb;
+                *reinterpret_cast<float4 *>(&L.coef[k][s * 16 + 4 * q]) =
+                    make_float4(nyb * wy[0], nyb * wy[1], nyb * wy[2], nyb * wy[3]);
+                wy[0] = wy[1];
+                wy[1] = wy[2];
+                wy[2] = wy[3];
+                // y[t - 4q - 5] enters: window index s - 4q + 12
+                wy[3] = L.yw[k][s - 4 * q + 12];
+            }
             const double nx = quad_dpp<kQuadFromNext>(st[0]);
             st[0] = __builtin_fma(-(double)c4.x, yb, st[1]);
             st[1] = __builtin_fma(-(double)c4.y, yb, st[2]);
@@ -252,8 +347,13 @@ kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restric
         }
         qs_sync();
         qs_flush(L, gx, lo);
-        if (lo > 0)
+        if constexpr (GA)
+            qs_flush_ga(L, ga, lo);
+        if (lo > 0) {
             qs_commit(L, r);
+            if constexpr (GA)
+                qs_commit_y(L, r);
+        }
         qs_sync();
     }
     if (valid && it.chunk == 0 && gyi != nullptr) {
