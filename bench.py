@@ -247,6 +247,10 @@ def batched_kernel_bytes(s, chunks, name):
     }.get(kind)
     if per is None:
         return None
+    if kind == "batched_bwd_apply" and W == 16 and not frames:
+        # the staged order-16 adjoint forms the per-sample ga rows itself
+        # (reads y, writes the rows): no separate coef_grads pass
+        per = (T, 12, 8)
     n, sig, coef = per
     return float((n * (sig + coef * N * rows)).sum())
 
