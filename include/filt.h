@@ -318,7 +318,10 @@ filt_status filt_plan_tune(filt_plan *p, const float *x, const float *a, const f
 filt_status filt_plan_get_chunks(const filt_plan *p, int32_t *chunks /* host, 5 */);
 
 /* Capture forward + backward on these buffers into a HIP graph (the stream
- * must not be capturing already), and replay it. */
+ * must not be capturing already), and replay it.  In the graph each order
+ * bucket's backward follows its own forward directly (one fork and one join
+ * for the step), so buckets overlap across the two directions; the results
+ * equal filt_plan_forward followed by filt_plan_backward. */
 filt_status filt_plan_capture(filt_plan *p, const float *x, const float *a, const float *yi,
                               const float *gy, float *y, float *gx, float *ga, float *gyi,
                               void *stream);

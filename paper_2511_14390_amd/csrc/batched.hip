@@ -582,6 +582,39 @@ filt_status run_backward(const filt_plan *p, const float *gy, const float *y, co
     });
 }
 
+// Forward then backward of every bucket on the bucket's own stream, with one
+// fork and one join: a bucket's adjoint needs only its own forward, so the
+// low-order buckets' backward runs while the order-16 forward still does
+// (the captured fwd + bwd step).
+filt_status run_step(const filt_plan *p, const float *x, const float *a, const float *yi,
+                     const float *gy, float *y, float *gx, float *ga, float *gyi, hipStream_t st)
+{
+    return fork_buckets(p, st, 0x1f, [&](int b, hipStream_t s) -> filt_status {
+        switch (b) {
+        case 0: {
+            const filt_status r = bucket_forward<1, 0>(p, x, a, yi, y, s);
+            return r != FILT_OK ? r : bucket_backward<1, 0>(p, gy, y, a, yi, gx, ga, gyi, s);
+        }
+        case 1: {
+            const filt_status r = bucket_forward<2, 1>(p, x, a, yi, y, s);
+            return r != FILT_OK ? r : bucket_backward<2, 1>(p, gy, y, a, yi, gx, ga, gyi, s);
+        }
+        case 2: {
+            const filt_status r = bucket_forward<4, 2>(p, x, a, yi, y, s);
+            return r != FILT_OK ? r : bucket_backward<4, 2>(p, gy, y, a, yi, gx, ga, gyi, s);
+        }
+        case 3: {
+            const filt_status r = bucket_forward<8, 3>(p, x, a, yi, y, s);
+            return r != FILT_OK ? r : bucket_backward<8, 3>(p, gy, y, a, yi, gx, ga, gyi, s);
+        }
+        default: {
+            const filt_status r = bucket_forward<16, 4>(p, x, a, yi, y, s);
+            return r != FILT_OK ? r : bucket_backward<16, 4>(p, gy, y, a, yi, gx, ga, gyi, s);
+        }
+        }
+    });
+}
+
 filt_status check_plan(const filt_plan *p)
 {
     if (p == nullptr)
@@ -800,9 +833,7 @@ filt_status filt_plan_capture(filt_plan *p, const float *x, const float *a, cons
     hipStream_t st = (hipStream_t)stream;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(FILT_EHIP, "hipStreamBeginCapture failed");
-    s = run_forward(p, x, a, yi, y, st);
-    if (s == FILT_OK)
-        s = run_backward(p, gy, y, a, yi, gx, ga, gyi, st);
+    s = run_step(p, x, a, yi, gy, y, gx, ga, gyi, st);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (s != FILT_OK) {
