@@ -518,6 +518,11 @@ bool bucket_busy(const filt_plan *p, int b)
 }
 
 
+// The stream each bucket's launches go to: the two smallest buckets share
+// one, so the step uses four concurrent streams (the hardware queues a
+// process gets by default).
+constexpr int kStreamOf[kBuckets] = {1, 1, 2, 3, 4};
+
 // Runs fn(b, stream) for every busy bucket in mask, each on its own stream
 // forked from st, the longest-running (highest order) first; st waits for
 // all of them.  With one busy bucket it runs on st directly.
@@ -540,12 +545,13 @@ filt_status fork_buckets(const filt_plan *p, hipStream_t st, unsigned mask, F &&
     for (int b = kBuckets - 1; b >= 0; --b) {
         if (!(((mask >> b) & 1u) && bucket_busy(p, b)))
             continue;
-        if (hipStreamWaitEvent(p->side[b], p->fork, 0) != hipSuccess)
+        hipStream_t side = p->side[kStreamOf[b]];
+        if (hipStreamWaitEvent(side, p->fork, 0) != hipSuccess)
             return fail(FILT_EHIP, "hipStreamWaitEvent (fork) failed");
         if (s == FILT_OK)
-            s = fn(b, p->side[b]);
+            s = fn(b, side);
         // join even after a failed launch so a capture stays well formed
-        if (hipEventRecord(p->join[b], p->side[b]) != hipSuccess ||
+        if (hipEventRecord(p->join[b], side) != hipSuccess ||
             hipStreamWaitEvent(st, p->join[b], 0) != hipSuccess)
             return fail(FILT_EHIP, "event join of a bucket stream failed");
     }
