@@ -24,7 +24,7 @@ namespace filt_detail {
 namespace {
 
 constexpr int kMrRow = 16;  // lanes per recurrence
-constexpr int kMrBlk = 8;   // steps loaded per block (double-buffered)
+constexpr int kMrBlk = 16;  // steps loaded per block (double-buffered)
 
 struct MrDims {
     int64_t B, T, L, C;
@@ -352,8 +352,10 @@ MrDims mr_dims(const filt_problem *p)
     d.layout = p->layout;
     int64_t L = p->chunk;
     if (L == 0) {
-        // about 4096 recurrences (rows of 16 lanes) over the whole problem
-        const int64_t want = std::max<int64_t>(1, (4096 + d.B - 1) / std::max<int64_t>(d.B, 1));
+        // about 16384 recurrences (rows of 16 lanes) over the whole problem:
+        // a row's step waits on its loads, so short chunks (more rows in
+        // flight) win until the carry over chunks dominates
+        const int64_t want = std::max<int64_t>(1, (16384 + d.B - 1) / std::max<int64_t>(d.B, 1));
         L = (d.T + want - 1) / want;
         L = std::min<int64_t>(8192, std::max<int64_t>(32, (L + 31) / 32 * 32));
     }
