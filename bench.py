@@ -557,6 +557,39 @@ def paper_sweep_main(args):
                       "K": 2, "parallelism": "single GPU",
                       "paper_hardware": "RTX 5060 Ti (the paper's; context only)"},
            "sweep": rows, "roofline": None, "cpu_baseline": None}
+    # roofline of the forward + backward at T = 2^20 as a whole: algorithmic
+    # bytes (z in, v out; gv, v in, gz out: 4 K each per step) over its time;
+    # one signal is bound by the per-step latency of the recurrence, so the
+    # fraction is small
+    Tl, K = rows[-1]["T"], 2
+    by = Tl * 4 * K * (2 + 3)
+    ach = by / (last["mr_fwd_bwd_us"] * 1e-6) / 1e9
+    rec["roofline"] = {"bound": "hbm", "kernel": "matrix recurrence forward + backward",
+                       "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                       "bytes_per_launch": by}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        # the oracle's matrix recurrence (FP64 NumPy loop over time, one
+        # thread) on a bounded sample: 2^16 steps of the same recurrence
+        Ts = 1 << 16
+        zs = rng.standard_normal((1, Ts, 2))
+        gs = rng.standard_normal((1, Ts, 2))
+        reps, c0 = 0, time.perf_counter()
+        while True:
+            vo = oracle.mr_forward(A.astype(np.float64), None, zs)
+            oracle.mr_backward(gs, A.astype(np.float64), None, vo)
+            reps += 1
+            if time.perf_counter() - c0 >= min(args.cpu_seconds, 10.0):
+                break
+        dt = time.perf_counter() - c0
+        rec["cpu_baseline"] = {"value": round(Ts * reps / dt / 1e9, 6), "unit": "Gsamples/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"forward + backward of one 2^16-step signal, FP64 "
+                                         f"NumPy loop, repeated {reps}x in {dt:.1f} s",
+                               "gpu_at_2^20_gsamples_s": round(Tl / (last["mr_fwd_bwd_us"]
+                                                                     * 1e-6) / 1e9, 4)}
     print(json.dumps(rec), flush=True)
 
 
