@@ -363,7 +363,11 @@ def batched_main(args):
     prof = F.profile_read()
     kern = {k: {"launches": c // wsteps, "avg_us": round(1e3 * ms / c, 2),
                 "total_ms_per_step": round(ms / wsteps, 4)} for k, (c, ms) in prof.items()}
-    dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"]) if kern else None
+    # the dominant kernel among those moving a per-sample volume (the carry
+    # kernels, several small launches per step, have no per-sample figure)
+    sized = [k for k in kern if batched_kernel_bytes(s, chunks, k) is not None]
+    pool = sized or list(kern)
+    dom = max(pool, key=lambda k: kern[k]["total_ms_per_step"]) if pool else None
 
     if args.calib_copy_mib > 0:
         src = torch.empty(args.calib_copy_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
