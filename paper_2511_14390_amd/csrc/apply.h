@@ -760,6 +760,13 @@ filt_status forward_w(const Dims &d, const io_t *x, const io_t *bc, const io_t *
     if constexpr (sizeof(io_t) == 4 && sizeof(acc_t) == 8 && W <= 16) {
         if (stream_eligible(d))
             return stream_forward_run<W>(d, x, ac, yi, states, y, st);
+        // time-invariant all-pole [B, T]: the same staged apply, the channel's
+        // row read as the row of one frame of T samples
+        if (lti_stream_eligible(d)) {
+            Dims e = d;
+            set_rows(e, d.T);
+            return stream_forward_run<W>(e, x, ac, yi, states, y, st);
+        }
     }
     if constexpr (kQuadApply<W, io_t, acc_t>) {
         if (quad_apply_eligible(d))
@@ -850,6 +857,16 @@ filt_status backward_w(const Dims &d, const io_t *gy, const io_t *x, const io_t 
             if (d.fd.m != 0)
                 return frame_coef_grads_run<io_t>(d, yb, x, xi, y, yi, ga, nullptr, st);
             return tv_coef_grads_run(d, yb, x, xi, y, yi, ga, nullptr, st);
+        }
+        // time-invariant all-pole [B, T] with gx (= ybar): the staged adjoint
+        // as one frame, then ga summed over time from ybar
+        if (lti_stream_eligible(d) && gx != nullptr) {
+            Dims e = d;
+            set_rows(e, d.T);
+            filt_status s = stream_backward_run<W>(e, gy, ac, states, gx, gyi, st);
+            if (s != FILT_OK || ga == nullptr)
+                return s;
+            return lti_allpole_ga_run(d, gx, y, yi, ga, part, st);
         }
     }
     // Order-16 per-sample problems without an FIR part: quad adjoint writing

@@ -687,6 +687,23 @@ filt_status tv_coef_grads_run(const Dims &d, const float *ybar, const float *x, 
                               const float *y, const float *yi, float *ga, float *gb,
                               hipStream_t st);
 bool tv_coef_grads_fits(const Dims &d);  // 32-bit thread indexing
+// grads.hip: time-invariant all-pole [B, T] ga from the adjoint ybar, summed
+// over time (per-block FP64 partials in part, then the time-invariant
+// reduction); part holds at least one record of N + 1 doubles per chunk.
+filt_status lti_allpole_ga_run(const Dims &d, const float *ybar, const float *y,
+                               const float *yi, float *ga, double *part, hipStream_t st);
+
+// Time-invariant all-pole [B, T] problems with many chunks run their
+// applies on the staged (stream) kernels as frame-held problems of one frame
+// of T samples: the channel's coefficient row is the frame's row
+// ([B][1][N] = [B][N]).  With few chunk chains (short or few signals) the
+// per-lane applies are faster (a staged wavefront then walks its runs with
+// little to overlap), hence the 32768-chain floor.
+inline bool lti_stream_eligible(const Dims &d)
+{
+    return !d.tv && !d.tz && d.layout == FILT_LAYOUT_BT && !d.has_b && d.M == 0 && d.N > 0 &&
+           d.N <= 8 && d.T >= 2 && d.T < ((int64_t)1 << 31) && d.B * d.C >= 32768;
+}
 
 // toeplitz.hip
 struct TzPlan {

@@ -250,4 +250,114 @@ filt_status tv_coef_grads_run(const Dims &d, const float *ybar, const float *x, 
     return check_launch("coefficient gradients");
 }
 
+// Time-invariant all-pole [B, T] problems whose adjoint ran as a staged
+// apply: ga_k = -sum_t ybar[t] y[t-k] (Sec. 3.1 Eq. 9 summed over time; y
+// before time 0 from yi).  One workgroup per (channel, block of samples):
+// FP64 sums over its samples, a fixed tree in LDS per tap, partials
+// part[(b*nblk + blk)*(N+1) + k] (slot N, the b_0 tap, zero) for the
+// time-invariant reduction.
+namespace {
+
+template <int KW>
+__global__ void __launch_bounds__(256)
+k_lti_ga_partial(Dims d, int64_t nblk, int64_t blk, const float *__restrict__ ybar,
+                 const float *__restrict__ y, const float *__restrict__ yi,
+                 double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int64_t b = blockIdx.x / nblk, k0 = blockIdx.x % nblk;
+    const int64_t t0 = k0 * blk;
+    const int64_t t1 = t0 + blk < d.T ? t0 + blk : d.T;
+    const int N = d.N;
+    const float *yb = ybar + b * d.T;
+    const float *yy = y + b * d.T;
+    double acc[KW];
+#pragma unroll
+    for (int k = 0; k < KW; ++k)
+        acc[k] = 0.0;
+    // consecutive threads take consecutive samples (coalesced loads); four
+    // samples per thread in flight at a time
+    constexpr int U = 4;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += (int64_t)U * blockDim.x) {
+        float v[U], w[U][KW];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t tu = t + (int64_t)u * blockDim.x;
+            const bool in = tu < t1;
+            v[u] = in ? yb[tu] : 0.f;
+#pragma unroll
+            for (int k = 1; k <= KW; ++k) {
+                float x = 0.f;
+                if (in && k <= N) {
+                    if (tu - k >= 0)
+                        x = yy[tu - k];
+                    else if (yi != nullptr)
+                        x = yi[b * N + (k - tu - 1)];
+                }
+                w[u][k - 1] = x;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < KW; ++k)
+                acc[k] += (double)v[u] * (double)w[u][k];
+    }
+    double *o = part + (b * nblk + k0) * (N + 1);
+    for (int k = 0; k < N; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < KW; ++kk)
+            if (kk == k)
+                a = acc[kk];
+        red[threadIdx.x] = a;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            o[k] = -red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        o[N] = 0.0;
+}
+
+}  // namespace
+
+filt_status lti_allpole_ga_run(const Dims &d, const float *ybar, const float *y,
+                               const float *yi, float *ga, double *part, hipStream_t st)
+{
+    // blocks of 8192 samples, at most one per chunk (the partial buffer holds
+    // one record per chunk)
+    int64_t nblk = (d.T + 8191) / 8192;
+    if (nblk > d.C)
+        nblk = d.C;
+    const int64_t blk = (d.T + nblk - 1) / nblk;
+    // taps padded to a power of two (N <= 8 here): the missing taps read zero
+#define GA_LAUNCH(KW)                                                                              \
+    FILT_LAUNCH("lti_ga_partial", k_lti_ga_partial<KW>, dim3((unsigned)(d.B * nblk)), dim3(256),  \
+                0, st, d, nblk, blk, ybar, y, yi, part)
+    if (d.N <= 1)
+        GA_LAUNCH(1);
+    else if (d.N <= 2)
+        GA_LAUNCH(2);
+    else if (d.N <= 4)
+        GA_LAUNCH(4);
+    else if (d.N <= 8)
+        GA_LAUNCH(8);
+    else
+        return fail(FILT_EUNSUPPORTED, "time-invariant ga pass: order %d above 8", d.N);
+#undef GA_LAUNCH
+    filt_status s = check_launch("time-invariant ga partials");
+    if (s != FILT_OK)
+        return s;
+    Dims r = d;
+    r.C = nblk;
+    r.M = 0;
+    return reduce_lti_run(r, part, ga, nullptr, false, st);
+}
+
 }  // namespace filt_detail

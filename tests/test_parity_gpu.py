@@ -118,6 +118,20 @@ def test_random_problems_fp32_state(gpu_device, M, N, tv, layout, T, chunk):
     compare(p, yg, gg, yo, go, label=f"f32state chunk={chunk}")
 
 
+@pytest.mark.parametrize("N,chunk", [(3, 32), (4, 32), (8, 32)])
+def test_time_invariant_allpole_bt_staged_applies(gpu_device, N, chunk):
+    # time-invariant all-pole [B, T] with at least 32768 chunk chains: the
+    # applies run on the staged kernels as one frame of T samples and ga is
+    # summed over time from ybar (FP64 state: only the FP32 I/O rounding
+    # separates the result from the oracle)
+    p = W.random_problem(4200 + N, B=64, T=16384 + 7, M=0, N=N, time_varying=False,
+                         layout="BT", rho_max=0.95, with_b=False)
+    assert p.x.shape[0] * -(-p.x.shape[1] // chunk) >= 32768
+    yg, gg = run_gpu(p, gpu_device, chunk=chunk, recurrence=True)
+    yo, go = run_oracle(p)
+    compare(p, yg, gg, yo, go, out_tol=2e-6, grad_tol=2e-6, label=f"staged LTI N={N}")
+
+
 @pytest.mark.parametrize("T", [1, 2, 5, 31, 32, 33, 95])
 def test_short_signals(gpu_device, T):
     p = W.random_problem(2000 + T, B=3, T=T, M=3, N=5, time_varying=True, layout="BT", hop=4)
