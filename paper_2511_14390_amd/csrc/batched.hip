@@ -126,6 +126,9 @@ struct filt_plan {
     size_t flags_n = 0;
     int64_t tiles_fwd_off[kBuckets] = {}, tiles_bwd_off[kBuckets] = {}, ntiles[kBuckets] = {};
     int64_t agg_off[kBuckets] = {}, inc_off[kBuckets] = {}, flag_off[kBuckets] = {};
+    int64_t ticket_off[kBuckets] = {};
+    int nlists[kBuckets] = {};
+    int64_t list_off[kBuckets][kOnePassLists + 1] = {};
     // frame-held segments per bucket: items (segment, first frame, frames)
     // of the per-frame gradient pass; and an adjoint buffer for backward
     // calls that want ga but no gx
@@ -201,9 +204,10 @@ filt_status plan_layout(filt_plan *p)
     }
     for (int b = 0; b < kBuckets; ++b)
         p->bucket_av[b] = true;
-    // single-pass buckets: tiles per segment, records, ticket orders (every
-    // tile after the tiles it waits for; longest segments first in each
-    // rank so the longest chains start early)
+    // single-pass buckets: tiles per segment, records, ticket lists (whole
+    // segments per list, balanced by tiles; in each list every tile after
+    // the tiles it waits for, longest segments first in each rank so the
+    // longest chains start early)
     std::vector<int2> tiles;
     size_t nflags = 0;
     {
@@ -239,17 +243,37 @@ filt_status plan_layout(filt_plan *p)
             p->inc_off[b] = (int64_t)off;
             off += (size_t)(nt * W);
             off = (off + 1) & ~size_t(1);
+            // flags, then the lists' ticket counters on lines of their own,
+            // then the timeout counter
             p->flag_off[b] = (int64_t)nflags;
-            nflags += (size_t)nt + 4;  // flags, ticket, timeouts
+            const size_t toff = ((size_t)nflags + (size_t)nt + kTicketStride - 1) /
+                                kTicketStride * kTicketStride;
+            p->ticket_off[b] = (int64_t)toff;
+            nflags = toff + (size_t)(kOnePassLists + 1) * kTicketStride;
+            const int nl = kOnePassLists;
+            p->nlists[b] = nl;
+            std::vector<int> list_of(nseg, -1);
+            std::vector<int64_t> load(nl, 0);
+            for (int i : order) {  // longest first, each to the lightest list
+                if (bucket_of(std::max(p->segs[i].N, 1)) != b)
+                    continue;
+                const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                list_of[i] = l;
+                load[l] += sd[i].ntile;
+            }
+            p->list_off[b][0] = 0;
+            for (int l = 0; l < nl; ++l)
+                p->list_off[b][l + 1] = p->list_off[b][l] + load[l];
             for (int dir = 0; dir < 2; ++dir) {
                 (dir == 0 ? p->tiles_fwd_off[b] : p->tiles_bwd_off[b]) = (int64_t)tiles.size();
-                for (int64_t r = 0; r < maxt; ++r)
-                    for (int i : order) {
-                        if (bucket_of(std::max(p->segs[i].N, 1)) != b || r >= sd[i].ntile)
-                            continue;
-                        const int64_t k = dir == 0 ? r : sd[i].ntile - 1 - r;
-                        tiles.push_back(make_int2(i, (int)k));
-                    }
+                for (int l = 0; l < nl; ++l)
+                    for (int64_t r = 0; r < maxt; ++r)
+                        for (int i : order) {
+                            if (list_of[i] != l || r >= sd[i].ntile)
+                                continue;
+                            const int64_t k = dir == 0 ? r : sd[i].ntile - 1 - r;
+                            tiles.push_back(make_int2(i, (int)k));
+                        }
             }
         }
     }
@@ -394,22 +418,25 @@ OnePassArgs onepass_args(const filt_plan *p, int b, bool bwd)
     A.agg = p->d_ws + p->agg_off[b];
     A.inc = p->d_ws + p->inc_off[b];
     A.flag = p->d_flags + p->flag_off[b];
-    A.ticket = A.flag + p->ntiles[b];
-    A.timeouts = A.ticket + 1;
+    A.ticket = p->d_flags + p->ticket_off[b];
+    A.timeouts = A.ticket + kOnePassLists * kTicketStride;
+    A.nlists = std::max(p->nlists[b], 1);
+    for (int l = 0; l <= kOnePassLists; ++l)
+        A.list_off[l] = p->list_off[b][std::min(l, A.nlists)];
     return A;
 }
 
 // Workgroups of a single-pass launch: enough for every CU to hold several
-// (the LDS of a tile bounds how many are resident); the rest find the
-// ticket counter past the end and leave.
-unsigned onepass_grid(int64_t ntiles)
+// (the LDS of a tile bounds how many are resident), and at least one per
+// ticket list; the rest find their list's counter past its end and leave.
+unsigned onepass_grid(int64_t ntiles, int nlists)
 {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, kCUs * 16));
+    return (unsigned)std::max<int64_t>(nlists, std::min<int64_t>(ntiles, kCUs * 16));
 }
 
-unsigned onepass_grid16(int64_t ntiles)
+unsigned onepass_grid16(int64_t ntiles, int nlists)
 {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ntiles, kCUs * 2));
+    return (unsigned)std::max<int64_t>(nlists, std::min<int64_t>(ntiles, kCUs * 2));
 }
 
 template <int W>
@@ -421,10 +448,10 @@ filt_status onepass_forward(const filt_plan *p, int b, const float *x, const flo
                 A.ntiles, A.ticket);
     if constexpr (W <= kOnePassMaxW)
         FILT_LAUNCH(FILT_BNAME("batched_onepass_fwd", W), kb_onepass_fwd<W>,
-                    dim3(onepass_grid(A.ntiles)), dim3(64), 0, st, A, x, a, yi, y);
+                    dim3(onepass_grid(A.ntiles, A.nlists)), dim3(64), 0, st, A, x, a, yi, y);
     else
         FILT_LAUNCH(FILT_BNAME("batched_onepass_fwd", W), kb_onepass16_fwd,
-                    dim3(onepass_grid16(A.ntiles)), dim3(OnePass16::kThreads), 0, st, A, x, a, yi,
+                    dim3(onepass_grid16(A.ntiles, A.nlists)), dim3(OnePass16::kThreads), 0, st, A, x, a, yi,
                     y);
     return check_launch("batched single-pass forward");
 }
@@ -439,10 +466,10 @@ filt_status onepass_backward(const filt_plan *p, int b, const float *gy, const f
                 A.ntiles, A.ticket);
     if constexpr (W <= kOnePassMaxW)
         FILT_LAUNCH(FILT_BNAME("batched_onepass_bwd", W), kb_onepass_bwd<W>,
-                    dim3(onepass_grid(A.ntiles)), dim3(64), 0, st, A, gy, a, y, yi, gx, ga, gyi);
+                    dim3(onepass_grid(A.ntiles, A.nlists)), dim3(64), 0, st, A, gy, a, y, yi, gx, ga, gyi);
     else
         FILT_LAUNCH(FILT_BNAME("batched_onepass_bwd", W), kb_onepass16_bwd,
-                    dim3(onepass_grid16(A.ntiles)), dim3(OnePass16::kThreads), 0, st, A, gy, a, y,
+                    dim3(onepass_grid16(A.ntiles, A.nlists)), dim3(OnePass16::kThreads), 0, st, A, gy, a, y,
                     yi, gx, ga, gyi);
     return check_launch("batched single-pass backward");
 }

@@ -20,12 +20,17 @@
 //   5. every lane reruns its sub-chunk from its exact entering state out of
 //      LDS and the tile's outputs leave through LDS with coalesced stores.
 //
-// Tiles take their order from an atomic ticket counter over a list in which
-// every tile comes after the tiles it waits for, so a wavefront only ever
-// waits for wavefronts that hold a smaller ticket and are therefore running
-// or done.  Every wait is bounded: past kSpinLimit polls it counts a timeout
-// and goes on with a zero state, so the kernel always ends (the result is
-// then wrong and the counter says so).
+// Tiles take their order from atomic ticket counters, each over a list in
+// which every tile comes after the tiles it waits for, so a wavefront only
+// ever waits for wavefronts that hold a smaller ticket of the same list and
+// are therefore running or done.  The bucket's segments are split over
+// kOnePassLists such lists (whole segments, balanced by tile count; a
+// tile's predecessors are in its own list), workgroup g serving list
+// g mod kOnePassLists: one counter per list instead of one for the launch,
+// since every ticket is an atomic at the device's coherence point and a
+// single counter serialises them all.  Every wait is bounded: past
+// kSpinLimit polls it counts a timeout and goes on with a zero state, so the
+// kernel always ends (the result is then wrong and the counter says so).
 //
 // The backward is the same structure in reverse time on the adjoint
 // (transposed form, Sec. 3.1 Eq. 7), tiles waiting for their successors,
@@ -50,16 +55,20 @@ struct OnePass {
 
 constexpr int kOnePassMaxW = 4;
 constexpr int kSpinLimit = 1 << 22;
+constexpr int kOnePassLists = 8;   // ticket lists of a launch (orders up to 4)
+constexpr int kTicketStride = 32;  // ints between two lists' counters (128 bytes)
 
 struct OnePassArgs {
     const SegDesc *segs;
-    const int2 *tiles;  // (segment, tile) in ticket order
+    const int2 *tiles;  // (segment, tile): the lists one after another, each in ticket order
     int64_t ntiles;
     double *agg;        // per tile: aggregate map (REC doubles)
     double *inc;        // per tile: inclusive state (W doubles)
     int *flag;          // per tile: 0 none, 1 aggregate, 2 inclusive
-    int *ticket;        // ticket counter (zero at launch)
+    int *ticket;        // list q's counter at ticket[q * kTicketStride] (zero at launch)
     int *timeouts;      // bounded waits that ran out
+    int nlists;         // lists in use (1 .. kOnePassLists)
+    int64_t list_off[kOnePassLists + 1];  // list q: tiles[list_off[q] .. list_off[q + 1])
 };
 
 // Records shared between workgroups (flags, aggregates, inclusive states)
@@ -468,11 +477,14 @@ kb_onepass_fwd(OnePassArgs A, const float *__restrict__ x, const float *__restri
     __shared__ __align__(16) float cs[64 * G::CS];
     __shared__ double stage[G::kLook * G::REC];
     const int lane = threadIdx.x;
+    const int q = (int)(blockIdx.x % (unsigned)A.nlists);
+    int *const counter = A.ticket + q * kTicketStride;
+    const int64_t lo = A.list_off[q], ln = A.list_off[q + 1] - lo;
     for (;;) {
-        const int64_t tk = take_ticket(A.ticket, lane);
-        if (tk >= A.ntiles)
+        const int64_t tk = take_ticket(counter, lane);
+        if (tk >= ln)
             return;
-        const int2 it = A.tiles[tk];
+        const int2 it = A.tiles[lo + tk];
         const SegDesc sd = A.segs[it.x];
         const int64_t k = it.y;
         const int64_t t0 = k * G::S;
@@ -587,11 +599,14 @@ kb_onepass_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__restr
     __shared__ __align__(16) float cs[64 * G::CS];
     __shared__ double stage[G::kLook * G::REC];
     const int lane = threadIdx.x;
+    const int q = (int)(blockIdx.x % (unsigned)A.nlists);
+    int *const counter = A.ticket + q * kTicketStride;
+    const int64_t lo = A.list_off[q], ln = A.list_off[q + 1] - lo;
     for (;;) {
-        const int64_t tk = take_ticket(A.ticket, lane);
-        if (tk >= A.ntiles)
+        const int64_t tk = take_ticket(counter, lane);
+        if (tk >= ln)
             return;
-        const int2 it = A.tiles[tk];
+        const int2 it = A.tiles[lo + tk];
         const SegDesc sd = A.segs[it.x];
         const int64_t k = it.y;
         const int64_t t0 = k * G::S;
@@ -751,15 +766,15 @@ kb_onepass_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__restr
     }
 }
 
-// Clears a bucket's flags and its ticket counter (a kernel, not a memset,
-// so captured graphs replay it faithfully).
+// Clears a bucket's flags and its lists' ticket counters (a kernel, not a
+// memset, so captured graphs replay it faithfully).
 __global__ void __launch_bounds__(256) kb_onepass_reset(int *flag, int64_t n, int *ticket)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         flag[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        *ticket = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kOnePassLists)
+        ticket[threadIdx.x * kTicketStride] = 0;
 }
 
 }  // namespace filt_detail

@@ -31,7 +31,7 @@
 
 namespace filt_detail {
 
-constexpr int kTicketRun16 = 1;  // tickets per atomic (see kTicketRun)
+constexpr int kTicketRun16 = 1;  // tickets per atomic (tickets held ahead delay the tiles waiting on them)
 
 struct OnePass16 {
     static constexpr int P = 16;            // sub-chunks (DPP rows) per tile
@@ -251,19 +251,22 @@ kb_onepass16_fwd(OnePassArgs A, const float *__restrict__ x, const float *__rest
     __shared__ int tk;
     const int t = threadIdx.x;
     const int row = t >> 4, j = t & 15;
+    const int q = (int)(blockIdx.x % (unsigned)A.nlists);
+    int *const counter = A.ticket + q * kTicketStride;
+    const int64_t lo = A.list_off[q], ln = A.list_off[q + 1] - lo;
     int64_t tkt = 0, run_end = 0;
     for (;;) {
         if (tkt == run_end) {
             if (t == 0)
-                tk = atomicAdd(A.ticket, kTicketRun16);
+                tk = atomicAdd(counter, kTicketRun16);
             __syncthreads();
             tkt = tk;
             run_end = tkt + kTicketRun16;
             __syncthreads();
         }
-        if (tkt >= A.ntiles)
+        if (tkt >= ln)
             return;
-        const int2 it = A.tiles[tkt++];
+        const int2 it = A.tiles[lo + tkt++];
         const SegDesc sd = A.segs[it.x];
         const int64_t k = it.y;
         const int64_t t0 = k * G::S;
@@ -408,19 +411,22 @@ kb_onepass16_bwd(OnePassArgs A, const float *__restrict__ gy, const float *__res
     __shared__ int tk;
     const int t = threadIdx.x;
     const int row = t >> 4, j = t & 15;
+    const int q = (int)(blockIdx.x % (unsigned)A.nlists);
+    int *const counter = A.ticket + q * kTicketStride;
+    const int64_t lo = A.list_off[q], ln = A.list_off[q + 1] - lo;
     int64_t tkt = 0, run_end = 0;
     for (;;) {
         if (tkt == run_end) {
             if (t == 0)
-                tk = atomicAdd(A.ticket, kTicketRun16);
+                tk = atomicAdd(counter, kTicketRun16);
             __syncthreads();
             tkt = tk;
             run_end = tkt + kTicketRun16;
             __syncthreads();
         }
-        if (tkt >= A.ntiles)
+        if (tkt >= ln)
             return;
-        const int2 it = A.tiles[tkt++];
+        const int2 it = A.tiles[lo + tkt++];
         const SegDesc sd = A.segs[it.x];
         const int64_t k = it.y;
         const int64_t t0 = k * G::S;
