@@ -88,6 +88,40 @@ def test_batched_short_empty_and_passthrough_segments(gpu_device):
         _check_segments(s, y, g, TIGHT, which=[0, 2, 3, 4, 5])
 
 
+def _segments_of_orders(T, N, seed):
+    """A packed problem with the given lengths and orders (per-sample rows
+    from bandwidth-expanded reflection coefficients held over 16 samples)."""
+    T = np.asarray(T, dtype=np.int64)
+    N = np.asarray(N, dtype=np.int32)
+    rng = np.random.default_rng(seed)
+    x_off = np.concatenate([[0], np.cumsum(T)[:-1]]).astype(np.int64)
+    a_len = (T * N + 3) // 4 * 4
+    a_off = np.concatenate([[0], np.cumsum(a_len)[:-1]]).astype(np.int64)
+    ic_off = np.concatenate([[0], np.cumsum(N)[:-1]]).astype(np.int64)
+    a = np.zeros(int(a_len.sum()), np.float32)
+    for i in range(len(T)):
+        t, n = int(T[i]), int(N[i])
+        if t and n:
+            k = rng.uniform(-0.9, 0.9, (-(-t // 16), n))
+            frames = W.bandwidth_expand(W.reflection_to_direct(k), 0.95)
+            a[a_off[i]:a_off[i] + t * n] = W.frame_held(frames, t, 16, 0).reshape(-1)
+    return W.Segments(T, N, x_off, a_off, ic_off,
+                      rng.standard_normal(int(T.sum())).astype(np.float32), a,
+                      rng.normal(0, 0.1, int(N.sum())).astype(np.float32),
+                      rng.standard_normal(int(T.sum())).astype(np.float32))
+
+
+@pytest.mark.parametrize("chunks", [[32, 32, 32, 64, 128], [-1, -1, -1, 256, 512]])
+def test_batched_every_order_of_the_upper_buckets(gpu_device, chunks):
+    # orders 5..16 (the order 5..8 and 9..16 buckets' row summaries, the
+    # lanes past N zeroed), ragged lengths with a partial last chunk
+    N = [5, 6, 7, 8, 9, 11, 13, 15, 16, 3]
+    T = [3001, 2049, 1537, 4100, 2222, 1999, 3333, 1025, 2600, 1800]
+    s = _segments_of_orders(T, N, seed=21)
+    _, _, y, g = _run_plan(s, gpu_device, chunks=chunks)
+    _check_segments(s, y, g, TIGHT)
+
+
 def test_batched_equals_dense_per_filter_calls(gpu_device):
     s = W.config5(nseg=10, Tmin=2000, Tmax=9000, seed=11)
     plan, (x, a, yi, gy), y, g = _run_plan(s, gpu_device)
