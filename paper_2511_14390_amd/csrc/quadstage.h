@@ -24,14 +24,18 @@ namespace filt_detail {
 
 constexpr int kQuadRun = 8;        // steps per staged run
 constexpr int kQuadChains = 16;    // chains (quads) per wavefront
-constexpr int kQuadYWin = 24;      // y samples staged per run for ga (run + 16 back, rounded)
+constexpr int kQuadYFirst = 24;    // y samples staged before the first (last in time) run
+constexpr int kQuadYRing = 32;     // y ring per chain (a power of two >= 24 + run)
 
 struct QuadStageLds {
     float coef[kQuadChains][kQuadRun * 16 + 4];  // the run's rows (padded)
     float sig[kQuadChains][kQuadRun + 1];
     float out[kQuadChains][kQuadRun + 1];
-    // adjoint with ga: y at chunk-relative times [lo - 17, lo + 7) of the run
-    float yw[kQuadChains][kQuadYWin + 1];
+    // adjoint with ga: y of chunk-relative time tt in slot tt mod 32; while
+    // run lo is computed it holds [lo - 17, lo + 7) (the run's window, the
+    // last sample of which enters at its first step), and the samples
+    // [lo - 25, lo - 17) of the next run's window wait in registers
+    float yw[kQuadChains][kQuadYRing + 1];
     // per chain: element offsets of the chunk's first row / sample, valid
     // steps, and the frame bookkeeping (lfm == 0: per-sample rows)
     int64_t ocoef[kQuadChains], osig[kQuadChains], ln[kQuadChains];
@@ -44,7 +48,7 @@ struct QuadStageLds {
 struct QuadStageRegs {
     float4 c[kQuadRun * kQuadChains * 4 / 64];  // 8 float4 pieces per lane
     float s[kQuadRun * kQuadChains / 64];       // 2 samples per lane
-    float y[kQuadYWin * kQuadChains / 64];      // 6 y samples per lane (ga only)
+    float y[kQuadYFirst * kQuadChains / 64];    // up to 6 y samples per lane (ga only)
     uint32_t okc, oks;
 };
 
@@ -126,19 +130,21 @@ __device__ __forceinline__ void qs_commit(QuadStageLds &L, const QuadStageRegs &
     }
 }
 
-// ga only: y at chunk-relative times lo - 17 + j, j < kQuadYWin, of every
-// chain (sample g -> chain g / 24, j = g % 24): before time 0 from the
-// initial conditions (zero past 16 or without them), clamped below T.
+// ga only: y at chunk-relative times t0 + e, e < NY (NY * 16 / 64 samples a
+// lane: sample g -> chain g / NY, e = g % NY), into the chains' rings:
+// before time 0 from the initial conditions (zero past 16 or without them),
+// clamped below T.
+template <int NY>
 __device__ __forceinline__ void qs_load_y(const QuadStageLds &L, const float *__restrict__ y,
-                                          const float *__restrict__ yi, int64_t lo,
+                                          const float *__restrict__ yi, int64_t t0,
                                           QuadStageRegs &r)
 {
     const int l = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < kQuadYWin * kQuadChains / 64; ++j) {
+    for (int j = 0; j < NY * kQuadChains / 64; ++j) {
         const int g = l + 64 * j;
-        const int i = g / kQuadYWin, e = g % kQuadYWin;
-        const int64_t tt = lo - 17 + e;          // chunk-relative
+        const int i = g / NY, e = g % NY;
+        const int64_t tt = t0 + e;                  // chunk-relative
         const int64_t ta = (int64_t)L.lt0[i] + tt;  // absolute in the segment
         float v = 0.f;
         if (ta >= 0) {
@@ -150,13 +156,15 @@ __device__ __forceinline__ void qs_load_y(const QuadStageLds &L, const float *__
     }
 }
 
-__device__ __forceinline__ void qs_commit_y(QuadStageLds &L, const QuadStageRegs &r)
+template <int NY>
+__device__ __forceinline__ void qs_commit_y(QuadStageLds &L, const QuadStageRegs &r, int64_t t0)
 {
     const int l = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < kQuadYWin * kQuadChains / 64; ++j) {
+    for (int j = 0; j < NY * kQuadChains / 64; ++j) {
         const int g = l + 64 * j;
-        L.yw[g / kQuadYWin][g % kQuadYWin] = r.y[j];
+        const int i = g / NY, e = g % NY;
+        L.yw[i][(int)(t0 + e) & (kQuadYRing - 1)] = r.y[j];
     }
 }
 
@@ -302,26 +310,28 @@ kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restric
     }
     qs_sync();
     QuadStageRegs r;
+    constexpr int kRing = kQuadYRing - 1;
     qs_load(L, a, gy, Lc - kQuadRun, r);
     if constexpr (GA)
-        qs_load_y(L, y, yi, Lc - kQuadRun, r);
+        qs_load_y<kQuadYFirst>(L, y, yi, Lc - kQuadRun - 17, r);
     qs_commit(L, r);
     if constexpr (GA)
-        qs_commit_y(L, r);
+        qs_commit_y<kQuadYFirst>(L, r, Lc - kQuadRun - 17);
     qs_sync();
-    // wy[i] = y[t - 4q - 1 - i] for the chunk's last step t = Lc - 1: window
-    // index (Lc - 1 - 4q - 1 - i) - (Lc - kQuadRun - 17)
+    // wy[i] = y[t - 4q - 1 - i] for the chunk's last step t = Lc - 1
     float wy[4];
     if constexpr (GA) {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            wy[i] = L.yw[k][kQuadRun + 15 - 4 * q - i];
+            wy[i] = L.yw[k][(int)(Lc - 2 - 4 * q - i) & kRing];
     }
     for (int64_t lo = Lc - kQuadRun; lo >= 0; lo -= kQuadRun) {
+        // the next run's rows and gy, and the y it adds to the ring
+        // ([lo - 25, lo - 17): the rest of its window is already there)
         if (lo > 0) {
             qs_load(L, a, gy, lo - kQuadRun, r);
             if constexpr (GA)
-                qs_load_y(L, y, yi, lo - kQuadRun, r);
+                qs_load_y<kQuadRun>(L, y, yi, lo - kQuadRun - 17, r);
         }
 #pragma unroll
         for (int s = kQuadRun - 1; s >= 0; --s) {
@@ -336,8 +346,8 @@ kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restric
                 wy[0] = wy[1];
                 wy[1] = wy[2];
                 wy[2] = wy[3];
-                // y[t - 4q - 5] enters: window index s - 4q + 12
-                wy[3] = L.yw[k][s - 4 * q + 12];
+                // y[t - 4q - 5] enters
+                wy[3] = L.yw[k][(int)(lo + s - 4 * q - 5) & kRing];
             }
             const double nx = quad_dpp<kQuadFromNext>(st[0]);
             st[0] = __builtin_fma(-(double)c4.x, yb, st[1]);
@@ -352,7 +362,7 @@ kb_bwd_apply_quad_staged(const SegDesc *__restrict__ segs, const Item *__restric
         if (lo > 0) {
             qs_commit(L, r);
             if constexpr (GA)
-                qs_commit_y(L, r);
+                qs_commit_y<kQuadRun>(L, r, lo - kQuadRun - 17);
         }
         qs_sync();
     }
