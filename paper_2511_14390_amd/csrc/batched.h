@@ -376,6 +376,29 @@ inline void persistent_grid(int64_t n, unsigned &blocks, unsigned &threads)
     blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, cap));
 }
 
+// acc + v * (lane s's xrow of the row), the broadcast folded into the FMA
+// (row_newbcast); FIRST: xrow was written by the step's own block, so the
+// two wait states a DPP read needs after a VALU write come first.
+template <int s, bool FIRST>
+__device__ __forceinline__ double row_bcast_fma(double acc, double xrow, double v)
+{
+#define FILT_XB_ASM(n) "v_fmac_f64_dpp %0, %1, %2 row_newbcast:" #n " row_mask:0xf bank_mask:0xf"
+#define FILT_XB_CASE(n)                                                                            \
+    if constexpr (s == n) {                                                                        \
+        if constexpr (FIRST)                                                                       \
+            asm("s_nop 1\n" FILT_XB_ASM(n) : "+v"(acc) : "v"(xrow), "v"(v));                      \
+        else                                                                                       \
+            asm(FILT_XB_ASM(n) : "+v"(acc) : "v"(xrow), "v"(v));                                   \
+    }
+    FILT_XB_CASE(0) FILT_XB_CASE(1) FILT_XB_CASE(2) FILT_XB_CASE(3) FILT_XB_CASE(4)
+    FILT_XB_CASE(5) FILT_XB_CASE(6) FILT_XB_CASE(7) FILT_XB_CASE(8) FILT_XB_CASE(9)
+    FILT_XB_CASE(10) FILT_XB_CASE(11) FILT_XB_CASE(12) FILT_XB_CASE(13) FILT_XB_CASE(14)
+    FILT_XB_CASE(15)
+#undef FILT_XB_CASE
+#undef FILT_XB_ASM
+    return acc;
+}
+
 // Order-16 bucket summaries by duality, one 16-lane DPP row per chunk and
 // no driven solve (sixteen chunks per 256-thread workgroup, no LDS, no
 // barriers).  Forward: row lane i runs the adjoint solve seeded with
@@ -384,7 +407,9 @@ inline void persistent_grid(int64_t n, unsigned &blocks, unsigned &threads)
 // Phi_c, and sum_t ybar_i[t] x[t] is s_c[i].  Adjoint: row lane j runs the
 // forward solve from the unit state e_j; its final state is row j of the
 // chunk's adjoint map (Phi_c transposed) and sum_t gy[t] y_j[t] is that
-// map's driven part.  Coefficients and the signal are read 16 steps ahead.
+// map's driven part.  Coefficients are read 16 steps ahead; the signal one
+// 16-step block ahead, lane j holding step j of the block, its value
+// broadcast to the row inside the accumulating FMA.
 template <bool FULL>
 __global__ void __launch_bounds__(256)
 kb_fwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ items, int64_t n,
@@ -407,23 +432,24 @@ kb_fwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ i
 #pragma unroll
         for (int e = 0; e < 16; ++e)
             ss[e] = (rc.live && e == ((j + 2) & 15)) ? 1.0 : 0.0;
-        float cb[16], xb[16];
+        float cb[16];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
+        for (int s = 0; s < 16; ++s)
             cb[s] = *rc.at(L - 16 + s);
-            xb[s] = xp[L - 16 + s];
-        }
+        // lane j holds x of step rel + j of the block; step s reads lane s's
+        float xn = xp[L - 16 + j];
         double acc = 0.0;
         for (int rel = L - 16; rel >= 0; rel -= 16) {
+            const double xrow = (double)xn;
+            xn = xp[max(rel - 16, 0) + j];
             static_for<16>([&](auto I) {
                 constexpr int s = 15 - decltype(I)::value;
                 const double cf = rc.cvt(cb[s]);
-                const double xv = (double)xb[s];
                 const int nx = max(rel - 16 + s, 0);
                 cb[s] = *rc.at(nx);
-                xb[s] = xp[nx];
-                acc = __builtin_fma(ss[(1 - s) & 15], xv, acc);
+                const double sv = ss[(1 - s) & 15];
                 row_bwd_step<s>(cf, ss);
+                acc = row_bcast_fma<s, s == 15>(acc, xrow, sv);
                 __builtin_amdgcn_sched_barrier(0);
             });
         }
@@ -464,25 +490,25 @@ kb_bwd_summary_dual(const SegDesc *__restrict__ segs, const Item *__restrict__ i
 #pragma unroll
         for (int e = 0; e < 16; ++e)
             h[e] = (rc.live && e == ((-1 - j) & 15)) ? 1.0 : 0.0;
-        float cb[16], gb[16];
+        float cb[16];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int r = min(s, valid - 1);
-            cb[s] = *rc.at(r);
-            gb[s] = gp[r];
-        }
+        for (int s = 0; s < 16; ++s)
+            cb[s] = *rc.at(min(s, valid - 1));
+        // lane j holds gy of step rel + j of the block (zero past the
+        // signal's end); step s reads lane s's
+        float gn = gp[min(j, valid - 1)];
         double acc = 0.0;
         for (int rel = 0; rel < L; rel += 16) {
+            const double grow = rel + j < valid ? (double)gn : 0.0;
+            gn = gp[min(rel + 16 + j, valid - 1)];
             static_for<16>([&](auto I) {
                 constexpr int s = decltype(I)::value;
                 const bool in = rel + s < valid;
                 const double cf = in ? rc.cvt(cb[s]) : 0.0;
-                const double gv = in ? (double)gb[s] : 0.0;
                 const int nx = min(rel + 16 + s, valid - 1);
                 cb[s] = *rc.at(nx);
-                gb[s] = gp[nx];
                 h[s] = row_fwd_step<s>(cf, h);
-                acc = __builtin_fma(gv, h[s], acc);
+                acc = row_bcast_fma<s, s == 0>(acc, grow, h[s]);
                 __builtin_amdgcn_sched_barrier(0);
             });
         }
