@@ -419,6 +419,38 @@ def batched_main(args):
                         "frac": round(ach / HBM_PEAK_GBS, 4),
                         "traffic": counted_traffic(workload, "packed", chunks[4], dom),
                         "bytes_per_launch": per_launch, "avg_launch_us": round(avg_us, 2)}
+            # the launch time above is a wall time while the other buckets'
+            # streams share the GPU; the same kernel with its bucket alone (a
+            # plan over that bucket's segments, same chunk lengths, eager
+            # steps, events around its launches) for context
+            Wd = int(dom.rpartition("_w")[2])
+            Wb = np.maximum(1, 2 ** np.ceil(np.log2(np.maximum(s.N, 1)))).astype(np.int64)
+            sel = np.nonzero(Wb == Wd)[0]
+            solo = F.BatchedFilter(s.T[sel], s.N[sel], s.x_off[sel], s.a_off[sel],
+                                   s.ic_off[sel], chunks=chunks, hop=hop)
+
+            def solo_step():
+                solo.forward(x, a, yi, out=y)
+                solo.backward(gy, y, a, yi, out={"x": gx, "a": ga, "yi": gyi})
+
+            solo_step()
+            torch.cuda.synchronize()
+            F.profile_only(dom)
+            F.profile_enable(True)
+            for _ in range(args.steps):
+                solo_step()
+            torch.cuda.synchronize()
+            F.profile_enable(False)
+            alone = F.profile_read()
+            F.profile_only(None)
+            solo.close()
+            if dom in alone:
+                c1, ms1 = alone[dom]
+                us1 = 1e3 * ms1 / c1
+                roofline["alone"] = {"avg_launch_us": round(us1, 2),
+                                     "achieved": round(per_launch / (us1 * 1e-6) / 1e9, 1),
+                                     "frac": round(per_launch / (us1 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                                     "what": "the kernel's bucket alone on the GPU"}
 
     # plain: one dense forward + backward call per filter, eager and captured
     segs = [(int(s.T[i]), int(s.N[i]), int(s.x_off[i]), int(s.a_off[i]), int(s.ic_off[i]),
