@@ -7,8 +7,8 @@
 // separate 64-byte pieces, and the same quad apply on channel-interleaved
 // data (where a wavefront's rows of one step are one 1 KB block) moves twice
 // the bytes per microsecond.  Here the wavefront loads the next run of
-// kQuadRun steps of all 16 chains together -- half a wavefront reads one
-// chain's run of rows, 512 contiguous bytes -- parks it in LDS, and each
+// kQuadRun steps of all 16 chains together -- a wavefront reads one chain's
+// run of rows, 1 KB contiguous -- parks it in LDS, and each
 // quad then reads its taps from LDS; outputs are gathered in LDS and stored
 // as contiguous runs.  The run after the one being computed is in flight in
 // registers meanwhile.  Same arithmetic as fwd_apply_quad / bwd_apply_quad
@@ -22,19 +22,24 @@
 
 namespace filt_detail {
 
-constexpr int kQuadRun = 8;        // steps per staged run
+constexpr int kQuadRun = 16;       // steps per staged run
 constexpr int kQuadChains = 16;    // chains (quads) per wavefront
-constexpr int kQuadYFirst = 24;    // y samples staged before the first (last in time) run
-constexpr int kQuadYRing = 32;     // y ring per chain (a power of two >= 24 + run)
+constexpr int kQuadYFirst = kQuadRun + 16;  // y samples staged before the first (last in time) run
+constexpr int kQuadYRing = 32;     // y ring per chain (a power of two >= run + 16)
+static_assert(kQuadRun % 4 == 0 && kQuadRun <= 16 && kQuadRun + 16 <= kQuadYRing,
+              "run length: whole float4 signal pieces, one ring");
+constexpr int kQuadCPieces = kQuadRun * kQuadChains * 4 / 64;  // row float4 pieces per lane
+constexpr int kQuadSPieces = kQuadRun * kQuadChains / 64;      // signal samples per lane
 
 struct QuadStageLds {
     float coef[kQuadChains][kQuadRun * 16 + 4];  // the run's rows (padded)
     float sig[kQuadChains][kQuadRun + 1];
     float out[kQuadChains][kQuadRun + 1];
     // adjoint with ga: y of chunk-relative time tt in slot tt mod 32; while
-    // run lo is computed it holds [lo - 17, lo + 7) (the run's window, the
-    // last sample of which enters at its first step), and the samples
-    // [lo - 25, lo - 17) of the next run's window wait in registers
+    // run lo is computed it holds [lo - 17, lo + kQuadRun - 1) (the run's
+    // window, the first sample of which enters at its last step), and the
+    // samples [lo - kQuadRun - 17, lo - 17) of the next run's window wait in
+    // registers
     float yw[kQuadChains][kQuadYRing + 1];
     // per chain: element offsets of the chunk's first row / sample, valid
     // steps, and the frame bookkeeping (lfm == 0: per-sample rows)
@@ -46,9 +51,9 @@ struct QuadStageLds {
 };
 
 struct QuadStageRegs {
-    float4 c[kQuadRun * kQuadChains * 4 / 64];  // 8 float4 pieces per lane
-    float s[kQuadRun * kQuadChains / 64];       // 2 samples per lane
-    float y[kQuadYFirst * kQuadChains / 64];    // up to 6 y samples per lane (ga only)
+    float4 c[kQuadCPieces];
+    float s[kQuadSPieces];
+    float y[kQuadYFirst * kQuadChains / 64];    // ga only
     uint32_t okc, oks;
 };
 
@@ -79,9 +84,9 @@ __device__ __forceinline__ void qs_set_chain(QuadStageLds &L, int i, const SegDe
 }
 
 // Load run `lo` (chunk-local steps [lo, lo + kQuadRun)) of all chains:
-// g = lane + 64 j; coefficient piece g -> chain g / 32, step (g % 32) / 4,
-// quarter g % 4 (half a wavefront per chain run: contiguous per-sample rows);
-// sample g -> chain g / 8, step g % 8.  Steps outside [0, n) read the
+// g = lane + 64 j; coefficient piece g -> chain g / (4 kQuadRun), step
+// (g / 4) % kQuadRun, quarter g % 4 (contiguous per-sample rows); sample
+// g -> chain g / kQuadRun, step g % kQuadRun.  Steps outside [0, n) read the
 // chain's first or last row and are zeroed at commit.
 __device__ __forceinline__ void qs_load(const QuadStageLds &L, const float *__restrict__ coef,
                                         const float *__restrict__ sig, int64_t lo,
@@ -90,9 +95,9 @@ __device__ __forceinline__ void qs_load(const QuadStageLds &L, const float *__re
     const int l = threadIdx.x;
     r.okc = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kQuadCPieces; ++j) {
         const int g = l + 64 * j;
-        const int i = g >> 5, s = (g & 31) >> 2, qq = g & 3;
+        const int i = g / (4 * kQuadRun), s = (g / 4) % kQuadRun, qq = g & 3;
         const int64_t n = L.ln[i];
         const int64_t t = lo + s;
         const int64_t tc = t < 0 ? 0 : (t < n ? t : (n > 0 ? n - 1 : 0));
@@ -102,9 +107,9 @@ __device__ __forceinline__ void qs_load(const QuadStageLds &L, const float *__re
     }
     r.oks = 0;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < kQuadSPieces; ++j) {
         const int g = l + 64 * j;
-        const int i = g >> 3, s = g & 7;
+        const int i = g / kQuadRun, s = g % kQuadRun;
         const int64_t n = L.ln[i];
         const int64_t t = lo + s;
         const int64_t tc = t < 0 ? 0 : (t < n ? t : (n > 0 ? n - 1 : 0));
@@ -117,16 +122,16 @@ __device__ __forceinline__ void qs_commit(QuadStageLds &L, const QuadStageRegs &
 {
     const int l = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kQuadCPieces; ++j) {
         const int g = l + 64 * j;
-        const int i = g >> 5, s = (g & 31) >> 2, qq = g & 3;
+        const int i = g / (4 * kQuadRun), s = (g / 4) % kQuadRun, qq = g & 3;
         *reinterpret_cast<float4 *>(&L.coef[i][s * 16 + 4 * qq]) =
             ((r.okc >> j) & 1u) ? r.c[j] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < kQuadSPieces; ++j) {
         const int g = l + 64 * j;
-        L.sig[g >> 3][g & 7] = ((r.oks >> j) & 1u) ? r.s[j] : 0.f;
+        L.sig[g / kQuadRun][g % kQuadRun] = ((r.oks >> j) & 1u) ? r.s[j] : 0.f;
     }
 }
 
@@ -176,9 +181,9 @@ __device__ __forceinline__ void qs_flush_ga(const QuadStageLds &L, float *__rest
 {
     const int l = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < kQuadCPieces; ++j) {
         const int g = l + 64 * j;
-        const int i = g >> 5, s = (g & 31) >> 2, qq = g & 3;
+        const int i = g / (4 * kQuadRun), s = (g / 4) % kQuadRun, qq = g & 3;
         if (L.lfm[i] == 0 && lo + s < L.ln[i]) {
             using f4 = float __attribute__((ext_vector_type(4)));
             const float4 v = *reinterpret_cast<const float4 *>(&L.coef[i][s * 16 + 4 * qq]);
@@ -195,9 +200,9 @@ __device__ __forceinline__ void qs_flush(const QuadStageLds &L, float *__restric
 {
     const int l = threadIdx.x;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < kQuadSPieces; ++j) {
         const int g = l + 64 * j;
-        const int i = g >> 3, s = g & 7;
+        const int i = g / kQuadRun, s = g % kQuadRun;
         if (lo + s < L.ln[i])
             out[L.osig[i] + lo + s] = L.out[i][s];
     }
